@@ -1,0 +1,231 @@
+"""Seeded synthetic inputs: model hyper-parameters, molecules, weights, targets.
+
+This module is the only thing the GPU library's tests and the oracle share.
+It holds no arithmetic of the method itself (no symmetry function, network or
+derivative): only the numbers a user would hand to the library — the
+ANI-2x-shaped hyper-parameters, random molecules of the sizes the paper
+simulates, Xavier-initialised weights — drawn from fixed seeds.
+
+Workloads (the paper's ligands are 48-75 atoms over H,C,N,O,F,S,Cl, Results,
+Table 1; its timings are single-ligand energy+force calls, Table 2):
+
+  cfg 1  one 24-atom molecule, H12 C8 N2 O2, 6 A cube, one model, FP64
+  cfg 2  one 64-atom ligand, 30:20:5:5:2:1:1 over H..Cl, 9 A cube, 8 models, FP32
+  cfg 3  512 molecules of U{10..120} atoms, ratio-sampled elements,
+         cube edge N^(1/3) * 2.2 A, 8 models, FP32
+  cfg 4  64 molecules of U{30..80} atoms with seeded target energies/forces
+  cfg 5  1024 Gaussian (sigma 0.05 A) replicas of one 48-atom ligand
+         (22:15:4:4:1:1:1), 8 models, BF16 MLP
+
+Geometry: sequential rejection sampling, a uniform candidate in the cube is
+accepted when it is at least 1.0 A from every accepted atom; element labels are
+exact counts (shuffled) where given, else drawn from the ratio.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+#: base seed of every workload; cfg k draws from SeedSequence(BASE_SEED + k)
+BASE_SEED = 220108110
+#: seed of the model weights, shared by every workload (model 0 of the
+#: ensemble is the single model of cfg 1)
+W_SEED = 220108110
+
+#: atomic numbers of the element table, index order = species index
+ELEMENTS = (1, 6, 7, 8, 9, 16, 17)
+ELEMENT_NAMES = ("H", "C", "N", "O", "F", "S", "Cl")
+#: element ratio of a drug-like ligand over H,C,N,O,F,S,Cl
+LIGAND_RATIO = (30, 20, 5, 5, 2, 1, 1)
+
+#: Hartree -> kcal/mol
+HARTREE_TO_KCALMOL = 627.5094740631
+
+
+def ani2x_hparams() -> dict:
+    """ANI-2x-shaped featuriser and network hyper-parameters.
+
+    Shift grids are half-open: 16 radial shifts from 0.8 A in steps of
+    (5.1-0.8)/16, 8 angular-distance shifts from 0.8 A in steps of (3.5-0.8)/8,
+    4 angle shifts at the bin midpoints (2z+1) pi / 8 of (0, pi).
+    """
+    return dict(
+        n_species=7,
+        rcr=5.1, rca=3.5,
+        eta_r=19.7, eta_a=12.5, zeta=14.1,
+        shf_r=[0.8 + k * (5.1 - 0.8) / 16.0 for k in range(16)],
+        shf_a=[0.8 + a * (3.5 - 0.8) / 8.0 for a in range(8)],
+        shf_z=[(2 * z + 1) * math.pi / 8.0 for z in range(4)],
+        angle_scale=0.95,
+        radial_pref=0.25,
+        widths=[1008, 256, 192, 160, 1],
+        celu_alpha=0.1,
+        energy_scale=HARTREE_TO_KCALMOL,
+    )
+
+
+def aev_dim(hp: dict) -> int:
+    s = hp["n_species"]
+    return s * len(hp["shf_r"]) + (s * (s + 1) // 2) * len(hp["shf_a"]) * len(hp["shf_z"])
+
+
+def net_size(widths) -> int:
+    return sum(widths[l + 1] * widths[l] + widths[l + 1] for l in range(len(widths) - 1))
+
+
+# --------------------------------------------------------------------------
+# geometry
+
+
+def random_molecule(rng: np.random.Generator, counts, box: float, min_dist: float = 1.0):
+    """Rejection-sampled coordinates (Angstrom) and shuffled species indices."""
+    counts = list(counts)
+    n = int(sum(counts))
+    species = np.repeat(np.arange(len(counts), dtype=np.int32), counts)
+    rng.shuffle(species)
+    pos = np.empty((n, 3), dtype=np.float64)
+    k = 0
+    tries = 0
+    while k < n:
+        c = rng.uniform(0.0, box, size=3)
+        tries += 1
+        if tries > 200000 * max(n, 1):
+            raise RuntimeError("rejection sampling did not converge")
+        if k == 0 or np.min(np.sum((pos[:k] - c) ** 2, axis=1)) >= min_dist * min_dist:
+            pos[k] = c
+            k += 1
+    return pos, species
+
+
+def ratio_counts(rng: np.random.Generator, n: int, ratio=LIGAND_RATIO):
+    p = np.asarray(ratio, dtype=np.float64)
+    p /= p.sum()
+    lab = rng.choice(len(ratio), size=n, p=p)
+    return np.bincount(lab, minlength=len(ratio))
+
+
+def rounded_counts(n: int, ratio):
+    """Largest-remainder rounding of n * ratio to integers summing to n."""
+    r = np.asarray(ratio, dtype=np.float64)
+    q = n * r / r.sum()
+    base = np.floor(q).astype(int)
+    rem = n - base.sum()
+    order = np.argsort(-(q - base), kind="stable")
+    base[order[:rem]] += 1
+    return base
+
+
+# --------------------------------------------------------------------------
+# weights
+
+
+def xavier_weights(n_models: int, widths, n_species: int = 7, seed: int = W_SEED):
+    """FP64 master weights, packed [model][species][layer]{W (out x in), b (out)}.
+
+    W ~ U(+-sqrt(6/(fan_in+fan_out))), b ~ U(+-1/sqrt(fan_in)); model m draws
+    from SeedSequence(seed).spawn(m+1)[m] so that model m is the same for any
+    ensemble size.
+    """
+    children = np.random.SeedSequence(seed).spawn(max(n_models, 8))
+    chunks = []
+    for m in range(n_models):
+        rng = np.random.Generator(np.random.PCG64(children[m]))
+        for _s in range(n_species):
+            for l in range(len(widths) - 1):
+                fin, fout = widths[l], widths[l + 1]
+                bw = math.sqrt(6.0 / (fin + fout))
+                chunks.append(rng.uniform(-bw, bw, size=fout * fin))
+                bb = 1.0 / math.sqrt(fin)
+                chunks.append(rng.uniform(-bb, bb, size=fout))
+    return np.concatenate(chunks).astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# batches
+
+
+@dataclass
+class Batch:
+    name: str
+    coords: np.ndarray          # [A, 3] float64
+    species: np.ndarray         # [A] int32 species indices
+    mol_offsets: np.ndarray     # [B+1] int32
+    n_models: int
+    precision: str              # "fp64" | "fp32" | "bf16"
+    target_E: np.ndarray | None = None
+    target_F: np.ndarray | None = None
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.mol_offsets[-1])
+
+    @property
+    def n_mols(self) -> int:
+        return len(self.mol_offsets) - 1
+
+
+def _streams(cfg: int):
+    ss = np.random.SeedSequence(BASE_SEED + cfg).spawn(4)
+    return [np.random.Generator(np.random.PCG64(s)) for s in ss]   # geom, species, spare, targets
+
+
+def _pack(mols):
+    coords = np.concatenate([m[0] for m in mols]) if mols else np.zeros((0, 3))
+    species = np.concatenate([m[1] for m in mols]).astype(np.int32) if mols else np.zeros(0, np.int32)
+    off = np.zeros(len(mols) + 1, dtype=np.int32)
+    off[1:] = np.cumsum([len(m[1]) for m in mols])
+    return coords, species, off
+
+
+def config_batch(cfg: int, n_mols: int | None = None) -> Batch:
+    """The seeded batch of workload cfg (1..5); n_mols truncates cfg 3/4/5."""
+    g_geom, g_spec, _g_spare, g_tgt = _streams(cfg)
+    if cfg == 1:
+        pos, sp = random_molecule(g_geom, [12, 8, 2, 2], 6.0)
+        c, s, o = _pack([(pos, sp)])
+        return Batch("single 24-atom molecule", c, s, o, 1, "fp64")
+    if cfg == 2:
+        pos, sp = random_molecule(g_geom, [30, 20, 5, 5, 2, 1, 1], 9.0)
+        c, s, o = _pack([(pos, sp)])
+        return Batch("single 64-atom ligand", c, s, o, 8, "fp32")
+    if cfg in (3, 4):
+        nb = 512 if cfg == 3 else 64
+        lo, hi = (10, 120) if cfg == 3 else (30, 80)
+        nb = nb if n_mols is None else n_mols
+        mols = []
+        for _ in range(nb):
+            n = int(g_spec.integers(lo, hi + 1))
+            counts = ratio_counts(g_spec, n)
+            mols.append(random_molecule(g_geom, counts, n ** (1.0 / 3.0) * 2.2))
+        c, s, o = _pack(mols)
+        if cfg == 3:
+            return Batch(f"{nb} molecules of {lo}-{hi} atoms", c, s, o, 8, "fp32")
+        return Batch(f"{nb} molecules of {lo}-{hi} atoms, seeded targets", c, s, o, 8, "fp32",
+                     extra={"target_seed": int(g_tgt.integers(1 << 30))})
+    if cfg == 5:
+        nrep = 1024 if n_mols is None else n_mols
+        counts = rounded_counts(48, LIGAND_RATIO)
+        base, sp = random_molecule(g_geom, counts, 48 ** (1.0 / 3.0) * 2.2)
+        mols = [(base + g_geom.normal(0.0, 0.05, size=base.shape), sp) for _ in range(nrep)]
+        c, s, o = _pack(mols)
+        return Batch(f"{nrep} replicas of a 48-atom ligand", c, s, o, 8, "bf16")
+    raise ValueError(f"unknown workload {cfg}")
+
+
+def random_batch(seed: int, sizes, box_scale: float = 2.2, ratio=LIGAND_RATIO) -> Batch:
+    """Free-form seeded batch (tests): molecules of the given atom counts."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    mols = []
+    for n in sizes:
+        counts = ratio_counts(g, int(n), ratio)
+        mols.append(random_molecule(g, counts, max(int(n), 1) ** (1.0 / 3.0) * box_scale))
+    c, s, o = _pack(mols)
+    return Batch(f"random batch seed {seed}", c, s, o, 8, "fp32")
+
+
+def round_to_fp32(a: np.ndarray) -> np.ndarray:
+    """FP32-rounded values widened back to FP64 (what an FP32 path really sees)."""
+    return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
