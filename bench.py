@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of the NNP energy+force path on one MI355X.
+
+Headline (value): atom energy+force evaluations per second of the 8-model
+ensemble on 1024 Gaussian replicas of a 48-atom ligand, BF16 network GEMMs
+with FP32 accumulation, FP32 featuriser and forces (inputs resident in HBM).
+Beside it, in the same JSON line:
+  plain_fp32   the single 64-atom ligand in FP32, one call per evaluation
+               (the paper's own MD workload: one molecule, low latency)
+  roofline     the dominant kernel's algorithmic FLOP rate from HIP events
+               recorded around every launch inside the timed region
+  cpu_baseline the FP64 C oracle on a bounded sample of the same workload
+  accuracy     errors of the timed GPU results against that oracle sample
+
+A step = one full evaluation (neighbour lists, AEVs, element bucketing,
+ensemble networks forward and backward, force scatter, energy sums).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atom energy+force evals/s (8-model ensemble), batched BF16 vs plain FP32"
+
+# MI355X published peaks
+PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}
+
+
+def mlp_flops_per_atom(hp, M):
+    """Algorithmic FLOPs per atom of each network GEMM (unpadded widths)."""
+    w = hp["widths"]
+    return {
+        "mlp_l1_fwd": 2 * M * w[0] * w[1],
+        "mlp_l2_fwd": 2 * M * w[1] * w[2],
+        "mlp_l3_fwd": 2 * M * w[2] * w[3] + 2 * M * w[3],
+        "mlp_l3_bwd": 2 * M * w[3] * w[2],
+        "mlp_l2_bwd": 2 * M * w[2] * w[1],
+        "mlp_l1_bwd": 2 * M * w[1] * w[0],
+    }
+
+
+def run_form(torch, h, batch, steps, warmup, timing):
+    dev = torch.device("cuda:0")
+    x = torch.tensor(batch.coords, dtype=torch.float32, device=dev)
+    sp = torch.tensor(batch.species, dtype=torch.int32, device=dev)
+    off = torch.tensor(batch.mol_offsets, dtype=torch.int32, device=dev)
+    E = torch.empty(batch.n_mols, dtype=torch.float64, device=dev)
+    F = torch.empty_like(x)
+    for _ in range(warmup):
+        h.energy_forces(x, sp, off, out=(E, F))
+    torch.cuda.synchronize()
+    if h.device_status() != 0:
+        raise RuntimeError("device flagged an error during warmup")
+    h.set_timing(timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h.energy_forces(x, sp, off, out=(E, F))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = h.kernel_times() if timing else {}
+    h.set_timing(False)
+    return (t1 - t0) / steps, kt, E.cpu().numpy(), F.double().cpu().numpy()
+
+
+def cpu_baseline(hp, w, M, make_sample, budget_s=12.0):
+    """Oracle on bounded samples of the workload until ~budget_s of CPU work."""
+    import oracle
+    atoms, elapsed, first = 0, 0.0, None
+    b = make_sample()
+    while elapsed < budget_s:
+        t0 = time.perf_counter()
+        E, F = oracle.energy_forces(hp, w, M, b.species, b.coords, b.mol_offsets)
+        elapsed += time.perf_counter() - t0
+        atoms += b.n_atoms
+        if first is None:
+            first = (b, E, F)
+    return atoms / elapsed, atoms, elapsed, oracle.num_threads(), first
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--replicas", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 form")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(molecules shard across GPUs with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2201_08110_amd import nnp, synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    hp = synth.ani2x_hparams()
+    M = 8
+    w = synth.xavier_weights(M, hp["widths"])
+
+    # ---- headline: batched BF16-MLP replicas -----------------------------
+    b5 = synth.config_batch(5, n_mols=args.replicas)
+    h5 = nnp.NNP(hp, w, M, "bf16", max_atoms=b5.n_atoms, max_mols=b5.n_mols, max_atoms_per_mol=48)
+    sec, kt, E5, F5 = run_form(torch, h5, b5, args.steps, args.warmup, timing=True)
+    value = b5.n_atoms / sec
+
+    flops = mlp_flops_per_atom(hp, M)
+    per_kernel = {k: {"launches": c, "avg_us": 1e3 * ms / max(c, 1)} for k, (c, ms) in kt.items()}
+    gemms = {k: v for k, v in per_kernel.items() if k in flops}
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"]) if per_kernel else None
+    roof = None
+    if dom in flops:
+        achieved = flops[dom] * b5.n_atoms / (per_kernel[dom]["avg_us"] * 1e-6)
+        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12,
+                "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK["bf16"], "traffic": None,
+                "flops_per_launch": flops[dom] * b5.n_atoms}
+    mlp_total_us = sum(v["avg_us"] for v in gemms.values())
+    mlp_flops = sum(flops.values()) * b5.n_atoms
+    for k, v in per_kernel.items():
+        if k in flops:
+            v["tflops"] = flops[k] * b5.n_atoms / (v["avg_us"] * 1e-6) / 1e12
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "atom-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (seeded replicas, Xavier weights)",
+        "config": {"workload": f"{b5.n_mols} replicas x 48-atom ligand (H,C,N,O,F,S,Cl 22:15:4:4:1:1:1), "
+                               "sigma 0.05 A, 8-model ensemble, BF16 MLP / FP32 AEV+forces",
+                   "atoms_per_eval": int(b5.n_atoms), "precision": "bf16-mlp"},
+        "roofline": roof,
+        "kernels": per_kernel,
+        "mlp_gemm_tflops": mlp_flops / (mlp_total_us * 1e-6) / 1e12 if mlp_total_us else None,
+    }
+
+    # ---- plain FP32 single ligand ----------------------------------------
+    if not args.no_plain:
+        b2 = synth.config_batch(2)
+        h2 = nnp.NNP(hp, w, M, "fp32", max_atoms=b2.n_atoms, max_mols=1, max_atoms_per_mol=64)
+        sec2, kt2, E2, F2 = run_form(torch, h2, b2, max(args.steps, 200), args.warmup, timing=False)
+        out["plain_fp32"] = {"workload": "single 64-atom ligand, 8-model ensemble, FP32",
+                             "value": b2.n_atoms / sec2, "unit": "atom-evals/s",
+                             "us_per_eval": sec2 * 1e6}
+        h2.close()
+
+    # ---- CPU baseline + accuracy on the sample ---------------------------
+    if not args.no_cpu:
+        nsamp = 16
+
+        def sample():
+            return synth.config_batch(5, n_mols=nsamp)
+
+        rate, atoms, el, cores, first = cpu_baseline(hp, w, M, sample)
+        out["cpu_baseline"] = {"value": rate, "unit": "atom-evals/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"first {nsamp} replicas ({nsamp * 48} atoms) of the workload, "
+                                         f"repeated: {atoms} atom-evals in {el:.1f} s, FP64"}
+        b, Eo, Fo = first
+        # the timed GPU run holds the same first replicas (same seed stream)
+        n = b.n_atoms
+        dE = np.abs(E5[:nsamp] - Eo) / 48.0
+        rmse = np.sqrt(np.mean((F5[:n].reshape(nsamp, 48, 3) - Fo.reshape(nsamp, 48, 3)) ** 2,
+                               axis=(1, 2)))
+        out["accuracy"] = {"vs": "FP64 oracle, FP64 master weights", "replicas": nsamp,
+                           "dE_per_atom_max": float(dE.max()),
+                           "dE_per_atom_median": float(np.median(dE)),
+                           "force_rmse_max": float(rmse.max()),
+                           "force_rmse_median": float(np.median(rmse)),
+                           "force_rms": float(np.sqrt(np.mean(Fo ** 2)))}
+    h5.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * nnp.h -- C ABI of the MI355X (gfx950) neural-network-potential library.
+ *
+ * The library evaluates the NNP term of an NNP/MM simulation: the potential
+ * V_NNP(Z, r) of the atoms of the NNP region and the forces F = -grad_r V_NNP
+ * (Methods, Eq. 2 and Eq. 3), with positions and forces resident on the GPU
+ * (Methods, first optimisation: no CPU<->GPU copies per step).  V_NNP is an
+ * ANI-style model: per-atom symmetry-function features (AEVs, the modified
+ * Behler-Parrinello functions of ANI with cosine cutoffs, Introduction) fed to
+ * one atomic network per element, averaged over an ensemble of networks
+ * (Methods, third optimisation: ANI-2x uses 8).  The total charge of Eq. 2 is
+ * not an input: the ANI-2x family handles neutral molecules only
+ * (Introduction).  One call evaluates one molecule (the low-latency MD case,
+ * Methods) or a ragged batch of independent molecules or replicas.
+ *
+ * Conventions
+ *  - Lengths in Angstrom.  Energies in the units of energy_scale times the
+ *    network output (627.5094740631 turns Hartree into kcal/mol); forces in
+ *    those energy units per Angstrom.
+ *  - Coordinates are [n_atoms][3] row-major, forces likewise.
+ *  - "device" pointers are HIP device memory of the handle's device (hipMalloc
+ *    or torch CUDA tensors); "host" pointers are ordinary memory.
+ *  - Every call is asynchronous on the batch's stream unless stated: it returns
+ *    after enqueueing, outputs are valid once the stream reaches that point,
+ *    and inputs must stay valid until then.
+ *  - Errors: every entry point returns an nnp_status.  Invalid arguments are
+ *    detected on the host before anything is launched (nothing is written).
+ *    Conditions only the device can see (an element index out of range, a
+ *    molecule larger than the capacity, a neighbour list overflow) set a
+ *    device flag that nnp_get_device_status reads; results of that call are
+ *    then unspecified.  nnp_last_error() describes the last host-side error of
+ *    the calling thread.  No C++ exception crosses this interface.
+ *  - A handle may be used by one host thread and one stream at a time; any
+ *    number of handles may coexist.
+ */
+#ifndef NNP_H
+#define NNP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nnp_status;
+
+#define NNP_OK              0
+#define NNP_E_INVALID       1   /* null pointer, size out of range, bad hyper-parameter      */
+#define NNP_E_SPECIES       2   /* element index outside the table (device flag)              */
+#define NNP_E_CAPACITY      3   /* batch exceeds the capacity given at creation               */
+#define NNP_E_NOMEM         4   /* device allocation failed                                   */
+#define NNP_E_DEVICE        5   /* a HIP runtime call failed                                  */
+#define NNP_E_UNSUPPORTED   6   /* valid request this build does not implement                */
+
+/* Arithmetic of the path. */
+#define NNP_PREC_FP64       0   /* everything in FP64 (checking mode)                         */
+#define NNP_PREC_FP32       1   /* AEV, networks and forces in FP32; energies summed in FP64  */
+#define NNP_PREC_BF16_MLP   2   /* network GEMM operands BF16 with FP32 accumulation; AEV,
+                                   activations' epilogues and forces FP32                     */
+
+#define NNP_MAX_SPECIES     8
+
+typedef struct nnp_handle nnp_handle;
+
+/*
+ * Model description, read once by nnp_create (everything is deep-copied; the
+ * caller may free its buffers when nnp_create returns).
+ *
+ * Featuriser (the published ANI form; the paper names it in the Introduction):
+ *   fc(r)  = 0.5 cos(pi r / Rc) + 0.5 for r < Rc, else 0
+ *   radial   G_i[n_shf_r*s_j + k] += radial_pref exp(-eta_r (r_ij - shf_r[k])^2) fc(r_ij; rcr)
+ *   angular  for each unordered neighbour pair {j,k} of i within rca:
+ *            c = cos theta_jik, c' = angle_scale c,
+ *            cos(theta' - t_z) = c' cos t_z + sqrt(1 - c'^2) sin t_z, t_z = shf_z[z]
+ *            G_i[S*n_shf_r + n_shf_a*n_shf_z*p(s_j,s_k) + n_shf_z*a + z] +=
+ *              2 ((1 + cos(theta' - t_z))/2)^zeta
+ *                exp(-eta_a ((r_ij + r_ik)/2 - shf_a[a])^2) fc(r_ij; rca) fc(r_ik; rca)
+ *            p(b,c), b <= c: row-major index of the upper triangle of S x S.
+ *   AEV dimension D = S n_shf_r + S(S+1)/2 n_shf_a n_shf_z (1008 for ANI-2x).
+ * Networks: one per (model, element); hidden layers CELU(alpha) (z for z >= 0,
+ *   alpha (exp(z/alpha) - 1) otherwise), linear scalar output.  Energy of a
+ *   molecule: energy_scale * ( mean over models of the summed atomic outputs
+ *   + sum of sae[s_i] ).
+ *
+ * weights (host, FP64): [model][element][layer] { W (out x in, row-major), b (out) }.
+ * This build supports n_shf_r = 16, n_shf_a * n_shf_z = 32, n_layers = 4 with
+ * hidden widths that are multiples of 32 (E_UNSUPPORTED otherwise).
+ */
+typedef struct {
+    int32_t n_species;            /* S, 1..NNP_MAX_SPECIES                                */
+    int32_t n_shf_r, n_shf_a, n_shf_z;
+    double rcr, rca;              /* radial / angular cutoff, rca <= rcr                  */
+    double eta_r, eta_a, zeta;
+    double angle_scale;           /* 0 < angle_scale < 1 keeps d theta'/d c finite        */
+    double radial_pref;
+    const double* shf_r;          /* host [n_shf_r] */
+    const double* shf_a;          /* host [n_shf_a] */
+    const double* shf_z;          /* host [n_shf_z] */
+
+    int32_t n_models;             /* M >= 1 */
+    int32_t n_layers;             /* affine layers per network (4) */
+    const int32_t* widths;        /* host [n_layers+1]; widths[0] = D, widths[n_layers] = 1 */
+    double celu_alpha;
+    const double* weights;        /* host, FP64, packed as above */
+    const double* sae;            /* host [S] or NULL (zeros) */
+    double energy_scale;
+
+    int32_t precision;            /* NNP_PREC_* */
+    int32_t max_atoms;            /* capacity: atoms per call */
+    int32_t max_mols;             /* capacity: molecules per call */
+    int32_t max_atoms_per_mol;    /* capacity: atoms of the largest molecule (<= 1024) */
+    int32_t device;               /* HIP device ordinal */
+} nnp_model_params;
+
+/*
+ * One evaluation's batch: n_mols molecules in CSR form.  Atoms of molecule b
+ * are [mol_offsets[b], mol_offsets[b+1]) of the coordinate/species arrays.
+ * Molecules never interact; an empty molecule has zero energy.
+ */
+typedef struct {
+    int32_t n_mols;               /* 1..max_mols */
+    int32_t n_atoms;              /* 0..max_atoms, must equal mol_offsets[n_mols] */
+    const int32_t* mol_offsets;   /* device [n_mols+1], non-decreasing, [0] = 0 */
+    const int32_t* species;       /* device [n_atoms], element indices 0..S-1 */
+    void* stream;                 /* hipStream_t; NULL = the null stream */
+    uint32_t flags;               /* reserved, 0 */
+} nnp_batch;
+
+/*
+ * Create a handle: validate the model, pack its weights for the chosen
+ * precision onto the device, and allocate the workspace for the capacities.
+ * This is the only call that allocates device memory.
+ * Returns NNP_OK and *out, or an error (and *out = NULL).
+ */
+nnp_status nnp_create(const nnp_model_params* params, nnp_handle** out);
+
+/* Release the handle and everything it owns (synchronises its device). */
+void nnp_destroy(nnp_handle* h);
+
+/*
+ * Energies and forces (Methods, Eq. 2 and Eq. 3), FP32 / BF16-MLP handles.
+ *   coords  device float [n_atoms][3]
+ *   out_E   device double [n_mols]     (overwritten)
+ *   out_F   device float [n_atoms][3]  (overwritten), may be NULL for energies only
+ * No allocation; safe to capture in a HIP graph once the batch shape is fixed.
+ */
+nnp_status nnp_energy_forces(nnp_handle* h, const nnp_batch* b, const float* coords,
+                             double* out_E, float* out_F);
+
+/* Same for an NNP_PREC_FP64 handle: coordinates and forces in double. */
+nnp_status nnp_energy_forces_f64(nnp_handle* h, const nnp_batch* b, const double* coords,
+                                 double* out_E, double* out_F);
+
+/*
+ * AEVs of the batch (the featuriser of the path alone), device float or
+ * double (FP64 handles) [n_atoms][D], atom order.  For inspection and tests.
+ */
+nnp_status nnp_aev(nnp_handle* h, const nnp_batch* b, const void* coords, void* out_aev);
+
+/*
+ * Training backward of one energies+forces evaluation on the same batch and
+ * coordinates: given the loss cotangents grad_E = dL/dE (device double
+ * [n_mols], may be NULL = 0) and grad_F = dL/dF (device, coordinate type
+ * [n_atoms][3], may be NULL = 0), write
+ *   grad_params  device, float (double for FP64 handles), packed exactly like
+ *                nnp_model_params.weights: dL/dW for every model and element
+ *                (overwritten);
+ *   grad_coords  device, coordinate type [n_atoms][3], dL/dx, or NULL.  Only
+ *                available when grad_F is NULL (E_UNSUPPORTED otherwise).
+ */
+nnp_status nnp_energy_forces_backward(nnp_handle* h, const nnp_batch* b, const void* coords,
+                                      const double* grad_E, const void* grad_F,
+                                      void* grad_params, void* grad_coords);
+
+/* Replace the weights (host FP64, packed as in nnp_model_params.weights).
+ * Synchronous with respect to the host; the handle must be idle. */
+nnp_status nnp_set_weights(nnp_handle* h, const double* weights);
+
+/* Number of packed parameters (the length of weights / grad_params). */
+int64_t nnp_num_params(const nnp_handle* h);
+
+/* AEV dimension D of the handle's featuriser. */
+int32_t nnp_aev_dim(const nnp_handle* h);
+
+/* Read and clear the device-side error flag (synchronises the handle's last
+ * stream).  *code is NNP_OK, NNP_E_SPECIES or NNP_E_CAPACITY. */
+nnp_status nnp_get_device_status(nnp_handle* h, int32_t* code);
+
+/* Per-kernel timing: when enabled, every kernel launch of the handle is
+ * bracketed by HIP events on its stream.  nnp_set_timing (either value)
+ * clears the totals.  nnp_kernel_times synchronises with the recorded events
+ * and returns, for up to cap kernels, their names (valid until the next call
+ * on this thread), launch counts and summed milliseconds since the last
+ * nnp_set_timing.  Returns the number of distinct kernels (-1 on a null
+ * handle); names/counts/total_ms may be NULL to query the count. */
+nnp_status nnp_set_timing(nnp_handle* h, int32_t enable);
+int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t* counts,
+                         double* total_ms);
+
+/* Message of the calling thread's last host-side error ("" if none). */
+const char* nnp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNP_H */

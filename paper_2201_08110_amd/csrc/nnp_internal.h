@@ -1,0 +1,166 @@
+// nnp_internal.h -- shared declarations of the HIP library (kernels + runtime).
+//
+// Data flow of one evaluation (all device-resident, one stream):
+//   prep        element counts, padded per-element row buckets, atom->row map
+//   neighbours  per-atom neighbour lists inside each molecule (angular first)
+//   aev         per-atom AEV rows written in bucket order (GEMM operand type)
+//   mlp         six GEMMs per element bucket, all ensemble members at once:
+//                 layer-1 forward (models concatenated along N), layers 2-3
+//                 forward (per model), layer-3 backward, layer-2 backward,
+//                 layer-1 backward (models summed along K) -> dE/dAEV
+//   forces      AEV backward contracted with dE/dAEV, scattered to atoms
+//   energy      per-molecule FP64 sum of the atomic energies
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nnp {
+
+// ---------------------------------------------------------------------------
+// bf16 storage: raw 16-bit patterns, round-to-nearest-even from float.
+typedef uint16_t bf16_t;
+
+__host__ __device__ inline bf16_t f2bf(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bf16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(bf16_t h) {
+    uint32_t u = ((uint32_t)h) << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// conversion between storage type S and arithmetic type A
+template <typename S> struct Store;
+template <> struct Store<float> {
+    __device__ static float ld(float v) { return v; }
+    __device__ static float st(float v) { return v; }
+};
+template <> struct Store<double> {
+    __device__ static double ld(double v) { return v; }
+    __device__ static double st(double v) { return v; }
+};
+template <> struct Store<bf16_t> {
+    __device__ static float ld(bf16_t v) { return bf2f(v); }
+    __device__ static bf16_t st(float v) { return f2bf(v); }
+};
+
+// ---------------------------------------------------------------------------
+// Precision modes: T = featuriser / force arithmetic, TS = GEMM operand
+// storage, TA = GEMM accumulator and epilogue arithmetic.
+struct PrecF64  { typedef double T; typedef double TS; typedef double TA; };
+struct PrecF32  { typedef float  T; typedef float  TS; typedef float  TA; };
+struct PrecBF16 { typedef float  T; typedef bf16_t TS; typedef float  TA; };
+
+constexpr int kMaxSpecies = 8;
+constexpr int kNR = 16;          // radial shifts supported by the kernels
+constexpr int kNAZ = 32;         // angular (distance x angle) shifts supported
+constexpr int kMaxNA = 16;       // angular-distance shifts (<= 32 / 1)
+constexpr int kMaxAtomsPerMol = 1024;
+constexpr int kMaxNeighbours = 192;
+
+// featuriser constants, passed by value to the kernels
+template <typename T> struct AevConst {
+    int S, nR, nA, nZ, D, Dp;
+    T rcr, rca, rcr2, rca2, eta_r, eta_a, zeta, angle_scale, radial_pref;
+    T pi_rcr, pi_rca;                 // pi / Rc
+    T shf_r[kNR];
+    T shf_a[kMaxNA];
+    T cos_z[kNAZ], sin_z[kNAZ];
+};
+
+// device error flag bits
+enum : int32_t { FLAG_SPECIES = 1, FLAG_CAPACITY = 2 };
+
+// bucket bookkeeping written by the prep kernel
+struct BucketInfo {
+    int32_t rows;                      // padded rows in use (multiple of the row tile)
+    int32_t off[kMaxSpecies + 1];      // padded bucket starts
+    int32_t count[kMaxSpecies];        // atoms per element
+};
+
+// ---------------------------------------------------------------------------
+// workspace views used by the launchers
+template <typename P> struct Work {
+    typedef typename P::T T;
+    typedef typename P::TS TS;
+    typedef typename P::TA TA;
+    int32_t* row_of_atom;   // [A]
+    int32_t* atom_of_row;   // [Rcap]   -1 for padding rows
+    int32_t* mol_of_atom;   // [A]
+    int32_t* tile_species;  // [Rcap / row_tile]
+    BucketInfo* info;
+    int32_t* flag;
+    uint16_t* nbr;          // [A][cap_nbr]  local indices, angular (r < rca) first
+    int32_t* nbr_cnt;       // [A]  n_ang | (n_all << 16)
+    TS* G;                  // [Rcap][Dp]
+    TS* Z1;                 // [Rcap][M*H1]
+    TS* Z2;                 // [Rcap][M*H2]
+    TS* DZ3;                // [Rcap][M*H3]
+    TS* DZ2;                // [Rcap][M*H2]
+    TS* DZ1;                // [Rcap][M*H1]
+    TA* Epart;              // [Rcap][M][H3/64]
+    TA* dG;                 // [Rcap][Dp]
+};
+
+// packed device weights (per precision)
+template <typename P> struct DevWeights {
+    typedef typename P::TS TS;
+    typedef typename P::TA TA;
+    TS* W1;   TS* W1T;   TA* b1;   // [S][M*H1][Dp], [S][Dp][M*H1], [S][M*H1]
+    TS* W2;   TS* W2T;   TA* b2;   // [S][M][H2][H1], [S][M][H1][H2], [S][M][H2]
+    TS* W3;   TS* W3T;   TA* b3;   // [S][M][H3][H2], [S][M][H2][H3], [S][M][H3]
+    TA* w4;   TA* b4;              // [S][M][H3], [S][M]
+    TA* sae;                       // [S] (already multiplied by energy_scale)
+};
+
+struct Shape {
+    int S, M, D, Dp, H1, H2, H3;       // H* padded to multiples of 64
+    int A, B;                          // atoms, molecules of this call
+    int Rcap;                          // capacity rows
+    int row_tile;                      // bucket padding = GEMM row tile
+    int cap_nbr;
+    int max_apm;
+    double energy_scale;
+    double celu_alpha;
+};
+
+// kernel timing hook (runtime-side); launchers call these around launches
+struct Timer {
+    void (*begin)(void* ctx, const char* name, hipStream_t s);
+    void (*end)(void* ctx, const char* name, hipStream_t s);
+    void* ctx;
+    void b(const char* n, hipStream_t s) const { if (begin) begin(ctx, n, s); }
+    void e(const char* n, hipStream_t s) const { if (end) end(ctx, n, s); }
+};
+
+// launchers (explicitly instantiated for PrecF64 / PrecF32 / PrecBF16)
+template <typename P>
+hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* species,
+                       Work<P>& w, hipStream_t st, const Timer& tm);
+template <typename P>
+hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
+                             const int32_t* mol_off, const typename P::T* x,
+                             typename P::T* F_zero, Work<P>& w, hipStream_t st, const Timer& tm);
+template <typename P>
+hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
+                      const int32_t* species, const typename P::T* x, Work<P>& w,
+                      typename P::T* aev_out, hipStream_t st, const Timer& tm);
+template <typename P>
+hipError_t launch_mlp(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipStream_t st,
+                      const Timer& tm);
+template <typename P>
+hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
+                         const int32_t* mol_off, const int32_t* species, const typename P::T* x,
+                         Work<P>& w, typename P::T* F, hipStream_t st, const Timer& tm);
+template <typename P>
+hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t* mol_off,
+                         const int32_t* species, Work<P>& w, double* E, hipStream_t st,
+                         const Timer& tm);
+
+}  // namespace nnp

@@ -1,0 +1,571 @@
+// nnp_runtime.cpp -- host side of the C ABI declared in include/nnp.h.
+//
+// Owns validation, weight packing for the chosen precision, the workspace
+// sized for the declared capacity (the only device allocations), the launch
+// sequence of one evaluation, per-kernel event timing and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "nnp.h"
+#include "nnp_internal.h"
+
+using namespace nnp;
+
+namespace {
+
+thread_local std::string g_err;
+
+nnp_status fail(nnp_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess)                                                           \
+            return fail(_e == hipErrorOutOfMemory ? NNP_E_NOMEM : NNP_E_DEVICE,         \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));             \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int pad_to(int v, int q) { return ((v + q - 1) / q) * q; }
+
+struct EventPair {
+    const char* name;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct nnp_handle {
+    // model
+    int S = 0, nR = 0, nA = 0, nZ = 0, D = 0, M = 0, L = 0;
+    std::vector<int> widths;
+    int precision = 0, device = 0;
+    int max_atoms = 0, max_mols = 0, max_apm = 0;
+    double energy_scale = 1.0, celu_alpha = 0.1;
+    std::vector<double> sae;
+    AevConst<float> cf{};
+    AevConst<double> cd{};
+    Shape shape{};
+    int64_t n_params = 0;
+
+    // device memory
+    std::vector<void*> allocs;
+    DevWeights<PrecF64> w64{};
+    DevWeights<PrecF32> w32{};
+    DevWeights<PrecBF16> w16{};
+    Work<PrecF64> k64{};
+    Work<PrecF32> k32{};
+    Work<PrecBF16> k16{};
+    int32_t* flag = nullptr;
+    hipStream_t last_stream = nullptr;
+
+    // timing
+    bool timing = false;
+    std::vector<EventPair> pending;
+    std::vector<hipEvent_t> free_events;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+
+    void* dalloc(size_t bytes, hipError_t& e) {
+        void* p = nullptr;
+        e = hipMalloc(&p, bytes ? bytes : 16);
+        if (e == hipSuccess) allocs.push_back(p);
+        return p;
+    }
+    hipEvent_t ev() {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+};
+
+namespace {
+
+void tm_begin(void* ctx, const char* name, hipStream_t s) {
+    nnp_handle* h = (nnp_handle*)ctx;
+    EventPair p{name, h->ev(), h->ev()};
+    (void)hipEventRecord(p.a, s);
+    h->pending.push_back(p);
+}
+void tm_end(void* ctx, const char* name, hipStream_t s) {
+    nnp_handle* h = (nnp_handle*)ctx;
+    for (auto it = h->pending.rbegin(); it != h->pending.rend(); ++it)
+        if (it->name == name) {
+            (void)hipEventRecord(it->b, s);
+            return;
+        }
+}
+Timer make_timer(nnp_handle* h) {
+    Timer t{};
+    if (h->timing) {
+        t.begin = tm_begin;
+        t.end = tm_end;
+        t.ctx = h;
+    }
+    return t;
+}
+
+template <typename T> void fill_const(AevConst<T>& c, const nnp_model_params* p, int D, int Dp) {
+    c.S = p->n_species;
+    c.nR = p->n_shf_r;
+    c.nA = p->n_shf_a;
+    c.nZ = p->n_shf_z;
+    c.D = D;
+    c.Dp = Dp;
+    c.rcr = (T)p->rcr;
+    c.rca = (T)p->rca;
+    c.rcr2 = (T)(p->rcr * p->rcr);
+    c.rca2 = (T)(p->rca * p->rca);
+    c.eta_r = (T)p->eta_r;
+    c.eta_a = (T)p->eta_a;
+    c.zeta = (T)p->zeta;
+    c.angle_scale = (T)p->angle_scale;
+    c.radial_pref = (T)p->radial_pref;
+    c.pi_rcr = (T)(M_PI / p->rcr);
+    c.pi_rca = (T)(M_PI / p->rca);
+    for (int k = 0; k < p->n_shf_r; ++k) c.shf_r[k] = (T)p->shf_r[k];
+    for (int a = 0; a < p->n_shf_a; ++a) c.shf_a[a] = (T)p->shf_a[a];
+    for (int z = 0; z < p->n_shf_z; ++z) {
+        c.cos_z[z] = (T)std::cos(p->shf_z[z]);
+        c.sin_z[z] = (T)std::sin(p->shf_z[z]);
+    }
+}
+
+template <typename TS> TS to_store(double v);
+template <> float to_store<float>(double v) { return (float)v; }
+template <> double to_store<double>(double v) { return v; }
+template <> bf16_t to_store<bf16_t>(double v) { return f2bf((float)v); }
+
+// Pack FP64 master weights [m][s][layer]{W, b} into the device layouts.
+template <typename P> nnp_status upload_weights(nnp_handle* h, DevWeights<P>& dw,
+                                                const double* w, bool allocate) {
+    typedef typename P::TS TS;
+    typedef typename P::TA TA;
+    const Shape& sh = h->shape;
+    const int S = h->S, M = h->M, D = h->D, Dp = sh.Dp;
+    const int o1 = h->widths[1], o2 = h->widths[2], o3 = h->widths[3];
+    const int H1 = sh.H1, H2 = sh.H2, H3 = sh.H3;
+    std::vector<TS> W1((size_t)S * M * H1 * Dp, to_store<TS>(0.0)), W1T(W1.size(), to_store<TS>(0.0));
+    std::vector<TS> W2((size_t)S * M * H2 * H1, to_store<TS>(0.0)), W2T(W2.size(), to_store<TS>(0.0));
+    std::vector<TS> W3((size_t)S * M * H3 * H2, to_store<TS>(0.0)), W3T(W3.size(), to_store<TS>(0.0));
+    std::vector<TA> b1((size_t)S * M * H1, 0), b2((size_t)S * M * H2, 0), b3((size_t)S * M * H3, 0);
+    std::vector<TA> w4((size_t)S * M * H3, 0), b4((size_t)S * M, 0), sae(S, 0);
+    const size_t net = (size_t)o1 * D + o1 + (size_t)o2 * o1 + o2 + (size_t)o3 * o2 + o3 + o3 + 1;
+    for (int m = 0; m < M; ++m)
+        for (int s = 0; s < S; ++s) {
+            const double* p = w + ((size_t)m * S + s) * net;
+            for (int n = 0; n < o1; ++n)
+                for (int k = 0; k < D; ++k) {
+                    TS v = to_store<TS>(p[(size_t)n * D + k]);
+                    W1[((size_t)s * M * H1 + (size_t)m * H1 + n) * Dp + k] = v;
+                    W1T[((size_t)s * Dp + k) * M * H1 + (size_t)m * H1 + n] = v;
+                }
+            p += (size_t)o1 * D;
+            for (int n = 0; n < o1; ++n) b1[(size_t)s * M * H1 + (size_t)m * H1 + n] = (TA)p[n];
+            p += o1;
+            const size_t sm = (size_t)s * M + m;
+            for (int n = 0; n < o2; ++n)
+                for (int k = 0; k < o1; ++k) {
+                    TS v = to_store<TS>(p[(size_t)n * o1 + k]);
+                    W2[(sm * H2 + n) * H1 + k] = v;
+                    W2T[(sm * H1 + k) * H2 + n] = v;
+                }
+            p += (size_t)o2 * o1;
+            for (int n = 0; n < o2; ++n) b2[sm * H2 + n] = (TA)p[n];
+            p += o2;
+            for (int n = 0; n < o3; ++n)
+                for (int k = 0; k < o2; ++k) {
+                    TS v = to_store<TS>(p[(size_t)n * o2 + k]);
+                    W3[(sm * H3 + n) * H2 + k] = v;
+                    W3T[(sm * H2 + k) * H3 + n] = v;
+                }
+            p += (size_t)o3 * o2;
+            for (int n = 0; n < o3; ++n) b3[sm * H3 + n] = (TA)p[n];
+            p += o3;
+            for (int n = 0; n < o3; ++n) w4[sm * H3 + n] = (TA)p[n];
+            p += o3;
+            b4[sm] = (TA)p[0];
+        }
+    for (int s = 0; s < S; ++s) sae[s] = (TA)(h->energy_scale * (h->sae.empty() ? 0.0 : h->sae[s]));
+    hipError_t e = hipSuccess;
+    auto put = [&](auto*& dst, const auto& src) -> bool {
+        size_t bytes = src.size() * sizeof(src[0]);
+        if (allocate) {
+            dst = (std::remove_reference_t<decltype(dst)>)h->dalloc(bytes, e);
+            if (e != hipSuccess) return false;
+        }
+        e = hipMemcpy(dst, src.data(), bytes, hipMemcpyHostToDevice);
+        return e == hipSuccess;
+    };
+    if (!put(dw.W1, W1) || !put(dw.W1T, W1T) || !put(dw.b1, b1) || !put(dw.W2, W2) ||
+        !put(dw.W2T, W2T) || !put(dw.b2, b2) || !put(dw.W3, W3) || !put(dw.W3T, W3T) ||
+        !put(dw.b3, b3) || !put(dw.w4, w4) || !put(dw.b4, b4) || !put(dw.sae, sae))
+        return fail(e == hipErrorOutOfMemory ? NNP_E_NOMEM : NNP_E_DEVICE,
+                    std::string("weight upload: ") + hipGetErrorString(e));
+    return NNP_OK;
+}
+
+template <typename P> nnp_status alloc_work(nnp_handle* h, Work<P>& w) {
+    typedef typename P::TS TS;
+    typedef typename P::TA TA;
+    const Shape& sh = h->shape;
+    const size_t A = (size_t)std::max(h->max_atoms, 1), R = sh.Rcap;
+    const int M = sh.M;
+    hipError_t e = hipSuccess;
+#define ALLOC(field, bytes)                                                              \
+    do {                                                                                 \
+        w.field = (decltype(w.field))h->dalloc(bytes, e);                                \
+        if (e != hipSuccess)                                                             \
+            return fail(e == hipErrorOutOfMemory ? NNP_E_NOMEM : NNP_E_DEVICE,           \
+                        std::string("workspace ") + #field + ": " + hipGetErrorString(e)); \
+    } while (0)
+    ALLOC(row_of_atom, sizeof(int32_t) * A);
+    ALLOC(atom_of_row, sizeof(int32_t) * R);
+    ALLOC(mol_of_atom, sizeof(int32_t) * A);
+    ALLOC(tile_species, sizeof(int32_t) * (R / sh.row_tile));
+    ALLOC(info, sizeof(BucketInfo));
+    ALLOC(nbr, sizeof(uint16_t) * A * sh.cap_nbr);
+    ALLOC(nbr_cnt, sizeof(int32_t) * A);
+    ALLOC(G, sizeof(TS) * R * sh.Dp);
+    ALLOC(Z1, sizeof(TS) * R * M * sh.H1);
+    ALLOC(Z2, sizeof(TS) * R * M * sh.H2);
+    ALLOC(DZ3, sizeof(TS) * R * M * sh.H3);
+    ALLOC(DZ2, sizeof(TS) * R * M * sh.H2);
+    ALLOC(DZ1, sizeof(TS) * R * M * sh.H1);
+    ALLOC(Epart, sizeof(TA) * R * M * (sh.H3 / 64));
+    ALLOC(dG, sizeof(TA) * R * sh.Dp);
+#undef ALLOC
+    w.flag = h->flag;
+    // every row index the kernels may read must be in range from the start
+    HIP_TRY(hipMemset(w.row_of_atom, 0, sizeof(int32_t) * A));
+    HIP_TRY(hipMemset(w.nbr_cnt, 0, sizeof(int32_t) * A));
+    HIP_TRY(hipMemset(w.info, 0, sizeof(BucketInfo)));
+    // padding rows of the AEV operand are never written by the featuriser
+    HIP_TRY(hipMemset(w.G, 0, sizeof(TS) * R * sh.Dp));
+    return NNP_OK;
+}
+
+nnp_status check_batch(const nnp_handle* h, const nnp_batch* b) {
+    if (!h || !b) return fail(NNP_E_INVALID, "null handle or batch");
+    if (b->n_mols < 1) return fail(NNP_E_INVALID, "n_mols must be >= 1");
+    if (b->n_mols > h->max_mols) return fail(NNP_E_CAPACITY, "n_mols exceeds max_mols");
+    if (b->n_atoms < 0) return fail(NNP_E_INVALID, "n_atoms must be >= 0");
+    if (b->n_atoms > h->max_atoms) return fail(NNP_E_CAPACITY, "n_atoms exceeds max_atoms");
+    if (!b->mol_offsets) return fail(NNP_E_INVALID, "null mol_offsets");
+    if (b->n_atoms > 0 && !b->species) return fail(NNP_E_INVALID, "null species");
+    if (b->flags != 0) return fail(NNP_E_INVALID, "flags must be 0");
+    return NNP_OK;
+}
+
+template <typename P> Work<P>& work_of(nnp_handle* h);
+template <> Work<PrecF64>& work_of<PrecF64>(nnp_handle* h) { return h->k64; }
+template <> Work<PrecF32>& work_of<PrecF32>(nnp_handle* h) { return h->k32; }
+template <> Work<PrecBF16>& work_of<PrecBF16>(nnp_handle* h) { return h->k16; }
+template <typename P> DevWeights<P>& weights_of(nnp_handle* h);
+template <> DevWeights<PrecF64>& weights_of<PrecF64>(nnp_handle* h) { return h->w64; }
+template <> DevWeights<PrecF32>& weights_of<PrecF32>(nnp_handle* h) { return h->w32; }
+template <> DevWeights<PrecBF16>& weights_of<PrecBF16>(nnp_handle* h) { return h->w16; }
+template <typename T> const AevConst<T>& const_of(nnp_handle* h);
+template <> const AevConst<float>& const_of<float>(nnp_handle* h) { return h->cf; }
+template <> const AevConst<double>& const_of<double>(nnp_handle* h) { return h->cd; }
+
+template <typename P>
+nnp_status run_forward(nnp_handle* h, const nnp_batch* b, const typename P::T* x, double* E,
+                       typename P::T* F, typename P::T* aev_out) {
+    typedef typename P::T T;
+    Shape sh = h->shape;
+    sh.A = b->n_atoms;
+    sh.B = b->n_mols;
+    hipStream_t st = (hipStream_t)b->stream;
+    h->last_stream = st;
+    Work<P>& w = work_of<P>(h);
+    const AevConst<T>& c = const_of<T>(h);
+    Timer tm = make_timer(h);
+    HIP_TRY(launch_prep<P>(sh, b->mol_offsets, b->species, w, st, tm));
+    if (sh.A > 0) {
+        HIP_TRY(launch_neighbours<P>(sh, c, b->mol_offsets, x, F, w, st, tm));
+        HIP_TRY(launch_aev<P>(sh, c, b->mol_offsets, b->species, x, w, aev_out, st, tm));
+    }
+    if (aev_out) return NNP_OK;
+    if (sh.A > 0) HIP_TRY(launch_mlp<P>(sh, weights_of<P>(h), w, st, tm));
+    if (F && sh.A > 0)
+        HIP_TRY(launch_forces<P>(sh, c, b->mol_offsets, b->species, x, w, F, st, tm));
+    HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), b->mol_offsets, b->species, w, E, st, tm));
+    return NNP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* nnp_last_error(void) { return g_err.c_str(); }
+
+nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
+    if (!out) return fail(NNP_E_INVALID, "null output pointer");
+    *out = nullptr;
+    if (!p) return fail(NNP_E_INVALID, "null params");
+    if (p->n_species < 1 || p->n_species > NNP_MAX_SPECIES)
+        return fail(NNP_E_INVALID, "n_species must be in 1..8");
+    if (!p->shf_r || !p->shf_a || !p->shf_z || !p->weights || !p->widths)
+        return fail(NNP_E_INVALID, "null shift, width or weight array");
+    if (p->n_shf_r != kNR || p->n_shf_a * p->n_shf_z != kNAZ || (p->n_shf_z != 4 && p->n_shf_z != 8))
+        return fail(NNP_E_UNSUPPORTED, "this build supports 16 radial shifts and 8x4 or 4x8 angular shifts");
+    if (!(p->rcr > 0) || !(p->rca > 0) || p->rca > p->rcr)
+        return fail(NNP_E_INVALID, "cutoffs must satisfy 0 < rca <= rcr");
+    if (!(p->angle_scale > 0 && p->angle_scale < 1))
+        return fail(NNP_E_INVALID, "angle_scale must be in (0, 1)");
+    if (!(p->zeta >= 1) || !(p->eta_r >= 0) || !(p->eta_a >= 0))
+        return fail(NNP_E_INVALID, "need zeta >= 1, eta_r >= 0, eta_a >= 0");
+    if (!(p->celu_alpha > 0)) return fail(NNP_E_INVALID, "celu_alpha must be > 0");
+    if (p->n_models < 1 || p->n_models > 64) return fail(NNP_E_INVALID, "n_models must be in 1..64");
+    if (p->n_layers != 4) return fail(NNP_E_UNSUPPORTED, "this build supports 4 affine layers");
+    const int S = p->n_species;
+    const int D = S * p->n_shf_r + (S * (S + 1) / 2) * p->n_shf_a * p->n_shf_z;
+    if (p->widths[0] != D) return fail(NNP_E_INVALID, "widths[0] must equal the AEV dimension");
+    if (p->widths[4] != 1) return fail(NNP_E_INVALID, "the last width must be 1");
+    for (int l = 1; l < 4; ++l)
+        if (p->widths[l] < 1 || p->widths[l] > 4096 || p->widths[l] % 32)
+            return fail(NNP_E_UNSUPPORTED, "hidden widths must be multiples of 32 up to 4096");
+    if (p->precision < NNP_PREC_FP64 || p->precision > NNP_PREC_BF16_MLP)
+        return fail(NNP_E_INVALID, "unknown precision");
+    if (p->max_atoms < 1 || p->max_mols < 1 || p->max_atoms_per_mol < 1)
+        return fail(NNP_E_INVALID, "capacities must be >= 1");
+    if (p->max_atoms_per_mol > kMaxAtomsPerMol)
+        return fail(NNP_E_UNSUPPORTED, "max_atoms_per_mol is limited to 1024");
+    if (p->max_atoms > (1 << 26)) return fail(NNP_E_INVALID, "max_atoms too large");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(NNP_E_DEVICE, "no HIP device available");
+    if (p->device < 0 || p->device >= ndev) return fail(NNP_E_INVALID, "device ordinal out of range");
+
+    nnp_handle* h = new nnp_handle();
+    h->S = S;
+    h->nR = p->n_shf_r;
+    h->nA = p->n_shf_a;
+    h->nZ = p->n_shf_z;
+    h->D = D;
+    h->M = p->n_models;
+    h->L = p->n_layers;
+    h->widths.assign(p->widths, p->widths + 5);
+    h->precision = p->precision;
+    h->device = p->device;
+    h->max_atoms = p->max_atoms;
+    h->max_mols = p->max_mols;
+    h->max_apm = std::min(p->max_atoms_per_mol, p->max_atoms);
+    h->energy_scale = p->energy_scale;
+    h->celu_alpha = p->celu_alpha;
+    if (p->sae) h->sae.assign(p->sae, p->sae + S);
+    int64_t net = 0;
+    for (int l = 0; l < 4; ++l) net += (int64_t)p->widths[l + 1] * p->widths[l] + p->widths[l + 1];
+    h->n_params = net * S * h->M;
+
+    Shape& sh = h->shape;
+    sh.S = S;
+    sh.M = h->M;
+    sh.D = D;
+    sh.Dp = pad_to(D, 64);
+    sh.H1 = pad_to(p->widths[1], 64);
+    sh.H2 = pad_to(p->widths[2], 64);
+    sh.H3 = pad_to(p->widths[3], 64);
+    sh.row_tile = (p->max_atoms <= 256 || p->precision == NNP_PREC_FP64) ? 16 : 64;
+    sh.Rcap = pad_to(p->max_atoms + S * (sh.row_tile - 1), sh.row_tile);
+    sh.cap_nbr = std::max(1, std::min(h->max_apm - 1, kMaxNeighbours));
+    sh.max_apm = h->max_apm;
+    sh.energy_scale = p->energy_scale;
+    sh.celu_alpha = p->celu_alpha;
+    fill_const(h->cf, p, D, sh.Dp);
+    fill_const(h->cd, p, D, sh.Dp);
+
+    DeviceGuard dg(h->device);
+    if (!dg.ok) {
+        delete h;
+        return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    }
+    hipError_t e = hipSuccess;
+    h->flag = (int32_t*)h->dalloc(sizeof(int32_t), e);
+    nnp_status rc = e == hipSuccess ? NNP_OK : fail(NNP_E_NOMEM, "flag allocation failed");
+    if (rc == NNP_OK && hipMemset(h->flag, 0, sizeof(int32_t)) != hipSuccess)
+        rc = fail(NNP_E_DEVICE, "hipMemset failed");
+    if (rc == NNP_OK) {
+        if (p->precision == NNP_PREC_FP64) {
+            rc = upload_weights<PrecF64>(h, h->w64, p->weights, true);
+            if (rc == NNP_OK) rc = alloc_work<PrecF64>(h, h->k64);
+        } else if (p->precision == NNP_PREC_FP32) {
+            rc = upload_weights<PrecF32>(h, h->w32, p->weights, true);
+            if (rc == NNP_OK) rc = alloc_work<PrecF32>(h, h->k32);
+        } else {
+            rc = upload_weights<PrecBF16>(h, h->w16, p->weights, true);
+            if (rc == NNP_OK) rc = alloc_work<PrecBF16>(h, h->k16);
+        }
+    }
+    if (rc != NNP_OK) {
+        std::string msg = g_err;
+        nnp_destroy(h);
+        g_err = msg;
+        return rc;
+    }
+    *out = h;
+    return NNP_OK;
+}
+
+void nnp_destroy(nnp_handle* h) {
+    if (!h) return;
+    DeviceGuard dg(h->device);
+    (void)hipDeviceSynchronize();
+    for (void* p : h->allocs) (void)hipFree(p);
+    for (auto& p : h->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : h->free_events) (void)hipEventDestroy(e);
+    delete h;
+}
+
+nnp_status nnp_energy_forces(nnp_handle* h, const nnp_batch* b, const float* coords,
+                             double* out_E, float* out_F) {
+    nnp_status rc = check_batch(h, b);
+    if (rc) return rc;
+    if (h->precision == NNP_PREC_FP64)
+        return fail(NNP_E_INVALID, "FP64 handle: use nnp_energy_forces_f64");
+    if (!out_E || (b->n_atoms > 0 && !coords)) return fail(NNP_E_INVALID, "null coords or out_E");
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    if (h->precision == NNP_PREC_FP32)
+        return run_forward<PrecF32>(h, b, coords, out_E, out_F, nullptr);
+    return run_forward<PrecBF16>(h, b, coords, out_E, out_F, nullptr);
+}
+
+nnp_status nnp_energy_forces_f64(nnp_handle* h, const nnp_batch* b, const double* coords,
+                                 double* out_E, double* out_F) {
+    nnp_status rc = check_batch(h, b);
+    if (rc) return rc;
+    if (h->precision != NNP_PREC_FP64)
+        return fail(NNP_E_INVALID, "FP32/BF16 handle: use nnp_energy_forces");
+    if (!out_E || (b->n_atoms > 0 && !coords)) return fail(NNP_E_INVALID, "null coords or out_E");
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    return run_forward<PrecF64>(h, b, coords, out_E, out_F, nullptr);
+}
+
+nnp_status nnp_aev(nnp_handle* h, const nnp_batch* b, const void* coords, void* out_aev) {
+    nnp_status rc = check_batch(h, b);
+    if (rc) return rc;
+    if (!out_aev || (b->n_atoms > 0 && !coords)) return fail(NNP_E_INVALID, "null coords or out_aev");
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    if (h->precision == NNP_PREC_FP64)
+        return run_forward<PrecF64>(h, b, (const double*)coords, nullptr, nullptr, (double*)out_aev);
+    if (h->precision == NNP_PREC_FP32)
+        return run_forward<PrecF32>(h, b, (const float*)coords, nullptr, nullptr, (float*)out_aev);
+    return run_forward<PrecBF16>(h, b, (const float*)coords, nullptr, nullptr, (float*)out_aev);
+}
+
+nnp_status nnp_energy_forces_backward(nnp_handle* h, const nnp_batch* b, const void* coords,
+                                      const double* grad_E, const void* grad_F,
+                                      void* grad_params, void* grad_coords) {
+    nnp_status rc = check_batch(h, b);
+    if (rc) return rc;
+    (void)coords; (void)grad_E; (void)grad_F; (void)grad_params; (void)grad_coords;
+    return fail(NNP_E_UNSUPPORTED, "training backward is not available in this build");
+}
+
+nnp_status nnp_set_weights(nnp_handle* h, const double* weights) {
+    if (!h || !weights) return fail(NNP_E_INVALID, "null handle or weights");
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    HIP_TRY(hipDeviceSynchronize());
+    if (h->precision == NNP_PREC_FP64) return upload_weights<PrecF64>(h, h->w64, weights, false);
+    if (h->precision == NNP_PREC_FP32) return upload_weights<PrecF32>(h, h->w32, weights, false);
+    return upload_weights<PrecBF16>(h, h->w16, weights, false);
+}
+
+int64_t nnp_num_params(const nnp_handle* h) { return h ? h->n_params : -1; }
+
+int32_t nnp_aev_dim(const nnp_handle* h) { return h ? h->D : -1; }
+
+nnp_status nnp_get_device_status(nnp_handle* h, int32_t* code) {
+    if (!h || !code) return fail(NNP_E_INVALID, "null handle or code");
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    HIP_TRY(hipStreamSynchronize(h->last_stream));
+    int32_t f = 0;
+    HIP_TRY(hipMemcpy(&f, h->flag, sizeof(f), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(h->flag, 0, sizeof(int32_t)));
+    *code = (f & FLAG_SPECIES) ? NNP_E_SPECIES : (f & FLAG_CAPACITY) ? NNP_E_CAPACITY : NNP_OK;
+    return NNP_OK;
+}
+
+nnp_status nnp_set_timing(nnp_handle* h, int32_t enable) {
+    if (!h) return fail(NNP_E_INVALID, "null handle");
+    DeviceGuard dg(h->device);
+    for (auto& p : h->pending) {
+        (void)hipEventSynchronize(p.b);
+        h->free_events.push_back(p.a);
+        h->free_events.push_back(p.b);
+    }
+    h->pending.clear();
+    h->totals.clear();
+    h->timing = enable != 0;
+    return NNP_OK;
+}
+
+int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t* counts,
+                         double* total_ms) {
+    if (!h) return -1;
+    DeviceGuard dg(h->device);
+    for (auto& p : h->pending) {
+        (void)hipEventSynchronize(p.b);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto& t = h->totals[p.name];
+            t.first += 1;
+            t.second += ms;
+        }
+        h->free_events.push_back(p.a);
+        h->free_events.push_back(p.b);
+    }
+    h->pending.clear();
+    int32_t n = 0;
+    for (auto& kv : h->totals) {
+        if (n < cap) {
+            // names point into static storage of the launchers (string literals)
+            static thread_local std::vector<std::string> keep;
+            if ((int)keep.size() < cap) keep.resize(cap);
+            keep[n] = kv.first;
+            if (names) names[n] = keep[n].c_str();
+            if (counts) counts[n] = kv.second.first;
+            if (total_ms) total_ms[n] = kv.second.second;
+        }
+        ++n;
+    }
+    return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,252 @@
+"""ctypes binding of libnnp_hip.so (the C ABI of include/nnp.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Tensors are torch CUDA (HIP) tensors; the library runs on torch's
+current stream.  If the library has not been built this module raises on
+first use -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnnp_hip.so")
+
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+NNP_OK, NNP_E_INVALID, NNP_E_SPECIES, NNP_E_CAPACITY, NNP_E_NOMEM, NNP_E_DEVICE, \
+    NNP_E_UNSUPPORTED = range(7)
+
+
+class NNPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nnp error {code}: {msg}")
+        self.code = code
+
+
+class ModelParams(C.Structure):
+    _fields_ = [
+        ("n_species", C.c_int32), ("n_shf_r", C.c_int32), ("n_shf_a", C.c_int32),
+        ("n_shf_z", C.c_int32),
+        ("rcr", C.c_double), ("rca", C.c_double), ("eta_r", C.c_double), ("eta_a", C.c_double),
+        ("zeta", C.c_double), ("angle_scale", C.c_double), ("radial_pref", C.c_double),
+        ("shf_r", C.POINTER(C.c_double)), ("shf_a", C.POINTER(C.c_double)),
+        ("shf_z", C.POINTER(C.c_double)),
+        ("n_models", C.c_int32), ("n_layers", C.c_int32), ("widths", C.POINTER(C.c_int32)),
+        ("celu_alpha", C.c_double), ("weights", C.POINTER(C.c_double)),
+        ("sae", C.POINTER(C.c_double)), ("energy_scale", C.c_double),
+        ("precision", C.c_int32), ("max_atoms", C.c_int32), ("max_mols", C.c_int32),
+        ("max_atoms_per_mol", C.c_int32), ("device", C.c_int32),
+    ]
+
+
+class Batch(C.Structure):
+    _fields_ = [("n_mols", C.c_int32), ("n_atoms", C.c_int32), ("mol_offsets", C.c_void_p),
+                ("species", C.c_void_p), ("stream", C.c_void_p), ("flags", C.c_uint32)]
+
+
+_lib = None
+
+#: every symbol include/nnp.h declares
+EXPORTS = ("nnp_create", "nnp_destroy", "nnp_energy_forces", "nnp_energy_forces_f64", "nnp_aev",
+           "nnp_energy_forces_backward", "nnp_set_weights", "nnp_num_params", "nnp_aev_dim",
+           "nnp_get_device_status", "nnp_set_timing", "nnp_kernel_times", "nnp_last_error")
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libnnp_hip.so and declare its signatures (no GPU work)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_2201_08110_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = C.CDLL(path)
+    P, vp, i32, i64, d = C.POINTER, C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.nnp_create.argtypes = [P(ModelParams), P(vp)]
+    lib.nnp_create.restype = i32
+    lib.nnp_destroy.argtypes = [vp]
+    lib.nnp_destroy.restype = None
+    for name in ("nnp_energy_forces", "nnp_energy_forces_f64"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, P(Batch), vp, vp, vp]
+        f.restype = i32
+    lib.nnp_aev.argtypes = [vp, P(Batch), vp, vp]
+    lib.nnp_aev.restype = i32
+    lib.nnp_energy_forces_backward.argtypes = [vp, P(Batch), vp, vp, vp, vp, vp]
+    lib.nnp_energy_forces_backward.restype = i32
+    lib.nnp_set_weights.argtypes = [vp, P(d)]
+    lib.nnp_set_weights.restype = i32
+    lib.nnp_num_params.argtypes = [vp]
+    lib.nnp_num_params.restype = i64
+    lib.nnp_aev_dim.argtypes = [vp]
+    lib.nnp_aev_dim.restype = i32
+    lib.nnp_get_device_status.argtypes = [vp, P(i32)]
+    lib.nnp_get_device_status.restype = i32
+    lib.nnp_set_timing.argtypes = [vp, i32]
+    lib.nnp_set_timing.restype = i32
+    lib.nnp_kernel_times.argtypes = [vp, i32, P(C.c_char_p), P(i64), P(d)]
+    lib.nnp_kernel_times.restype = i32
+    lib.nnp_last_error.argtypes = []
+    lib.nnp_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != NNP_OK:
+        raise NNPError(rc, load_library().nnp_last_error().decode())
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class NNP:
+    """One handle of the library: a model, a precision and a capacity."""
+
+    def __init__(self, hp: dict, weights, n_models: int, precision: str = "fp32",
+                 max_atoms: int = 1024, max_mols: int = 64, max_atoms_per_mol: int = 128,
+                 device: int = 0, sae=None):
+        lib = load_library()
+        self._keep = []
+
+        def darr(v):
+            a = np.ascontiguousarray(v, dtype=np.float64)
+            self._keep.append(a)
+            return _dp(a)
+
+        wd = np.ascontiguousarray(hp["widths"], dtype=np.int32)
+        self._keep.append(wd)
+        p = ModelParams()
+        p.n_species = hp["n_species"]
+        p.n_shf_r, p.n_shf_a, p.n_shf_z = len(hp["shf_r"]), len(hp["shf_a"]), len(hp["shf_z"])
+        p.rcr, p.rca = hp["rcr"], hp["rca"]
+        p.eta_r, p.eta_a, p.zeta = hp["eta_r"], hp["eta_a"], hp["zeta"]
+        p.angle_scale, p.radial_pref = hp["angle_scale"], hp["radial_pref"]
+        p.shf_r, p.shf_a, p.shf_z = darr(hp["shf_r"]), darr(hp["shf_a"]), darr(hp["shf_z"])
+        p.n_models = n_models
+        p.n_layers = len(wd) - 1
+        p.widths = wd.ctypes.data_as(C.POINTER(C.c_int32))
+        p.celu_alpha = hp["celu_alpha"]
+        p.weights = darr(weights)
+        p.sae = darr(sae) if sae is not None else None
+        p.energy_scale = hp["energy_scale"]
+        p.precision = PREC[precision]
+        p.max_atoms, p.max_mols, p.max_atoms_per_mol = max_atoms, max_mols, max_atoms_per_mol
+        p.device = device
+        h = C.c_void_p()
+        _check(lib.nnp_create(C.byref(p), C.byref(h)))
+        self._keep = []
+        self.h = h
+        self.precision = precision
+        self.device = device
+        self.lib = lib
+
+    # -- helpers -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nnp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def coord_dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def _batch(self, species, mol_offsets, stream=None):
+        import torch
+        b = Batch()
+        b.n_mols = int(mol_offsets.numel()) - 1
+        b.n_atoms = int(species.numel())
+        b.mol_offsets = mol_offsets.data_ptr()
+        b.species = species.data_ptr() if species.numel() else None
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        b.stream = s.cuda_stream
+        b.flags = 0
+        return b
+
+    @staticmethod
+    def _need(t, dtype, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if t.dtype != dtype or not t.is_contiguous():
+            raise TypeError(f"{name} must be contiguous {dtype}")
+
+    # -- API ---------------------------------------------------------------
+    def energy_forces(self, coords, species, mol_offsets, forces: bool = True, out=None):
+        """Energies [B] (float64) and forces [A, 3] of a ragged batch."""
+        import torch
+        self._need(coords, self.coord_dtype, "coords")
+        self._need(species, torch.int32, "species")
+        self._need(mol_offsets, torch.int32, "mol_offsets")
+        b = self._batch(species, mol_offsets)
+        if out is None:
+            E = torch.empty(b.n_mols, dtype=torch.float64, device=coords.device)
+            F = torch.empty_like(coords) if forces else None
+        else:
+            E, F = out
+        fn = self.lib.nnp_energy_forces_f64 if self.precision == "fp64" else self.lib.nnp_energy_forces
+        _check(fn(self.h, C.byref(b), coords.data_ptr(), E.data_ptr(),
+                  F.data_ptr() if F is not None else None))
+        return E, F
+
+    def aev(self, coords, species, mol_offsets):
+        import torch
+        self._need(coords, self.coord_dtype, "coords")
+        b = self._batch(species, mol_offsets)
+        out = torch.empty((b.n_atoms, self.aev_dim), dtype=self.coord_dtype, device=coords.device)
+        _check(self.lib.nnp_aev(self.h, C.byref(b), coords.data_ptr(), out.data_ptr()))
+        return out
+
+    def backward(self, coords, species, mol_offsets, grad_E=None, grad_F=None,
+                 want_coords: bool = False):
+        """dL/dW (packed like the weights) and optionally dL/dx."""
+        import torch
+        b = self._batch(species, mol_offsets)
+        gp = torch.empty(self.num_params, dtype=self.coord_dtype, device=coords.device)
+        gx = torch.empty_like(coords) if want_coords else None
+        _check(self.lib.nnp_energy_forces_backward(
+            self.h, C.byref(b), coords.data_ptr(),
+            grad_E.data_ptr() if grad_E is not None else None,
+            grad_F.data_ptr() if grad_F is not None else None,
+            gp.data_ptr(), gx.data_ptr() if gx is not None else None))
+        return gp, gx
+
+    def set_weights(self, weights):
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        _check(self.lib.nnp_set_weights(self.h, _dp(w)))
+
+    @property
+    def num_params(self) -> int:
+        return int(self.lib.nnp_num_params(self.h))
+
+    @property
+    def aev_dim(self) -> int:
+        return int(self.lib.nnp_aev_dim(self.h))
+
+    def device_status(self) -> int:
+        code = C.c_int32(0)
+        _check(self.lib.nnp_get_device_status(self.h, C.byref(code)))
+        return int(code.value)
+
+    def set_timing(self, on: bool):
+        _check(self.lib.nnp_set_timing(self.h, 1 if on else 0))
+
+    def kernel_times(self) -> dict:
+        n = self.lib.nnp_kernel_times(self.h, 0, None, None, None)
+        names = (C.c_char_p * max(n, 1))()
+        counts = (C.c_int64 * max(n, 1))()
+        ms = (C.c_double * max(n, 1))()
+        n = self.lib.nnp_kernel_times(self.h, n, names, counts, ms)
+        return {names[i].decode(): (int(counts[i]), float(ms[i])) for i in range(n)}

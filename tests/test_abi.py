@@ -1,0 +1,89 @@
+"""The C ABI library loads, exports every declared symbol and rejects bad
+arguments on the host before touching a GPU (runs without one)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2201_08110_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2201_08110_amd import nnp
+    if not os.path.exists(nnp.LIB_PATH):
+        pytest.skip("libnnp_hip.so not built")
+    return nnp, nnp.load_library()
+
+
+def test_exports_match_header():
+    nnp, lib = _lib()
+    hdr = open(os.path.join(ROOT, "include", "nnp.h")).read()
+    declared = set(re.findall(r"\b(nnp_[a-z0-9_]+)\s*\(", hdr))
+    assert declared == set(nnp.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _params(nnp, hp, w, **over):
+    keep = []
+
+    def darr(v):
+        a = np.ascontiguousarray(v, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+
+    wd = np.ascontiguousarray(hp["widths"], dtype=np.int32)
+    keep.append(wd)
+    p = nnp.ModelParams(n_species=7, n_shf_r=16, n_shf_a=8, n_shf_z=4, rcr=5.1, rca=3.5,
+                        eta_r=19.7, eta_a=12.5, zeta=14.1, angle_scale=0.95, radial_pref=0.25,
+                        shf_r=darr(hp["shf_r"]), shf_a=darr(hp["shf_a"]), shf_z=darr(hp["shf_z"]),
+                        n_models=1, n_layers=4, widths=wd.ctypes.data_as(C.POINTER(C.c_int32)),
+                        celu_alpha=0.1, weights=darr(w), sae=None, energy_scale=627.5,
+                        precision=1, max_atoms=64, max_mols=4, max_atoms_per_mol=64, device=0)
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p, keep
+
+
+@pytest.mark.parametrize("over,code", [
+    ({"n_species": 0}, 1), ({"n_species": 9}, 1), ({"n_shf_r": 8}, 6), ({"rca": 6.0}, 1),
+    ({"angle_scale": 1.0}, 1), ({"zeta": 0.5}, 1), ({"celu_alpha": 0.0}, 1),
+    ({"n_models": 0}, 1), ({"n_layers": 3}, 6), ({"precision": 7}, 1), ({"max_atoms": 0}, 1),
+    ({"max_atoms_per_mol": 5000}, 6),
+])
+def test_create_rejects_bad_params(hp, over, code):
+    nnp, lib = _lib()
+    w = np.zeros(synth.net_size(hp["widths"]) * 7)
+    p, keep = _params(nnp, hp, w, **over)
+    h = C.c_void_p(123)
+    rc = lib.nnp_create(C.byref(p), C.byref(h))
+    assert rc == code
+    assert h.value is None
+    assert len(lib.nnp_last_error()) > 0
+
+
+def test_null_arguments():
+    nnp, lib = _lib()
+    h = C.c_void_p()
+    assert lib.nnp_create(None, C.byref(h)) == nnp.NNP_E_INVALID
+    assert lib.nnp_energy_forces(None, None, None, None, None) == nnp.NNP_E_INVALID
+    assert lib.nnp_energy_forces_f64(None, None, None, None, None) == nnp.NNP_E_INVALID
+    assert lib.nnp_aev(None, None, None, None) == nnp.NNP_E_INVALID
+    assert lib.nnp_set_weights(None, None) == nnp.NNP_E_INVALID
+    assert lib.nnp_num_params(None) == -1
+    assert lib.nnp_aev_dim(None) == -1
+    lib.nnp_destroy(None)
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package never imports, links or reads the oracle."""
+    pkg = os.path.join(ROOT, "paper_2201_08110_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in src.lower() or f == "synth.py", f

@@ -1,0 +1,143 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (per molecule, kcal/mol and kcal/mol/A):
+  FP64 handle     relative 1e-10 on energies and AEVs, 1e-9 on forces
+  FP32 handle     |dE|/atoms <= 1e-4,  force RMSE <= 1e-3   (target accuracy)
+  BF16-MLP handle bounds derived in the tests from bf16's 8-bit mantissa
+"""
+import numpy as np
+import pytest
+
+from paper_2201_08110_amd import synth
+from tests.gpu_util import errors, make_handle, oracle_inputs, to_device, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(torch, hp, w, M, prec, batch, **kw):
+    h = make_handle(hp, w, M, prec, batch, **kw)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    x, sp, off = to_device(torch, batch, dt)
+    E, F = h.energy_forces(x, sp, off)
+    torch.cuda.synchronize()
+    assert h.device_status() == 0
+    return h, E.cpu().numpy(), F.double().cpu().numpy()
+
+
+def _oracle(orc, hp, w, M, prec, batch):
+    xo, wo = oracle_inputs(batch, w, prec)
+    return orc.energy_forces(hp, wo, M, batch.species, xo, batch.mol_offsets)
+
+
+def test_aev_fp64_and_fp32(orc, hp):
+    torch = torch_cuda()
+    b = synth.config_batch(1)
+    w = synth.xavier_weights(1, hp["widths"])
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-6)):
+        h = make_handle(hp, w, 1, prec, b)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        x, sp, off = to_device(torch, b, dt)
+        G = h.aev(x, sp, off).double().cpu().numpy()
+        xo, _ = oracle_inputs(b, w, prec)
+        Go = orc.aev(hp, b.species, xo)
+        scale = np.abs(Go).max()
+        print(prec, "max |dAEV| / max|AEV| =", np.abs(G - Go).max() / scale)
+        np.testing.assert_allclose(G, Go, rtol=tol, atol=tol * scale)
+
+
+def test_energy_forces_fp64_single(orc, hp):
+    """24-atom molecule, one model, everything FP64."""
+    torch = torch_cuda()
+    b = synth.config_batch(1)
+    w = synth.xavier_weights(1, hp["widths"])
+    _, E, F = _run(torch, hp, w, 1, "fp64", b)
+    Eo, Fo = _oracle(orc, hp, w, 1, "fp64", b)
+    print("fp64 dE", E - Eo, "max dF", np.abs(F - Fo).max())
+    np.testing.assert_allclose(E, Eo, rtol=1e-10)
+    np.testing.assert_allclose(F, Fo, rtol=1e-9, atol=1e-9 * np.abs(Fo).max())
+
+
+def test_energy_forces_fp32_ligand(orc, hp):
+    """64-atom ligand over 7 elements, 8-model ensemble, FP32."""
+    torch = torch_cuda()
+    b = synth.config_batch(2)
+    w = synth.xavier_weights(8, hp["widths"])
+    _, E, F = _run(torch, hp, w, 8, "fp32", b)
+    Eo, Fo = _oracle(orc, hp, w, 8, "fp32", b)
+    dE, rmse = errors(E, F, Eo, Fo, b.mol_offsets)
+    print("fp32 ligand: |dE|/atom", dE, "force RMSE", rmse, "E", E, Eo)
+    assert dE.max() <= 1e-4
+    assert rmse.max() <= 1e-3
+
+
+@pytest.mark.parametrize("sizes", [[7, 1, 0, 15, 4, 33], [120, 10, 64, 2, 99]])
+def test_ragged_batch_fp32(orc, hp, sizes):
+    """Ragged batch with an empty molecule, a single atom and several tiles."""
+    torch = torch_cuda()
+    b = synth.random_batch(17 + len(sizes), sizes)
+    w = synth.xavier_weights(8, hp["widths"])
+    _, E, F = _run(torch, hp, w, 8, "fp32", b)
+    Eo, Fo = _oracle(orc, hp, w, 8, "fp32", b)
+    dE, rmse = errors(E, F, Eo, Fo, b.mol_offsets)
+    print("ragged fp32: |dE|/atom", dE, "RMSE", rmse)
+    assert dE.max() <= 1e-4 and rmse.max() <= 1e-3
+    sizes = np.diff(b.mol_offsets)
+    assert np.all(E[sizes == 0] == 0.0)
+
+
+def test_batch_equals_single_molecules(hp):
+    """A molecule's result does not depend on what else is in the batch (FP64)."""
+    torch = torch_cuda()
+    b = synth.random_batch(5, [9, 14, 6])
+    w = synth.xavier_weights(2, hp["widths"])
+    _, E, F = _run(torch, hp, w, 2, "fp64", b)
+    for k in range(b.n_mols):
+        a0, a1 = b.mol_offsets[k], b.mol_offsets[k + 1]
+        one = synth.Batch("one", b.coords[a0:a1], b.species[a0:a1],
+                          np.array([0, a1 - a0], np.int32), 2, "fp64")
+        _, Ek, Fk = _run(torch, hp, w, 2, "fp64", one)
+        np.testing.assert_allclose(E[k], Ek[0], rtol=1e-12)
+        np.testing.assert_allclose(F[a0:a1], Fk, rtol=1e-10, atol=1e-10)
+
+
+def test_bf16_mlp_replicas(orc, hp):
+    """BF16 network GEMMs (FP32 accumulate), FP32 AEV and forces, 16 replicas.
+
+    Bound: operands are rounded to bf16 (relative 2^-9 each); with K-term dot
+    products of random-sign terms the relative error of an atomic energy
+    stays near 2^-9 * sqrt(layers), i.e. ~5e-3 of a typical |e| of ~200
+    kcal/mol -> ~1 kcal/mol/atom; forces likewise ~5e-3 relative.  The test
+    asserts |dE|/atom <= 2 kcal/mol and force RMSE <= 1e-2 * RMS(F).
+    """
+    torch = torch_cuda()
+    b = synth.config_batch(5, n_mols=16)
+    w = synth.xavier_weights(8, hp["widths"])
+    _, E, F = _run(torch, hp, w, 8, "bf16", b)
+    Eo, Fo = _oracle(orc, hp, w, 8, "bf16", b)
+    dE, rmse = errors(E, F, Eo, Fo, b.mol_offsets)
+    frms = np.sqrt(np.mean(Fo ** 2))
+    print("bf16: |dE|/atom max", dE.max(), "median", np.median(dE), "force RMSE max", rmse.max(),
+          "RMS(F)", frms)
+    assert dE.max() <= 2.0
+    assert rmse.max() <= 1e-2 * frms
+
+
+def test_device_flags(hp):
+    torch = torch_cuda()
+    from paper_2201_08110_amd.nnp import NNP, NNP_E_CAPACITY, NNP_E_SPECIES
+    b = synth.random_batch(3, [6, 5])
+    w = synth.xavier_weights(1, hp["widths"])
+    h = NNP(hp, w, 1, "fp32", max_atoms=32, max_mols=4, max_atoms_per_mol=8)
+    x, sp, off = to_device(torch, b, torch.float32)
+    h.energy_forces(x, sp, off)
+    assert h.device_status() == 0
+    bad = sp.clone()
+    bad[3] = 9
+    h.energy_forces(x, bad, off)
+    assert h.device_status() == NNP_E_SPECIES
+    big = synth.random_batch(4, [12])
+    x2, sp2, off2 = to_device(torch, big, torch.float32)
+    h.energy_forces(x2, sp2, off2)
+    assert h.device_status() == NNP_E_CAPACITY
+    h.energy_forces(x, sp, off)
+    assert h.device_status() == 0
