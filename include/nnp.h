@@ -60,6 +60,12 @@ typedef int32_t nnp_status;
 
 #define NNP_MAX_SPECIES     8
 
+/* nnp_batch.flags */
+#define NNP_FLAG_GRAPH      1u  /* replay a captured HIP graph of the whole evaluation while the
+                                   batch shape, every pointer and the stream stay the same
+                                   (first such call runs eagerly and captures); needs a non-null
+                                   stream and is ignored while per-kernel timing is on          */
+
 typedef struct nnp_handle nnp_handle;
 
 /*
@@ -123,7 +129,7 @@ typedef struct {
     const int32_t* mol_offsets;   /* device [n_mols+1], non-decreasing, [0] = 0 */
     const int32_t* species;       /* device [n_atoms], element indices 0..S-1 */
     void* stream;                 /* hipStream_t; NULL = the null stream */
-    uint32_t flags;               /* reserved, 0 */
+    uint32_t flags;               /* 0 or NNP_FLAG_GRAPH */
 } nnp_batch;
 
 /*

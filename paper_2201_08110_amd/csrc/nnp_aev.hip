@@ -5,31 +5,48 @@
 // functions the paper names (Introduction; Methods, software stack), with a
 // cosine cutoff; forces are F = -dV/dx (Methods, Eq. 3) by the exact chain
 // rule through the same terms.  Work mapping (wave64):
-//   * a workgroup owns one molecule chunk; the molecule's coordinates and
-//     element labels are staged in LDS;
-//   * one wavefront per central atom; radial work is spread over
-//     (neighbour, 4-shift group) lanes, angular work over neighbour pairs
-//     {j<k}, enumerated in-wave from the atom's angular neighbour list (no
-//     triple list is materialised);
-//   * the 1008-wide AEV row (forward) or dE/dAEV row (backward) of the atom
-//     lives in the wave's LDS slice; the backward accumulates the molecule's
-//     forces in LDS and adds them to global memory once per workgroup.
+//   * a workgroup owns a chunk of one molecule's atoms; the molecule's
+//     coordinates and element labels are staged in LDS;
+//   * one wavefront per central atom, whose neighbour geometry (vectors,
+//     distances, cutoff values) is cached in the wave's LDS slice;
+//   * neighbour lists are sorted by element (angular neighbours first), so
+//     radial terms of one element and angular terms of one element pair come
+//     in runs: lanes accumulate a run in registers and flush it once into an
+//     LDS row slice they own -- no atomics, bitwise reproducible;
+//   * angular pairs {j<k} are enumerated in-wave from the angular list by a
+//     triangular decode (no triple list is materialised): a lane per pair
+//     computes the 8 distance and 4 angle factors, then lanes per output slot
+//     expand the 32 products;
+//   * the backward recomputes the terms, contracts them with the atom's
+//     dE/dAEV row (LDS, element-pair blocks padded to 33 words against bank
+//     conflicts), accumulates the molecule's forces in LDS and adds them to
+//     global memory once per workgroup.
+#include <algorithm>
+
 #include "nnp_internal.h"
 
 namespace nnp {
 
 // --------------------------------------------------------------------------
-// math in the featuriser's type
-__device__ inline float m_exp(float x) { return expf(x); }
+// math in the featuriser's type.  FP32 uses the hardware transcendental
+// instructions (v_exp_f32 = 2^x, v_log_f32 = log2, v_sin/v_cos_f32 take
+// revolutions, v_sqrt_f32, v_rcp_f32; each within about 1 ulp on the ranges
+// used here: arguments of cos/sin lie in [0, pi]); FP64 uses the accurate
+// library functions.
+__device__ inline float m_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 __device__ inline double m_exp(double x) { return exp(x); }
-__device__ inline float m_cos(float x) { return cosf(x); }
+__device__ inline float m_cos(float x) { return __builtin_amdgcn_cosf(x * 0.159154943091895336f); }
 __device__ inline double m_cos(double x) { return cos(x); }
-__device__ inline float m_sin(float x) { return sinf(x); }
+__device__ inline float m_sin(float x) { return __builtin_amdgcn_sinf(x * 0.159154943091895336f); }
 __device__ inline double m_sin(double x) { return sin(x); }
-__device__ inline float m_sqrt(float x) { return sqrtf(x); }
+__device__ inline float m_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline double m_sqrt(double x) { return sqrt(x); }
+__device__ inline float m_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double m_rcp(double x) { return 1.0 / x; }
 // x^p for x in [0, 1], p > 0 (0^p = 0)
-__device__ inline float m_powu(float x, float p) { return x > 0.f ? exp2f(p * log2f(x)) : 0.f; }
+__device__ inline float m_powu(float x, float p) {
+    return x > 0.f ? __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(x)) : 0.f;
+}
 __device__ inline double m_powu(double x, double p) { return x > 0.0 ? pow(x, p) : 0.0; }
 
 __device__ inline void wave_sync() {
@@ -64,36 +81,30 @@ __host__ __device__ inline void decode_pair(int p, int n, int& j, int& k) {
 }
 
 // ==========================================================================
-// prep: one workgroup of 1024 threads.  Molecule sanity checks, atom ->
-// molecule map, element histogram, padded bucket starts, a stable counting
-// sort of atoms into element buckets (row_of_atom / atom_of_row) and the
-// element of every row tile.
-__global__ __launch_bounds__(1024) void k_prep(int A, int B, int S, int row_tile, int max_apm,
-                                               int Rcap, const int32_t* __restrict__ mol_off,
-                                               const int32_t* __restrict__ species,
-                                               int32_t* __restrict__ row_of_atom,
-                                               int32_t* __restrict__ atom_of_row,
-                                               int32_t* __restrict__ mol_of_atom,
-                                               int32_t* __restrict__ tile_species,
-                                               BucketInfo* __restrict__ info,
-                                               int32_t* __restrict__ flag) {
+// Element bucketing (three kernels): per-block element counts and molecule
+// checks; one small scan of the block counts into padded bucket starts; a
+// stable scatter of every atom to its bucket row.
+__global__ __launch_bounds__(1024) void k_bucket_count(int A, int B, int S, int max_apm,
+                                                       const int32_t* __restrict__ mol_off,
+                                                       const int32_t* __restrict__ species,
+                                                       int32_t* __restrict__ mol_of_atom,
+                                                       int32_t* __restrict__ blk_cnt,
+                                                       int32_t* __restrict__ flag) {
     __shared__ int cnt[kMaxSpecies];
-    __shared__ int base[kMaxSpecies + 1];
-    __shared__ int running[kMaxSpecies];
-    __shared__ int wcnt[16][kMaxSpecies];
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const int tid = threadIdx.x, blk = blockIdx.x;
     if (tid < kMaxSpecies) cnt[tid] = 0;
-    if (tid == 0 && (mol_off[0] != 0 || mol_off[B] != A)) atomicOr(flag, FLAG_CAPACITY);
+    if (blk == 0 && tid == 0 && (mol_off[0] != 0 || mol_off[B] != A)) atomicOr(flag, FLAG_CAPACITY);
     __syncthreads();
-    for (int b = tid; b < B; b += blockDim.x) {
+    const int b = blk * kPrepBlock + tid;
+    if (b < B) {
         int a0 = mol_off[b], a1 = mol_off[b + 1];
-        if (a0 < 0 || a1 < a0 || a1 > A || a1 - a0 > max_apm) {
+        if (a0 < 0 || a1 < a0 || a1 > A || a1 - a0 > max_apm)
             atomicOr(flag, FLAG_CAPACITY);
-            continue;
-        }
-        for (int a = a0; a < a1; ++a) mol_of_atom[a] = b;
+        else
+            for (int a = a0; a < a1; ++a) mol_of_atom[a] = b;
     }
-    for (int a = tid; a < A; a += blockDim.x) {
+    const int a = blk * kPrepBlock + tid;
+    if (a < A) {
         int s = species[a];
         if (s < 0 || s >= S) {
             atomicOr(flag, FLAG_SPECIES);
@@ -102,12 +113,33 @@ __global__ __launch_bounds__(1024) void k_prep(int A, int B, int S, int row_tile
         atomicAdd(&cnt[s], 1);
     }
     __syncthreads();
+    if (tid < kMaxSpecies) blk_cnt[blk * kMaxSpecies + tid] = cnt[tid];
+}
+
+__global__ __launch_bounds__(256) void k_bucket_scan(int nblk, int S, int row_tile, int Rcap,
+                                                     const int32_t* __restrict__ blk_cnt,
+                                                     int32_t* __restrict__ blk_base,
+                                                     int32_t* __restrict__ atom_of_row,
+                                                     int32_t* __restrict__ tile_species,
+                                                     BucketInfo* __restrict__ info,
+                                                     int32_t* __restrict__ flag) {
+    __shared__ int tot[kMaxSpecies];
+    __shared__ int base[kMaxSpecies + 1];
+    const int tid = threadIdx.x;
+    if (tid < S) {   // one thread per element walks the blocks in order
+        int run = 0;
+        for (int k = 0; k < nblk; ++k) {
+            blk_base[k * kMaxSpecies + tid] = run;
+            run += blk_cnt[k * kMaxSpecies + tid];
+        }
+        tot[tid] = run;
+    }
+    __syncthreads();
     if (tid == 0) {
         base[0] = 0;
         for (int s = 0; s < S; ++s) {
-            base[s + 1] = base[s] + ((cnt[s] + row_tile - 1) / row_tile) * row_tile;
-            info->count[s] = cnt[s];
-            running[s] = 0;
+            base[s + 1] = base[s] + ((tot[s] + row_tile - 1) / row_tile) * row_tile;
+            info->count[s] = tot[s];
         }
         for (int s = 0; s <= S; ++s) info->off[s] = base[s];
         int rows = base[S];
@@ -119,6 +151,9 @@ __global__ __launch_bounds__(1024) void k_prep(int A, int B, int S, int row_tile
     }
     __syncthreads();
     const int rows = base[S] <= Rcap ? base[S] : 0;
+    if (tid < S) {   // bucket starts become absolute
+        for (int k = 0; k < nblk; ++k) blk_base[k * kMaxSpecies + tid] += base[tid];
+    }
     for (int t = tid; t < Rcap / row_tile; t += blockDim.x) {
         int r = t * row_tile, s = -1;
         if (r < rows)
@@ -126,185 +161,387 @@ __global__ __launch_bounds__(1024) void k_prep(int A, int B, int S, int row_tile
                 if (base[q] <= r && r < base[q + 1]) s = q;
         tile_species[t] = s;
     }
-    for (int r = tid; r < rows; r += blockDim.x) atom_of_row[r] = -1;
-    __syncthreads();
-    if (rows == 0 && A > 0) return;
+    // padding rows of every bucket
+    for (int s = 0; s < S; ++s)
+        for (int r = base[s] + tot[s] + tid; r < base[s + 1] && r < rows; r += blockDim.x)
+            atom_of_row[r] = -1;
+}
+
+__global__ __launch_bounds__(1024) void k_bucket_scatter(int A, int S, const int32_t* __restrict__ species,
+                                                         const int32_t* __restrict__ blk_base,
+                                                         const BucketInfo* __restrict__ info,
+                                                         int32_t* __restrict__ row_of_atom,
+                                                         int32_t* __restrict__ atom_of_row) {
+    __shared__ int wcnt[kPrepBlock / 64][kMaxSpecies];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, blk = blockIdx.x;
+    const int a = blk * kPrepBlock + tid;
+    int s = -1;
+    if (a < A) {
+        s = species[a];
+        if (s < 0 || s >= S) s = 0;
+    }
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int c0 = 0; c0 < A; c0 += blockDim.x) {
-        int a = c0 + tid;
-        int s = -1;
-        if (a < A) {
-            s = species[a];
-            if (s < 0 || s >= S) s = 0;
-        }
-        int mypre = 0;
-        for (int q = 0; q < S; ++q) {
-            unsigned long long m = __ballot(s == q);
-            if (lane == 0) wcnt[wave][q] = __popcll(m);
-            if (s == q) mypre = __popcll(m & lt);
-        }
-        __syncthreads();
-        if (s >= 0) {
-            int pre = 0;
-            for (int w = 0; w < wave; ++w) pre += wcnt[w][s];
-            int row = base[s] + running[s] + pre + mypre;
-            row_of_atom[a] = row;
-            atom_of_row[row] = a;
-        }
-        __syncthreads();
-        if (tid < S) {
-            int add = 0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) add += wcnt[w][tid];
-            running[tid] += add;
-        }
-        __syncthreads();
+    int mypre = 0;
+    for (int q = 0; q < S; ++q) {
+        unsigned long long m = __ballot(s == q);
+        if (lane == 0) wcnt[wave][q] = __popcll(m);
+        if (s == q) mypre = __popcll(m & lt);
+    }
+    __syncthreads();
+    if (s >= 0 && info->rows > 0) {
+        int pre = 0;
+        for (int w = 0; w < wave; ++w) pre += wcnt[w][s];
+        const int row = blk_base[blk * kMaxSpecies + s] + pre + mypre;
+        row_of_atom[a] = row;
+        atom_of_row[row] = a;
     }
 }
 
 template <typename P>
 hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* species,
                        Work<P>& w, hipStream_t st, const Timer& tm) {
+    const int nblk = std::max((sh.A + kPrepBlock - 1) / kPrepBlock, (sh.B + kPrepBlock - 1) / kPrepBlock);
+    int32_t* blk_cnt = w.blk;
+    int32_t* blk_base = w.blk + (size_t)nblk * kMaxSpecies;
     tm.b("prep", st);
-    hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, sh.A, sh.B, sh.S, sh.row_tile,
-                       sh.max_apm, sh.Rcap, mol_off, species, w.row_of_atom, w.atom_of_row,
-                       w.mol_of_atom, w.tile_species, w.info, w.flag);
+    hipLaunchKernelGGL(k_bucket_count, dim3(nblk), dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S,
+                       sh.max_apm, mol_off, species, w.mol_of_atom, blk_cnt, w.flag);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(256), 0, st, nblk, sh.S, sh.row_tile, sh.Rcap,
+                       blk_cnt, blk_base, w.atom_of_row, w.tile_species, w.info, w.flag);
+    if (sh.A > 0)
+        hipLaunchKernelGGL(k_bucket_scatter, dim3((sh.A + kPrepBlock - 1) / kPrepBlock),
+                           dim3(kPrepBlock), 0, st, sh.A, sh.S, species, blk_base, w.info,
+                           w.row_of_atom, w.atom_of_row);
     tm.e("prep", st);
     return hipGetLastError();
 }
 
+// bump allocator over dynamic LDS (16-byte aligned slices)
+struct LdsBump {
+    char* p;
+    __device__ explicit LdsBump(char* base) : p(base) {}
+    template <typename X> __device__ X* take(size_t n) {
+        X* r = (X*)p;
+        p += (sizeof(X) * n + 15) & ~size_t(15);
+        return r;
+    }
+};
+template <typename X> inline size_t lds_bytes(size_t n) { return (sizeof(X) * n + 15) & ~size_t(15); }
+
 // ==========================================================================
-// neighbour lists: for every atom, the local indices of the atoms of its
-// molecule within rcr, those within rca first.  All pairs of the molecule are
-// tested from LDS (molecules are at most kMaxAtomsPerMol atoms).  Also zeroes
-// the force output.
-constexpr int kChunk = 64;     // central atoms per workgroup
+// Neighbour lists: for every atom, the local indices of the atoms of its
+// molecule within rcr, those within rca first, each of the two runs sorted
+// by element.  A workgroup of one wave owns up to 64 central atoms of one
+// molecule, one lane per atom; the molecule's atoms are staged in LDS in
+// element order (small molecules: every atom is tested) or in (element,
+// cutoff cell) order (large molecules: only the <= 27 cells around the
+// central atom's cell are tested), so the scan emits sorted lists, which are
+// assembled in LDS and written out coalesced.  Also zeroes the forces.
+constexpr int kNbrChunk = 64;  // central atoms per neighbour-list workgroup
+constexpr int kChunk = 16;     // central atoms per AEV / force workgroup
 constexpr int kWaves = 4;
+constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
+
+constexpr int kCellMin = 128;       // molecules larger than this use cutoff cells
+constexpr int kMaxCellsPerDim = 6;  // cells per dimension (cell edge >= rcr)
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_neighbours(int A, int max_apm, int cap, T rca2, T rcr2,
-                                                    const int32_t* __restrict__ mol_off,
-                                                    const T* __restrict__ x, T* __restrict__ F,
-                                                    uint16_t* __restrict__ nbr,
-                                                    int32_t* __restrict__ nbr_cnt,
-                                                    int32_t* __restrict__ flag) {
-    __shared__ T sx[kMaxAtomsPerMol * 3];
+__device__ inline T wave_min(T v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+template <typename T>
+__device__ inline T wave_max(T v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, int cap, T rcr, T rca2,
+                                                   T rcr2, const int32_t* __restrict__ mol_off,
+                                                   const int32_t* __restrict__ species,
+                                                   const T* __restrict__ x, T* __restrict__ F,
+                                                   uint16_t* __restrict__ nbr,
+                                                   int32_t* __restrict__ nbr_cnt,
+                                                   int32_t* __restrict__ flag) {
+    extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x;
     const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
     if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
-    const int i0 = blockIdx.y * kChunk;
+    const int i0 = blockIdx.y * kNbrChunk;
     if (i0 >= n) return;
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    for (int t = tid; t < 3 * n; t += blockDim.x) sx[t] = x[3 * (size_t)a0 + t];
-    __syncthreads();
+    const int lane = lane_id();
+    const bool cells = n > kCellMin;
+    LdsBump lb(smem);
+    T* sx = lb.take<T>(4 * (size_t)max_apm);            // staged atoms: x y z
+    int* sid = lb.take<int>(max_apm);                   // local index of the k-th staged atom
+    uint16_t* lst = lb.take<uint16_t>((size_t)kNbrChunk * cap);
+    int* kstart = nullptr;                              // [nkeys+1] bucket starts (cells)
+    int* kcur = nullptr;                                // [nkeys]   scatter cursors
+    int* akey = nullptr;                                // [max_apm] key of every atom
+    if (max_apm > kCellMin) {
+        kstart = lb.take<int>(kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim + 1);
+        kcur = lb.take<int>(kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim);
+        akey = lb.take<int>(max_apm);
+    }
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int i1 = min(i0 + kChunk, n);
-    for (int il = i0 + wave; il < i1; il += kWaves) {
-        const size_t ai = (size_t)a0 + il;
-        if (F && lane < 3) F[3 * ai + lane] = T(0);
-        const T xi0 = sx[3 * il], xi1 = sx[3 * il + 1], xi2 = sx[3 * il + 2];
-        uint16_t* out = nbr + ai * cap;
-        int cntv = 0, nang = 0;
-        for (int pass = 0; pass < 2; ++pass) {
+
+    // ---- staging.  Small molecules: atoms in element order (one bucket per
+    // element).  Large molecules: atoms in (element, cell) order over a grid
+    // of cutoff cells with edge >= rcr, so a central atom scans <= 27 cells.
+    int nc0 = 1, nc1 = 1, nc2 = 1;
+    T lo0 = 0, lo1 = 0, lo2 = 0, ih0 = 0, ih1 = 0, ih2 = 0;
+    if (!cells) {
+        int base = 0;
+        for (int q = 0; q < S; ++q) {
             for (int j0 = 0; j0 < n; j0 += 64) {
-                int j = j0 + lane;
-                bool keep = false;
-                if (j < n && j != il) {
-                    T d0 = sx[3 * j] - xi0, d1 = sx[3 * j + 1] - xi1, d2 = sx[3 * j + 2] - xi2;
-                    T r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                    keep = pass == 0 ? (r2 < rca2) : (r2 >= rca2 && r2 < rcr2);
+                const int j = j0 + lane;
+                int s = -1;
+                if (j < n) {
+                    s = species[a0 + j];
+                    s = (s < 0 || s >= S) ? 0 : s;
                 }
-                unsigned long long m = __ballot(keep);
-                int pos = cntv + __popcll(m & lt);
-                if (keep && pos < cap) out[pos] = (uint16_t)j;
-                cntv += __popcll(m);
+                const unsigned long long m = __ballot(s == q);
+                if (s == q) {
+                    const int pos = base + __popcll(m & lt);
+                    sid[pos] = j;
+                    sx[4 * pos + 0] = x[3 * ((size_t)a0 + j) + 0];
+                    sx[4 * pos + 1] = x[3 * ((size_t)a0 + j) + 1];
+                    sx[4 * pos + 2] = x[3 * ((size_t)a0 + j) + 2];
+                }
+                base += __popcll(m);
             }
-            if (pass == 0) nang = cntv;
         }
-        if (lane == 0) {
-            int nall = cntv;
-            if (nall > cap) {
-                atomicOr(flag, FLAG_CAPACITY);
-                nall = cap;
-                nang = nang > cap ? cap : nang;
-            }
-            nbr_cnt[ai] = nang | (nall << 16);
+    } else {
+        T mn0 = T(1e30), mn1 = T(1e30), mn2 = T(1e30), mx0 = T(-1e30), mx1 = T(-1e30), mx2 = T(-1e30);
+        for (int j = lane; j < n; j += 64) {
+            const T* p = x + 3 * ((size_t)a0 + j);
+            mn0 = fmin(mn0, p[0]); mx0 = fmax(mx0, p[0]);
+            mn1 = fmin(mn1, p[1]); mx1 = fmax(mx1, p[1]);
+            mn2 = fmin(mn2, p[2]); mx2 = fmax(mx2, p[2]);
+        }
+        lo0 = wave_min(mn0); lo1 = wave_min(mn1); lo2 = wave_min(mn2);
+        const T e0 = wave_max(mx0) - lo0, e1 = wave_max(mx1) - lo1, e2 = wave_max(mx2) - lo2;
+        nc0 = min(max((int)(e0 / rcr), 1), kMaxCellsPerDim);
+        nc1 = min(max((int)(e1 / rcr), 1), kMaxCellsPerDim);
+        nc2 = min(max((int)(e2 / rcr), 1), kMaxCellsPerDim);
+        ih0 = e0 > T(0) ? T(nc0) / e0 : T(0);
+        ih1 = e1 > T(0) ? T(nc1) / e1 : T(0);
+        ih2 = e2 > T(0) ? T(nc2) / e2 : T(0);
+        const int ncell = nc0 * nc1 * nc2, nkeys = S * ncell;
+        for (int k = lane; k <= nkeys; k += 64) kstart[k] = 0;
+        wave_sync();
+        for (int j = lane; j < n; j += 64) {
+            int s = species[a0 + j];
+            s = (s < 0 || s >= S) ? 0 : s;
+            const T* p = x + 3 * ((size_t)a0 + j);
+            const int c0 = min((int)((p[0] - lo0) * ih0), nc0 - 1);
+            const int c1 = min((int)((p[1] - lo1) * ih1), nc1 - 1);
+            const int c2 = min((int)((p[2] - lo2) * ih2), nc2 - 1);
+            const int key = s * ncell + (c2 * nc1 + c1) * nc0 + c0;
+            akey[j] = key;
+            atomicAdd(&kstart[key + 1], 1);
+        }
+        wave_sync();
+        // inclusive scan of the counts (lane-blocked, then across lanes)
+        const int per = (nkeys + 64) / 64;
+        const int k0 = lane * per, k1 = min(k0 + per, nkeys + 1);
+        int run = 0;
+        for (int k = k0; k < k1; ++k) run += kstart[k];
+        int pre = run;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(pre, o);
+            if (lane >= o) pre += v;
+        }
+        pre -= run;
+        for (int k = k0; k < k1; ++k) {
+            pre += kstart[k];
+            kstart[k] = pre;
+        }
+        wave_sync();
+        for (int k = lane; k < nkeys; k += 64) kcur[k] = kstart[k];
+        wave_sync();
+        for (int j = lane; j < n; j += 64) {
+            const int pos = atomicAdd(&kcur[akey[j]], 1);
+            sid[pos] = j;
+            sx[4 * pos + 0] = x[3 * ((size_t)a0 + j) + 0];
+            sx[4 * pos + 1] = x[3 * ((size_t)a0 + j) + 1];
+            sx[4 * pos + 2] = x[3 * ((size_t)a0 + j) + 2];
         }
     }
+    wave_sync();
+
+    // ---- one lane per central atom: scan the staged atoms in order
+    const int il = i0 + lane;
+    const bool act = il < n;
+    T xi0 = 0, xi1 = 0, xi2 = 0;
+    if (act) {
+        xi0 = x[3 * ((size_t)a0 + il) + 0];
+        xi1 = x[3 * ((size_t)a0 + il) + 1];
+        xi2 = x[3 * ((size_t)a0 + il) + 2];
+        if (F) {
+            F[3 * ((size_t)a0 + il) + 0] = T(0);
+            F[3 * ((size_t)a0 + il) + 1] = T(0);
+            F[3 * ((size_t)a0 + il) + 2] = T(0);
+        }
+    }
+    uint16_t* my = lst + (size_t)lane * cap;
+    int cnt = 0, nang = 0;
+#define NNP_TEST(k)                                                                            \
+    {                                                                                          \
+        const int j_ = sid[k];                                                                 \
+        const T d0 = sx[4 * (k)] - xi0, d1 = sx[4 * (k) + 1] - xi1, d2 = sx[4 * (k) + 2] - xi2; \
+        const T r2 = d0 * d0 + d1 * d1 + d2 * d2;                                             \
+        if (act && j_ != il && (pass == 0 ? (r2 < rca2) : (r2 >= rca2 && r2 < rcr2))) {        \
+            if (cnt < cap) my[cnt] = (uint16_t)j_;                                             \
+            ++cnt;                                                                             \
+        }                                                                                      \
+    }
+    if (!cells) {
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int k = 0; k < n; ++k) NNP_TEST(k)
+            if (pass == 0) nang = cnt;
+        }
+    } else {
+        const int ncell = nc0 * nc1 * nc2;
+        const int c0 = act ? min((int)((xi0 - lo0) * ih0), nc0 - 1) : 0;
+        const int c1 = act ? min((int)((xi1 - lo1) * ih1), nc1 - 1) : 0;
+        const int c2 = act ? min((int)((xi2 - lo2) * ih2), nc2 - 1) : 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int q = 0; q < S; ++q)
+                for (int z = max(c2 - 1, 0); z <= min(c2 + 1, nc2 - 1); ++z)
+                    for (int y = max(c1 - 1, 0); y <= min(c1 + 1, nc1 - 1); ++y)
+                        for (int xx = max(c0 - 1, 0); xx <= min(c0 + 1, nc0 - 1); ++xx) {
+                            const int key = q * ncell + (z * nc1 + y) * nc0 + xx;
+                            for (int k = kstart[key]; k < kstart[key + 1]; ++k) NNP_TEST(k)
+                        }
+            if (pass == 0) nang = cnt;
+        }
+    }
+#undef NNP_TEST
+    if (act) {
+        int nall = cnt;
+        if (nall > cap) {
+            atomicOr(flag, FLAG_CAPACITY);
+            nall = cap;
+            nang = nang > cap ? cap : nang;
+        }
+        nbr_cnt[(size_t)a0 + il] = nang | (nall << 16);
+    }
+    wave_sync();
+    // coalesced copy of the chunk's lists
+    const int na = min(kNbrChunk, n - i0);
+    uint16_t* dst = nbr + ((size_t)a0 + i0) * cap;
+    for (int e = lane; e < na * cap; e += 64) dst[e] = lst[e];
 }
 
 template <typename P>
 hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
-                             const int32_t* mol_off, const typename P::T* x, typename P::T* F,
-                             Work<P>& w, hipStream_t st, const Timer& tm) {
+                             const int32_t* mol_off, const int32_t* species,
+                             const typename P::T* x, typename P::T* F, Work<P>& w, hipStream_t st,
+                             const Timer& tm) {
     typedef typename P::T T;
-    dim3 grid(sh.B, (sh.max_apm + kChunk - 1) / kChunk);
+    dim3 grid(sh.B, (sh.max_apm + kNbrChunk - 1) / kNbrChunk);
+    const int nkeys = kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim;
+    size_t lds = lds_bytes<T>(4 * (size_t)sh.max_apm) + lds_bytes<int>(sh.max_apm) +
+                 lds_bytes<uint16_t>((size_t)kNbrChunk * sh.cap_nbr);
+    if (sh.max_apm > kCellMin)
+        lds += lds_bytes<int>(nkeys + 1) + lds_bytes<int>(nkeys) + lds_bytes<int>(sh.max_apm);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    hipError_t e = ensure_lds((const void*)k_neighbours<T>, lds);
+    if (e != hipSuccess) return e;
     tm.b("neighbours", st);
-    hipLaunchKernelGGL(k_neighbours<T>, grid, dim3(256), 0, st, sh.A, sh.max_apm, sh.cap_nbr, c.rca2,
-                       c.rcr2, mol_off, x, F, w.nbr, w.nbr_cnt, w.flag);
+    hipLaunchKernelGGL(k_neighbours<T>, grid, dim3(64), lds, st, sh.A, sh.S, sh.max_apm,
+                       sh.cap_nbr, c.rcr, c.rca2, c.rcr2, mol_off, species, x, F, w.nbr,
+                       w.nbr_cnt, w.flag);
     tm.e("neighbours", st);
     return hipGetLastError();
 }
 
 // ==========================================================================
-// shared-memory layout of the AEV kernels (dynamic LDS):
-//   sx    [max_apm*3] T   molecule coordinates
-//   ssp   [max_apm]  int  molecule element labels
-//   sF    [max_apm*3] T   force accumulators (backward only)
-//   per wave: row [Dp] T, nb [cap*4] T (dx, dy, dz, r), nsp [cap] int
-//             (element), nid [cap] int (local index)
-template <typename T> struct AevSmem {
-    T* sx;
-    int* ssp;
-    T* sF;
-    T* row;
-    T* nb;
-    int* nsp;
-    int* nid;
-    __device__ AevSmem(char* base, int max_apm, int Dp, int cap, int wave, bool forces) {
-        size_t o = 0;
-        sx = (T*)(base + o);   o += sizeof(T) * 3 * max_apm;
-        sF = (T*)(base + o);   o += forces ? sizeof(T) * 3 * max_apm : 0;
-        o = (o + 15) & ~size_t(15);
-        row = (T*)(base + o) + (size_t)wave * Dp;   o += sizeof(T) * (size_t)kWaves * Dp;
-        nb = (T*)(base + o) + (size_t)wave * cap * 4; o += sizeof(T) * (size_t)kWaves * cap * 4;
-        ssp = (int*)(base + o);  o += sizeof(int) * max_apm;
-        nsp = (int*)(base + o) + (size_t)wave * cap;  o += sizeof(int) * (size_t)kWaves * cap;
-        nid = (int*)(base + o) + (size_t)wave * cap;
+// Shared set-up of the AEV and force kernels: the molecule's coordinates and
+// elements, and the chunk's neighbour counts, bucket rows and neighbour lists,
+// all staged in LDS once per workgroup.
+constexpr int kNbStride = 8;   // dx dy dz r fc_r dfc_r fc_a dfc_a
+
+template <typename T> struct ChunkStage {
+    T* sx;            // [max_apm*3]
+    int* ssp;         // [max_apm]
+    int* ccnt;        // [kChunk]      packed neighbour counts
+    int* crow;        // [kChunk]      bucket rows
+    uint16_t* clst;   // [kChunk*cap]  neighbour lists
+    __device__ void take(LdsBump& lb, int max_apm, int cap) {
+        sx = lb.take<T>(3 * (size_t)max_apm);
+        ssp = lb.take<int>(max_apm);
+        ccnt = lb.take<int>(kChunk);
+        crow = lb.take<int>(kChunk);
+        clst = lb.take<uint16_t>((size_t)kChunk * cap);
     }
-    static size_t bytes(int max_apm, int Dp, int cap, bool forces) {
-        size_t o = sizeof(T) * 3 * max_apm + (forces ? sizeof(T) * 3 * max_apm : 0);
-        o = (o + 15) & ~size_t(15);
-        o += sizeof(T) * (size_t)kWaves * Dp + sizeof(T) * (size_t)kWaves * cap * 4;
-        o += sizeof(int) * max_apm + 2 * sizeof(int) * (size_t)kWaves * cap;
-        return o;
+    static size_t bytes(int max_apm, int cap) {
+        return lds_bytes<T>(3 * (size_t)max_apm) + lds_bytes<int>(max_apm) +
+               2 * lds_bytes<int>(kChunk) + lds_bytes<uint16_t>((size_t)kChunk * cap);
+    }
+    __device__ void load(const T* __restrict__ x, const int32_t* __restrict__ species, int S,
+                         int a0, int n, int i0, int nc, int cap,
+                         const uint16_t* __restrict__ nbr, const int32_t* __restrict__ nbr_cnt,
+                         const int32_t* __restrict__ row_of_atom) {
+        const int tid = threadIdx.x;
+        for (int t = tid; t < 3 * n; t += blockDim.x) sx[t] = x[3 * (size_t)a0 + t];
+        for (int t = tid; t < n; t += blockDim.x) {
+            int s = species[a0 + t];
+            ssp[t] = (s < 0 || s >= S) ? 0 : s;
+        }
+        for (int t = tid; t < nc; t += blockDim.x) {
+            ccnt[t] = nbr_cnt[(size_t)a0 + i0 + t];
+            crow[t] = row_of_atom[(size_t)a0 + i0 + t];
+        }
+        const uint16_t* src = nbr + ((size_t)a0 + i0) * cap;
+        for (int e = tid; e < nc * cap; e += blockDim.x) clst[e] = src[e];
     }
 };
 
-// neighbour geometry of atom il into the wave's cache; returns n_ang, n_all
 template <typename T>
-__device__ inline void load_neighbours(const AevSmem<T>& sm, const uint16_t* __restrict__ nb_list,
-                                       int cnt, int il, int& nang, int& nall) {
-    nang = cnt & 0xffff;
-    nall = cnt >> 16;
-    const T xi0 = sm.sx[3 * il], xi1 = sm.sx[3 * il + 1], xi2 = sm.sx[3 * il + 2];
+__device__ inline void load_neighbours(const AevConst<T>& c, const T* __restrict__ sx,
+                                       const int* __restrict__ ssp,
+                                       const uint16_t* __restrict__ nb_list, int nang, int nall,
+                                       int il, T* __restrict__ nb, int* __restrict__ nsp,
+                                       int* __restrict__ nid) {
+    const T xi0 = sx[3 * il], xi1 = sx[3 * il + 1], xi2 = sx[3 * il + 2];
     for (int t = lane_id(); t < nall; t += 64) {
-        int j = nb_list[t];
-        T d0 = sm.sx[3 * j] - xi0, d1 = sm.sx[3 * j + 1] - xi1, d2 = sm.sx[3 * j + 2] - xi2;
-        sm.nb[4 * t + 0] = d0;
-        sm.nb[4 * t + 1] = d1;
-        sm.nb[4 * t + 2] = d2;
-        sm.nb[4 * t + 3] = m_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        sm.nsp[t] = sm.ssp[j];
-        sm.nid[t] = j;
+        const int j = nb_list[t];
+        const T d0 = sx[3 * j] - xi0, d1 = sx[3 * j + 1] - xi1, d2 = sx[3 * j + 2] - xi2;
+        const T r = m_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        T* e = nb + kNbStride * t;
+        e[0] = d0;
+        e[1] = d1;
+        e[2] = d2;
+        e[3] = r;
+        e[4] = T(0.5) * m_cos(c.pi_rcr * r) + T(0.5);
+        e[5] = -T(0.5) * c.pi_rcr * m_sin(c.pi_rcr * r);
+        if (t < nang) {
+            e[6] = T(0.5) * m_cos(c.pi_rca * r) + T(0.5);
+            e[7] = -T(0.5) * c.pi_rca * m_sin(c.pi_rca * r);
+        } else {
+            e[6] = T(0);
+            e[7] = T(0);
+        }
+        nsp[t] = ssp[j];
+        nid[t] = j;
     }
 }
 
 // --------------------------------------------------------------------------
 // AEV forward.  Output row of atom a goes to G[row_of_atom[a]] in the GEMM
 // operand type; optionally also to aev_out[a] (atom order, unpadded).
+//
+// Per wave LDS: neighbour cache [cap][8] T + elements + indices [cap]; the
+// atom's AEV row [Dp] T; pair factors [64][NA + NZ] T + blocks [64].
+// Lanes accumulate runs of equal element (radial) or element pair (angular)
+// in registers and flush a run with one LDS atomic add, so only run
+// boundaries touch shared memory.
 template <typename P, int NZ>
-__global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, int max_apm, int cap,
-                                             const int32_t* __restrict__ mol_off,
+__global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
+                                             int cap, const int32_t* __restrict__ mol_off,
                                              const int32_t* __restrict__ species,
                                              const typename P::T* __restrict__ x,
                                              const uint16_t* __restrict__ nbr,
@@ -314,82 +551,145 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
                                              typename P::T* __restrict__ aev_out) {
     typedef typename P::T T;
     typedef typename P::TS TS;
+    constexpr int NA = kNAZ / NZ;
+    constexpr int PF = NA + NZ;
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x;
     const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
     if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
     const int i0 = blockIdx.y * kChunk;
     if (i0 >= n) return;
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    AevSmem<T> sm(smem, max_apm, c.Dp, cap, wave, false);
-    for (int t = tid; t < 3 * n; t += blockDim.x) sm.sx[t] = x[3 * (size_t)a0 + t];
-    for (int t = tid; t < n; t += blockDim.x) {
-        int s = species[a0 + t];
-        sm.ssp[t] = (s < 0 || s >= c.S) ? 0 : s;
-    }
+    const int nc = min(kChunk, n - i0);
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
+    const int S = c.S, RL = kNR * S;
+
+    LdsBump lb(smem);
+    ChunkStage<T> cs;
+    cs.take(lb, max_apm, cap);
+    T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
+    int* nsp = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
+    int* nid = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
+    T* row = lb.take<T>((size_t)nw * c.Dp) + (size_t)wave * c.Dp;
+    T* pf = lb.take<T>((size_t)nw * 64 * PF) + (size_t)wave * 64 * PF;
+    int* pb = lb.take<int>((size_t)nw * 64) + (size_t)wave * 64;
+    cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, row_of_atom);
     __syncthreads();
-    const int radial_len = c.S * kNR;
-    const int i1 = min(i0 + kChunk, n);
-    for (int il = i0 + wave; il < i1; il += kWaves) {
-        const size_t ai = (size_t)a0 + il;
-        int nang, nall;
-        load_neighbours(sm, nbr + ai * cap, nbr_cnt[ai], il, nang, nall);
-        for (int e = lane; e < c.Dp; e += 64) sm.row[e] = T(0);
+
+    for (int ic = wave; ic < nc; ic += nw) {
+        const int il = i0 + ic;
+        const int cnt = cs.ccnt[ic];
+        const int nang = cnt & 0xffff, nall = cnt >> 16;
+        load_neighbours(c, cs.sx, cs.ssp, cs.clst + (size_t)ic * cap, nang, nall, il, nb, nsp, nid);
+        for (int e = lane; e < c.Dp; e += 64) row[e] = T(0);
         wave_sync();
-        // radial: lane per (neighbour, group of 4 shifts)
-        for (int it = lane; it < 4 * nall; it += 64) {
-            const int t = it >> 2, q = it & 3;
-            const T r = sm.nb[4 * t + 3];
-            const T fc = T(0.5) * m_cos(c.pi_rcr * r) + T(0.5);
-            T* dst = sm.row + kNR * sm.nsp[t] + 4 * q;
+
+        // ---- radial: lane (group g, shift k); neighbours t = g, g+4, ...
+        {
+            const int g = lane >> 4, k = lane & 15;
+            const T sk = c.shf_r[k];
+            T acc = T(0);
+            int cur = -1;
+            for (int t0 = g; t0 < nall; t0 += 16) {
+                int sv[4];
+                T vv[4];
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const T d = r - c.shf_r[4 * q + kk];
-                lds_add(dst + kk, c.radial_pref * m_exp(-c.eta_r * d * d) * fc);
+                for (int u = 0; u < 4; ++u) {
+                    const int t = t0 + 4 * u;
+                    sv[u] = t < nall ? nsp[t] : -2;
+                    const T d = (t < nall ? nb[kNbStride * t + 3] : T(0)) - sk;
+                    vv[u] = t < nall ? c.radial_pref * m_exp(-c.eta_r * d * d) * nb[kNbStride * t + 4]
+                                     : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (sv[u] >= 0 && sv[u] != cur) {
+                        if (cur >= 0) lds_add(row + kNR * cur + k, acc);
+                        acc = T(0);
+                        cur = sv[u];
+                    }
+                    acc += vv[u];
+                }
             }
+            if (cur >= 0) lds_add(row + kNR * cur + k, acc);
         }
-        // angular: lane per unordered neighbour pair {j<k} of the angular list
+
+        // ---- angular, in batches of 64 neighbour pairs
         const int npair = nang * (nang - 1) / 2;
-        for (int p = lane; p < npair; p += 64) {
-            int j, k;
-            decode_pair(p, nang, j, k);
-            const T dj0 = sm.nb[4 * j], dj1 = sm.nb[4 * j + 1], dj2 = sm.nb[4 * j + 2];
-            const T rj = sm.nb[4 * j + 3];
-            const T dk0 = sm.nb[4 * k], dk1 = sm.nb[4 * k + 1], dk2 = sm.nb[4 * k + 2];
-            const T rk = sm.nb[4 * k + 3];
-            T cs = (dj0 * dk0 + dj1 * dk1 + dj2 * dk2) / (rj * rk);
-            cs = cs > T(1) ? T(1) : (cs < T(-1) ? T(-1) : cs);
-            const T cp = c.angle_scale * cs;
-            const T sn = m_sqrt(T(1) - cp * cp);
-            const T fcc = (T(0.5) * m_cos(c.pi_rca * rj) + T(0.5)) *
-                          (T(0.5) * m_cos(c.pi_rca * rk) + T(0.5));
-            const T rm = T(0.5) * (rj + rk);
-            constexpr int NA = kNAZ / NZ;
-            T fz[NZ];
-            T fa[NA];
+        const int h = lane >> 5, q = lane & 31, qa = q / NZ, qz = q % NZ;
+        T acc = T(0);
+        int cur = -1;
+        for (int p0 = 0; p0 < npair; p0 += 64) {
+            const int nbat = min(64, npair - p0);
+            // phase A: one lane per pair computes the 12 factors
+            if (lane < nbat) {
+                int j, k;
+                decode_pair(p0 + lane, nang, j, k);
+                const T* ej = nb + kNbStride * j;
+                const T* ek = nb + kNbStride * k;
+                const T rj = ej[3], rk = ek[3];
+                T cs_ = (ej[0] * ek[0] + ej[1] * ek[1] + ej[2] * ek[2]) * m_rcp(rj * rk);
+                cs_ = cs_ > T(1) ? T(1) : (cs_ < T(-1) ? T(-1) : cs_);
+                const T cp = c.angle_scale * cs_;
+                const T sn = m_sqrt(T(1) - cp * cp);
+                const T fcc = ej[6] * ek[6];
+                const T rm = T(0.5) * (rj + rk);
+                T* f = pf + PF * lane;
 #pragma unroll
-            for (int z = 0; z < NZ; ++z) {
-                const T cz = cp * c.cos_z[z] + sn * c.sin_z[z];
-                fz[z] = T(2) * m_powu(T(0.5) * (T(1) + cz), c.zeta);
+                for (int a = 0; a < NA; ++a) {
+                    const T d = rm - c.shf_a[a];
+                    f[a] = m_exp(-c.eta_a * d * d) * fcc;
+                }
+#pragma unroll
+                for (int z = 0; z < NZ; ++z) {
+                    const T cz = cp * c.cos_z[z] + sn * c.sin_z[z];
+                    f[NA + z] = T(2) * m_powu(T(0.5) * (T(1) + cz), c.zeta);
+                }
+                pb[lane] = RL + kNAZ * pair_index(nsp[j], nsp[k], S);
             }
+            wave_sync();
+            // phase B: lane (half h, slot q) expands pairs t = h, h+2, ...
+            for (int t0 = h; t0 < nbat; t0 += 8) {
+                int bk[4];
+                T vv[4];
 #pragma unroll
-            for (int a = 0; a < NA; ++a) {
-                const T d = rm - c.shf_a[a];
-                fa[a] = m_exp(-c.eta_a * d * d) * fcc;
+                for (int u = 0; u < 4; ++u) {
+                    const int t = t0 + 2 * u;
+                    bk[u] = t < nbat ? pb[t] : -2;
+                    vv[u] = t < nbat ? pf[PF * t + qa] * pf[PF * t + NA + qz] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (bk[u] >= 0 && bk[u] != cur) {
+                        if (cur >= 0) lds_add(row + cur + q, acc);
+                        acc = T(0);
+                        cur = bk[u];
+                    }
+                    acc += vv[u];
+                }
             }
-            T* dst = sm.row + radial_len + kNAZ * pair_index(sm.nsp[j], sm.nsp[k], c.S);
-#pragma unroll
-            for (int a = 0; a < NA; ++a)
-#pragma unroll
-                for (int z = 0; z < NZ; ++z) lds_add(dst + NZ * a + z, fz[z] * fa[a]);
+            wave_sync();
         }
+        if (cur >= 0) lds_add(row + cur + q, acc);
         wave_sync();
-        const size_t row = (size_t)row_of_atom[ai];
-        for (int e = lane; e < c.Dp; e += 64) G[row * c.Dp + e] = Store<TS>::st(sm.row[e]);
-        if (aev_out)
-            for (int e = lane; e < c.D; e += 64) aev_out[ai * c.D + e] = sm.row[e];
+
+        // ---- write the row (zero padding beyond D)
+        const size_t grow = (size_t)cs.crow[ic];
+        const size_t ai = (size_t)a0 + il;
+        for (int e = lane; e < c.Dp; e += 64) {
+            const T v = row[e];
+            G[grow * c.Dp + e] = Store<TS>::st(v);
+            if (aev_out && e < c.D) aev_out[ai * c.D + e] = v;
+        }
         wave_sync();
     }
+}
+
+template <typename T>
+static size_t aev_lds(int max_apm, int cap, int Dp, int NZ, int nw) {
+    const int PF = kNAZ / NZ + NZ;
+    return ChunkStage<T>::bytes(max_apm, cap) + lds_bytes<T>((size_t)nw * cap * kNbStride) +
+           2 * lds_bytes<int>((size_t)nw * cap) + lds_bytes<T>((size_t)nw * Dp) +
+           lds_bytes<T>((size_t)nw * 64 * PF) + lds_bytes<int>((size_t)nw * 64);
 }
 
 template <typename P>
@@ -398,15 +698,208 @@ hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const i
                       typename P::T* aev_out, hipStream_t st, const Timer& tm) {
     typedef typename P::T T;
     dim3 grid(sh.B, (sh.max_apm + kChunk - 1) / kChunk);
-    size_t lds = AevSmem<T>::bytes(sh.max_apm, c.Dp, sh.cap_nbr, false);
+    int nw = kWaves;
+    size_t lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw);
+    while (lds > kMaxLds && nw > 1) lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw /= 2);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = c.nZ == 4 ? k_aev<P, 4> : k_aev<P, 8>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("aev", st);
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, c, sh.A, sh.max_apm, sh.cap_nbr, mol_off,
-                       species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.G, aev_out);
+    hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.cap_nbr,
+                       mol_off, species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.G, aev_out);
     tm.e("aev", st);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// AEV tangent (JVP): Gdot_i = sum_j dG_i/dx_j . v_j for a coordinate tangent
+// v (the force-loss cotangent of training), rows written to Gd in bucket
+// order.  Same structure as the forward: per pair the distance factors P_a,
+// Q_a and the angle factors fz_z, dfz_z/dc are formed once, and
+//   Gdot[a, z] += fz_z P_a + dfz_z Q_a,
+//   P_a = A'_a rmdot F + A_a Fdot,  Q_a = A_a F cdot,
+// with A_a the distance Gaussian, F = fc_j fc_k and the dotted quantities
+// their rates along v.
+template <typename P, int NZ>
+__global__ __launch_bounds__(256) void k_aev_jvp(AevConst<typename P::T> c, int A, int max_apm,
+                                                 int cap, const int32_t* __restrict__ mol_off,
+                                                 const int32_t* __restrict__ species,
+                                                 const typename P::T* __restrict__ x,
+                                                 const typename P::T* __restrict__ v,
+                                                 const uint16_t* __restrict__ nbr,
+                                                 const int32_t* __restrict__ nbr_cnt,
+                                                 const int32_t* __restrict__ row_of_atom,
+                                                 typename P::TS* __restrict__ Gd) {
+    typedef typename P::T T;
+    typedef typename P::TS TS;
+    constexpr int NA = kNAZ / NZ;
+    constexpr int PF = 2 * NA + 2 * NZ;       // P[NA] Q[NA] fz[NZ] dfz[NZ]
+    constexpr int TS_ = 4;                     // per neighbour: v_j - v_i (3), rdot
+    extern __shared__ __align__(16) char smem[];
+    const int b = blockIdx.x;
+    const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
+    if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
+    const int i0 = blockIdx.y * kChunk;
+    if (i0 >= n) return;
+    const int nc = min(kChunk, n - i0);
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
+    const int S = c.S, RL = kNR * S;
+
+    LdsBump lb(smem);
+    ChunkStage<T> cs;
+    cs.take(lb, max_apm, cap);
+    T* sv = lb.take<T>(3 * (size_t)max_apm);
+    T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
+    T* nt = lb.take<T>((size_t)nw * cap * TS_) + (size_t)wave * cap * TS_;
+    int* nsp = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
+    int* nid = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
+    T* row = lb.take<T>((size_t)nw * c.Dp) + (size_t)wave * c.Dp;
+    T* pf = lb.take<T>((size_t)nw * 64 * PF) + (size_t)wave * 64 * PF;
+    int* pb = lb.take<int>((size_t)nw * 64) + (size_t)wave * 64;
+    cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, row_of_atom);
+    for (int t = tid; t < 3 * n; t += blockDim.x) sv[t] = v[3 * (size_t)a0 + t];
+    __syncthreads();
+
+    for (int ic = wave; ic < nc; ic += nw) {
+        const int il = i0 + ic;
+        const int cnt = cs.ccnt[ic];
+        const int nang = cnt & 0xffff, nall = cnt >> 16;
+        load_neighbours(c, cs.sx, cs.ssp, cs.clst + (size_t)ic * cap, nang, nall, il, nb, nsp, nid);
+        wave_sync();
+        for (int t = lane; t < nall; t += 64) {
+            const int j = nid[t];
+            const T* e = nb + kNbStride * t;
+            const T ir = m_rcp(e[3]);
+            const T w0 = sv[3 * j] - sv[3 * il], w1 = sv[3 * j + 1] - sv[3 * il + 1],
+                    w2 = sv[3 * j + 2] - sv[3 * il + 2];
+            nt[TS_ * t + 0] = w0;
+            nt[TS_ * t + 1] = w1;
+            nt[TS_ * t + 2] = w2;
+            nt[TS_ * t + 3] = (e[0] * w0 + e[1] * w1 + e[2] * w2) * ir;   // rdot = u . (v_j - v_i)
+        }
+        for (int e = lane; e < c.Dp; e += 64) row[e] = T(0);
+        wave_sync();
+
+        // ---- radial: d/dt of pref exp(-eta (r - s_k)^2) fc(r) = (d term/dr) rdot
+        {
+            const int g = lane >> 4, k = lane & 15;
+            const T sk = c.shf_r[k];
+            T acc = T(0);
+            int cur = -1;
+            for (int t = g; t < nall; t += 4) {
+                const int sp = nsp[t];
+                if (sp != cur) {
+                    if (cur >= 0) lds_add(row + kNR * cur + k, acc);
+                    acc = T(0);
+                    cur = sp;
+                }
+                const T* e = nb + kNbStride * t;
+                const T d = e[3] - sk;
+                const T ex = c.radial_pref * m_exp(-c.eta_r * d * d);
+                acc += ex * (T(-2) * c.eta_r * d * e[4] + e[5]) * nt[TS_ * t + 3];
+            }
+            if (cur >= 0) lds_add(row + kNR * cur + k, acc);
+        }
+
+        // ---- angular
+        const int npair = nang * (nang - 1) / 2;
+        const int h = lane >> 5, q = lane & 31, qa = q / NZ, qz = q % NZ;
+        T acc = T(0);
+        int cur = -1;
+        for (int p0 = 0; p0 < npair; p0 += 64) {
+            const int nbat = min(64, npair - p0);
+            if (lane < nbat) {
+                int j, k;
+                decode_pair(p0 + lane, nang, j, k);
+                const T* ej = nb + kNbStride * j;
+                const T* ek = nb + kNbStride * k;
+                const T rj = ej[3], rk = ek[3];
+                const T ij = m_rcp(rj), ik = m_rcp(rk);
+                const T uj0 = ej[0] * ij, uj1 = ej[1] * ij, uj2 = ej[2] * ij;
+                const T uk0 = ek[0] * ik, uk1 = ek[1] * ik, uk2 = ek[2] * ik;
+                T cs_ = uj0 * uk0 + uj1 * uk1 + uj2 * uk2;
+                cs_ = cs_ > T(1) ? T(1) : (cs_ < T(-1) ? T(-1) : cs_);
+                const T* tj = nt + TS_ * j;
+                const T* tk = nt + TS_ * k;
+                const T rjd = tj[3], rkd = tk[3];
+                // cdot = ((u_k - c u_j)/r_j).(v_j - v_i) + ((u_j - c u_k)/r_k).(v_k - v_i)
+                const T cdot = ((uk0 - cs_ * uj0) * tj[0] + (uk1 - cs_ * uj1) * tj[1] +
+                                (uk2 - cs_ * uj2) * tj[2]) * ij +
+                               ((uj0 - cs_ * uk0) * tk[0] + (uj1 - cs_ * uk1) * tk[1] +
+                                (uj2 - cs_ * uk2) * tk[2]) * ik;
+                const T cp = c.angle_scale * cs_;
+                const T sn = m_sqrt(T(1) - cp * cp);
+                const T F = ej[6] * ek[6];
+                const T Fd = ej[7] * ek[6] * rjd + ej[6] * ek[7] * rkd;
+                const T rm = T(0.5) * (rj + rk), rmd = T(0.5) * (rjd + rkd);
+                T* f = pf + PF * lane;
+#pragma unroll
+                for (int a = 0; a < NA; ++a) {
+                    const T d = rm - c.shf_a[a];
+                    const T Aa = m_exp(-c.eta_a * d * d);
+                    f[a] = T(-2) * c.eta_a * d * Aa * rmd * F + Aa * Fd;   // P_a
+                    f[NA + a] = Aa * F * cdot;                            // Q_a
+                }
+#pragma unroll
+                for (int z = 0; z < NZ; ++z) {
+                    const T cz = cp * c.cos_z[z] + sn * c.sin_z[z];
+                    const T hh = T(0.5) * (T(1) + cz);
+                    const T hp = m_powu(hh, c.zeta - T(1));
+                    f[2 * NA + z] = T(2) * hp * hh;
+                    f[2 * NA + NZ + z] = c.zeta * hp * c.angle_scale *
+                                         (c.cos_z[z] - cp * c.sin_z[z] * m_rcp(sn));
+                }
+                pb[lane] = RL + kNAZ * pair_index(nsp[j], nsp[k], S);
+            }
+            wave_sync();
+            for (int t = h; t < nbat; t += 2) {
+                const int blk = pb[t];
+                if (blk != cur) {
+                    if (cur >= 0) lds_add(row + cur + q, acc);
+                    acc = T(0);
+                    cur = blk;
+                }
+                const T* f = pf + PF * t;
+                acc += f[2 * NA + qz] * f[qa] + f[2 * NA + NZ + qz] * f[NA + qa];
+            }
+            wave_sync();
+        }
+        if (cur >= 0) lds_add(row + cur + q, acc);
+        wave_sync();
+        const size_t grow = (size_t)cs.crow[ic];
+        for (int e = lane; e < c.Dp; e += 64) Gd[grow * c.Dp + e] = Store<TS>::st(row[e]);
+        wave_sync();
+    }
+}
+
+template <typename T>
+static size_t jvp_lds(int max_apm, int cap, int Dp, int NZ, int nw) {
+    const int PF = 2 * (kNAZ / NZ) + 2 * NZ;
+    return ChunkStage<T>::bytes(max_apm, cap) + lds_bytes<T>(3 * (size_t)max_apm) +
+           lds_bytes<T>((size_t)nw * cap * kNbStride) + lds_bytes<T>((size_t)nw * cap * 4) +
+           2 * lds_bytes<int>((size_t)nw * cap) + lds_bytes<T>((size_t)nw * Dp) +
+           lds_bytes<T>((size_t)nw * 64 * PF) + lds_bytes<int>((size_t)nw * 64);
+}
+
+template <typename P>
+hipError_t launch_aev_jvp(const Shape& sh, const AevConst<typename P::T>& c,
+                          const int32_t* mol_off, const int32_t* species,
+                          const typename P::T* x, const typename P::T* v, Work<P>& w,
+                          typename P::TS* Gd, hipStream_t st, const Timer& tm) {
+    typedef typename P::T T;
+    dim3 grid(sh.B, (sh.max_apm + kChunk - 1) / kChunk);
+    int nw = kWaves;
+    size_t lds = jvp_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw);
+    while (lds > kMaxLds && nw > 1) lds = jvp_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw /= 2);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    auto kern = c.nZ == 4 ? k_aev_jvp<P, 4> : k_aev_jvp<P, 8>;
+    hipError_t e = ensure_lds((const void*)kern, lds);
+    if (e != hipSuccess) return e;
+    tm.b("aev_jvp", st);
+    hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.cap_nbr,
+                       mol_off, species, x, v, w.nbr, w.nbr_cnt, w.row_of_atom, Gd);
+    tm.e("aev_jvp", st);
     return hipGetLastError();
 }
 
@@ -414,9 +907,12 @@ hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const i
 // AEV backward: dE/dx contracted from dE/dAEV rows (dG, already scaled to
 // energy units), forces F = -dE/dx accumulated per molecule in LDS and added
 // to F (zeroed by the neighbour kernel) once per workgroup.
+constexpr int kBlkPad = kNAZ + 1;   // LDS stride of one element-pair block of dG
+constexpr int kMaxDpOverLanes = 20; // Dp <= 1280 = 20 * 64
+
 template <typename P, int NZ>
-__global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A, int max_apm, int cap,
-                                                const int32_t* __restrict__ mol_off,
+__global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A, int max_apm,
+                                                int cap, const int32_t* __restrict__ mol_off,
                                                 const int32_t* __restrict__ species,
                                                 const typename P::T* __restrict__ x,
                                                 const uint16_t* __restrict__ nbr,
@@ -425,98 +921,117 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
                                                 const typename P::TA* __restrict__ dG,
                                                 typename P::T* __restrict__ F) {
     typedef typename P::T T;
+    typedef typename P::TA TA;
+    constexpr int NA = kNAZ / NZ;
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x;
     const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
     if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
     const int i0 = blockIdx.y * kChunk;
     if (i0 >= n) return;
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    AevSmem<T> sm(smem, max_apm, c.Dp, cap, wave, true);
-    for (int t = tid; t < 3 * n; t += blockDim.x) {
-        sm.sx[t] = x[3 * (size_t)a0 + t];
-        sm.sF[t] = T(0);
-    }
-    for (int t = tid; t < n; t += blockDim.x) {
-        int s = species[a0 + t];
-        sm.ssp[t] = (s < 0 || s >= c.S) ? 0 : s;
-    }
+    const int nc = min(kChunk, n - i0);
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
+    const int S = c.S, RL = kNR * S, NB = S * (S + 1) / 2;
+    const int GL = RL + kBlkPad * NB;
+
+    LdsBump lb(smem);
+    ChunkStage<T> cs;
+    cs.take(lb, max_apm, cap);
+    T* sF = lb.take<T>(3 * (size_t)max_apm);
+    T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
+    int* nsp = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
+    int* nid = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
+    T* g = lb.take<T>((size_t)nw * GL) + (size_t)wave * GL;
+
+    cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, row_of_atom);
+    for (int t = tid; t < 3 * n; t += blockDim.x) sF[t] = T(0);
     __syncthreads();
-    const int radial_len = c.S * kNR;
-    const T dfc_r = -T(0.5) * c.pi_rcr, dfc_a = -T(0.5) * c.pi_rca;
-    const int i1 = min(i0 + kChunk, n);
-    for (int il = i0 + wave; il < i1; il += kWaves) {
-        const size_t ai = (size_t)a0 + il;
-        int nang, nall;
-        load_neighbours(sm, nbr + ai * cap, nbr_cnt[ai], il, nang, nall);
-        const size_t row = (size_t)row_of_atom[ai];
-        for (int e = lane; e < c.D; e += 64) sm.row[e] = (T)dG[row * c.Dp + e];
+    for (int ic = wave; ic < nc; ic += nw) {
+        const int il = i0 + ic;
+        const int cnt = cs.ccnt[ic];
+        const int nang = cnt & 0xffff, nall = cnt >> 16;
+        // the atom's dE/dAEV row: all loads in flight before the first use
+        {
+            const TA* src = dG + (size_t)cs.crow[ic] * c.Dp;
+            TA v[kMaxDpOverLanes];
+#pragma unroll
+            for (int u = 0; u < kMaxDpOverLanes; ++u) {
+                const int e = lane + 64 * u;
+                v[u] = e < c.D ? src[e] : TA(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kMaxDpOverLanes; ++u) {
+                const int e = lane + 64 * u;
+                if (e < c.D) {
+                    const int le = e < RL ? e : RL + kBlkPad * ((e - RL) / kNAZ) + (e - RL) % kNAZ;
+                    g[le] = (T)v[u];
+                }
+            }
+        }
+        load_neighbours(c, cs.sx, cs.ssp, cs.clst + (size_t)ic * cap, nang, nall, il, nb, nsp, nid);
         wave_sync();
         T fi0 = 0, fi1 = 0, fi2 = 0;   // force on the central atom, per lane
-        // radial
+        // radial: lane per (neighbour, group of 4 shifts)
         for (int it = lane; it < ((4 * nall + 63) & ~63); it += 64) {
             const bool act = it < 4 * nall;
             const int t = act ? (it >> 2) : 0, q = it & 3;
             T dEdr = 0;
             if (act) {
-                const T r = sm.nb[4 * t + 3];
-                const T fc = T(0.5) * m_cos(c.pi_rcr * r) + T(0.5);
-                const T dfc = dfc_r * m_sin(c.pi_rcr * r);
-                const T* g = sm.row + kNR * sm.nsp[t] + 4 * q;
+                const T* e = nb + kNbStride * t;
+                const T r = e[3], fc = e[4], dfc = e[5];
+                const T* gg = g + kNR * nsp[t] + 4 * q;
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const T d = r - c.shf_r[4 * q + kk];
                     const T ex = c.radial_pref * m_exp(-c.eta_r * d * d);
-                    dEdr += g[kk] * ex * (T(-2) * c.eta_r * d * fc + dfc);
+                    dEdr += gg[kk] * ex * (T(-2) * c.eta_r * d * fc + dfc);
                 }
             }
             // the four shift groups of one neighbour sit in adjacent lanes
             dEdr += __shfl_xor(dEdr, 1);
             dEdr += __shfl_xor(dEdr, 2);
             if (act && q == 0) {
-                const T inv = T(1) / sm.nb[4 * t + 3];
-                const T u0 = sm.nb[4 * t] * inv, u1 = sm.nb[4 * t + 1] * inv,
-                        u2 = sm.nb[4 * t + 2] * inv;
-                const int j = sm.nid[t];
+                const T* e = nb + kNbStride * t;
+                const T inv = m_rcp(e[3]);
+                const T u0 = e[0] * inv, u1 = e[1] * inv, u2 = e[2] * inv;
+                const int j = nid[t];
                 // dE/dx_j = dEdr u, dE/dx_i = -dEdr u;  F = -dE/dx
-                lds_add(&sm.sF[3 * j + 0], -dEdr * u0);
-                lds_add(&sm.sF[3 * j + 1], -dEdr * u1);
-                lds_add(&sm.sF[3 * j + 2], -dEdr * u2);
+                lds_add(&sF[3 * j + 0], -dEdr * u0);
+                lds_add(&sF[3 * j + 1], -dEdr * u1);
+                lds_add(&sF[3 * j + 2], -dEdr * u2);
                 fi0 += dEdr * u0;
                 fi1 += dEdr * u1;
                 fi2 += dEdr * u2;
             }
         }
-        // angular
+        // angular: lane per neighbour pair
         const int npair = nang * (nang - 1) / 2;
         for (int p = lane; p < npair; p += 64) {
             int j, k;
             decode_pair(p, nang, j, k);
-            const T rj = sm.nb[4 * j + 3], rk = sm.nb[4 * k + 3];
-            const T ij = T(1) / rj, ik = T(1) / rk;
-            const T uj0 = sm.nb[4 * j] * ij, uj1 = sm.nb[4 * j + 1] * ij, uj2 = sm.nb[4 * j + 2] * ij;
-            const T uk0 = sm.nb[4 * k] * ik, uk1 = sm.nb[4 * k + 1] * ik, uk2 = sm.nb[4 * k + 2] * ik;
-            T cs = uj0 * uk0 + uj1 * uk1 + uj2 * uk2;
-            cs = cs > T(1) ? T(1) : (cs < T(-1) ? T(-1) : cs);
-            const T cp = c.angle_scale * cs;
+            const T* ej = nb + kNbStride * j;
+            const T* ek = nb + kNbStride * k;
+            const T rj = ej[3], rk = ek[3];
+            const T ij = m_rcp(rj), ik = m_rcp(rk);
+            const T uj0 = ej[0] * ij, uj1 = ej[1] * ij, uj2 = ej[2] * ij;
+            const T uk0 = ek[0] * ik, uk1 = ek[1] * ik, uk2 = ek[2] * ik;
+            T cs_ = uj0 * uk0 + uj1 * uk1 + uj2 * uk2;
+            cs_ = cs_ > T(1) ? T(1) : (cs_ < T(-1) ? T(-1) : cs_);
+            const T cp = c.angle_scale * cs_;
             const T sn = m_sqrt(T(1) - cp * cp);
-            const T fcj = T(0.5) * m_cos(c.pi_rca * rj) + T(0.5);
-            const T fck = T(0.5) * m_cos(c.pi_rca * rk) + T(0.5);
-            const T dfcj = dfc_a * m_sin(c.pi_rca * rj);
-            const T dfck = dfc_a * m_sin(c.pi_rca * rk);
+            const T fcj = ej[6], fck = ek[6], dfcj = ej[7], dfck = ek[7];
             const T fcc = fcj * fck;
             const T rm = T(0.5) * (rj + rk);
-            const T* g = sm.row + radial_len + kNAZ * pair_index(sm.nsp[j], sm.nsp[k], c.S);
-            constexpr int NA = kNAZ / NZ;
+            const T* gb = g + RL + kBlkPad * pair_index(nsp[j], nsp[k], S);
             T fz[NZ], dfz[NZ];
 #pragma unroll
             for (int z = 0; z < NZ; ++z) {
                 const T cz = cp * c.cos_z[z] + sn * c.sin_z[z];
-                const T h = T(0.5) * (T(1) + cz);
-                const T hp = m_powu(h, c.zeta - T(1));
-                fz[z] = T(2) * hp * h;
+                const T hh = T(0.5) * (T(1) + cz);
+                const T hp = m_powu(hh, c.zeta - T(1));
+                fz[z] = T(2) * hp * hh;
                 // d cos(theta'-t)/dc = s (cos t - c' sin t / sqrt(1 - c'^2))
-                const T dcz = c.angle_scale * (c.cos_z[z] - cp * c.sin_z[z] / sn);
+                const T dcz = c.angle_scale * (c.cos_z[z] - cp * c.sin_z[z] * m_rcp(sn));
                 dfz[z] = c.zeta * hp * dcz;
             }
             T Dc = 0, Drj = 0, Drk = 0;
@@ -528,7 +1043,7 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
                 T sg = 0, sgd = 0;
 #pragma unroll
                 for (int z = 0; z < NZ; ++z) {
-                    const T gg = g[NZ * a + z];
+                    const T gg = gb[NZ * a + z];
                     sg += gg * fz[z];
                     sgd += gg * dfz[z];
                 }
@@ -537,19 +1052,19 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
                 Drk += sg * (dfa_half * fcc + fa * fcj * dfck);
             }
             // dc/dx_j = (u_k - c u_j)/r_j ; dc/dx_k = (u_j - c u_k)/r_k
-            const T gj0 = Drj * uj0 + Dc * (uk0 - cs * uj0) * ij;
-            const T gj1 = Drj * uj1 + Dc * (uk1 - cs * uj1) * ij;
-            const T gj2 = Drj * uj2 + Dc * (uk2 - cs * uj2) * ij;
-            const T gk0 = Drk * uk0 + Dc * (uj0 - cs * uk0) * ik;
-            const T gk1 = Drk * uk1 + Dc * (uj1 - cs * uk1) * ik;
-            const T gk2 = Drk * uk2 + Dc * (uj2 - cs * uk2) * ik;
-            const int jj = sm.nid[j], kk = sm.nid[k];
-            lds_add(&sm.sF[3 * jj + 0], -gj0);
-            lds_add(&sm.sF[3 * jj + 1], -gj1);
-            lds_add(&sm.sF[3 * jj + 2], -gj2);
-            lds_add(&sm.sF[3 * kk + 0], -gk0);
-            lds_add(&sm.sF[3 * kk + 1], -gk1);
-            lds_add(&sm.sF[3 * kk + 2], -gk2);
+            const T gj0 = Drj * uj0 + Dc * (uk0 - cs_ * uj0) * ij;
+            const T gj1 = Drj * uj1 + Dc * (uk1 - cs_ * uj1) * ij;
+            const T gj2 = Drj * uj2 + Dc * (uk2 - cs_ * uj2) * ij;
+            const T gk0 = Drk * uk0 + Dc * (uj0 - cs_ * uk0) * ik;
+            const T gk1 = Drk * uk1 + Dc * (uj1 - cs_ * uk1) * ik;
+            const T gk2 = Drk * uk2 + Dc * (uj2 - cs_ * uk2) * ik;
+            const int jj = nid[j], kk = nid[k];
+            lds_add(&sF[3 * jj + 0], -gj0);
+            lds_add(&sF[3 * jj + 1], -gj1);
+            lds_add(&sF[3 * jj + 2], -gj2);
+            lds_add(&sF[3 * kk + 0], -gk0);
+            lds_add(&sF[3 * kk + 1], -gk1);
+            lds_add(&sF[3 * kk + 2], -gk2);
             fi0 += gj0 + gk0;
             fi1 += gj1 + gk1;
             fi2 += gj2 + gk2;
@@ -560,17 +1075,25 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
             fi2 += __shfl_xor(fi2, off);
         }
         if (lane == 0) {
-            lds_add(&sm.sF[3 * il + 0], fi0);
-            lds_add(&sm.sF[3 * il + 1], fi1);
-            lds_add(&sm.sF[3 * il + 2], fi2);
+            lds_add(&sF[3 * il + 0], fi0);
+            lds_add(&sF[3 * il + 1], fi1);
+            lds_add(&sF[3 * il + 2], fi2);
         }
         wave_sync();
     }
     __syncthreads();
     for (int t = tid; t < 3 * n; t += blockDim.x) {
-        T v = sm.sF[t];
+        T v = sF[t];
         if (v != T(0)) gbl_add(&F[3 * (size_t)a0 + t], v);
     }
+}
+
+template <typename T>
+static size_t forces_lds(int max_apm, int cap, int S, int nw) {
+    const int GL = kNR * S + kBlkPad * S * (S + 1) / 2;
+    return ChunkStage<T>::bytes(max_apm, cap) + lds_bytes<T>(3 * (size_t)max_apm) +
+           lds_bytes<T>((size_t)nw * cap * kNbStride) + 2 * lds_bytes<int>((size_t)nw * cap) +
+           lds_bytes<T>((size_t)nw * GL);
 }
 
 template <typename P>
@@ -578,14 +1101,17 @@ hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
                          const int32_t* mol_off, const int32_t* species, const typename P::T* x,
                          Work<P>& w, typename P::T* F, hipStream_t st, const Timer& tm) {
     typedef typename P::T T;
+    if (c.Dp > 64 * kMaxDpOverLanes) return hipErrorInvalidValue;
     dim3 grid(sh.B, (sh.max_apm + kChunk - 1) / kChunk);
-    size_t lds = AevSmem<T>::bytes(sh.max_apm, c.Dp, sh.cap_nbr, true);
+    int nw = kWaves;
+    size_t lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw);
+    while (lds > kMaxLds && nw > 1) lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw /= 2);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = c.nZ == 4 ? k_forces<P, 4> : k_forces<P, 8>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("forces", st);
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, c, sh.A, sh.max_apm, sh.cap_nbr,
+    hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.cap_nbr,
                        mol_off, species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.dG, F);
     tm.e("forces", st);
     return hipGetLastError();
@@ -641,14 +1167,17 @@ hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t
     template hipError_t launch_prep<P>(const Shape&, const int32_t*, const int32_t*, Work<P>&,  \
                                        hipStream_t, const Timer&);                             \
     template hipError_t launch_neighbours<P>(const Shape&, const AevConst<P::T>&,              \
-                                             const int32_t*, const P::T*, P::T*, Work<P>&,     \
-                                             hipStream_t, const Timer&);                       \
+                                             const int32_t*, const int32_t*, const P::T*,      \
+                                             P::T*, Work<P>&, hipStream_t, const Timer&);      \
     template hipError_t launch_aev<P>(const Shape&, const AevConst<P::T>&, const int32_t*,     \
                                       const int32_t*, const P::T*, Work<P>&, P::T*,            \
                                       hipStream_t, const Timer&);                              \
     template hipError_t launch_forces<P>(const Shape&, const AevConst<P::T>&, const int32_t*,  \
                                          const int32_t*, const P::T*, Work<P>&, P::T*,         \
                                          hipStream_t, const Timer&);                           \
+    template hipError_t launch_aev_jvp<P>(const Shape&, const AevConst<P::T>&, const int32_t*, \
+                                          const int32_t*, const P::T*, const P::T*, Work<P>&,  \
+                                          P::TS*, hipStream_t, const Timer&);                  \
     template hipError_t launch_energy<P>(const Shape&, const DevWeights<P>&, const int32_t*,   \
                                          const int32_t*, Work<P>&, double*, hipStream_t,       \
                                          const Timer&);

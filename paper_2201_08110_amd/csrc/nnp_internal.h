@@ -7,13 +7,19 @@
 //   mlp         six GEMMs per element bucket, all ensemble members at once:
 //                 layer-1 forward (models concatenated along N), layers 2-3
 //                 forward (per model), layer-3 backward, layer-2 backward,
-//                 layer-1 backward (models summed along K) -> dE/dAEV
+//                 layer-1 backward (models summed along K) -> dE/dAEV;
+//                 activations are stored after CELU and CELU' is recovered
+//                 from them
 //   forces      AEV backward contracted with dE/dAEV, scattered to atoms
 //   energy      per-molecule FP64 sum of the atomic energies
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
 
 namespace nnp {
 
@@ -62,6 +68,7 @@ constexpr int kNR = 16;          // radial shifts supported by the kernels
 constexpr int kNAZ = 32;         // angular (distance x angle) shifts supported
 constexpr int kMaxNA = 16;       // angular-distance shifts (<= 32 / 1)
 constexpr int kMaxAtomsPerMol = 1024;
+constexpr int kPrepBlock = 1024;   // atoms per block of the bucketing kernels
 constexpr int kMaxNeighbours = 192;
 
 // featuriser constants, passed by value to the kernels
@@ -94,18 +101,39 @@ template <typename P> struct Work {
     int32_t* atom_of_row;   // [Rcap]   -1 for padding rows
     int32_t* mol_of_atom;   // [A]
     int32_t* tile_species;  // [Rcap / row_tile]
+    int32_t* blk;           // [2][n_blocks][kMaxSpecies]  per-block counts / bases
     BucketInfo* info;
     int32_t* flag;
     uint16_t* nbr;          // [A][cap_nbr]  local indices, angular (r < rca) first
     int32_t* nbr_cnt;       // [A]  n_ang | (n_all << 16)
     TS* G;                  // [Rcap][Dp]
-    TS* Z1;                 // [Rcap][M*H1]
-    TS* Z2;                 // [Rcap][M*H2]
+    TS* H1;                 // [Rcap][M*H1]  layer-1 activations CELU(z1)
+    TS* H2;                 // [Rcap][M*H2]  layer-2 activations CELU(z2)
     TS* DZ3;                // [Rcap][M*H3]
     TS* DZ2;                // [Rcap][M*H2]
     TS* DZ1;                // [Rcap][M*H1]
     TA* Epart;              // [Rcap][M][H3/64]
     TA* dG;                 // [Rcap][Dp]
+};
+
+// extra workspace of the training backward (allocated on its first call)
+template <typename P> struct TrainWork {
+    typedef typename P::TS TS;
+    TS* GD;     // [Rcap][Dp]     AEV tangent along the force cotangent
+    TS* H3;     // [Rcap][M*H3]   layer-3 activations
+    TS* TH1;    // [Rcap][M*H1]   tangent activations
+    TS* TH2;    // [Rcap][M*H2]
+    TS* TH3;    // [Rcap][M*H3]
+    TS* ZDB1;   // [Rcap][M*H1]   adjoints of the tangent pre-activations
+    TS* ZDB2;   // [Rcap][M*H2]
+    TS* ZDB3;   // [Rcap][M*H3]
+    TS* TMP;    // [Rcap][M*max(H1,H2)]
+};
+
+// host-computed layout of one network inside the packed parameter array
+struct NetLayout {
+    int o1, o2, o3, D;                 // unpadded widths
+    long offW1, offb1, offW2, offb2, offW3, offb3, offw4, offb4, net;
 };
 
 // packed device weights (per precision)
@@ -139,14 +167,31 @@ struct Timer {
     void e(const char* n, hipStream_t s) const { if (end) end(ctx, n, s); }
 };
 
+// Raise a kernel's dynamic-LDS limit once per (kernel, device): later calls
+// (including those recorded into a HIP graph) do no host-side work.
+inline hipError_t ensure_lds(const void* kern, size_t bytes) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, size_t> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    std::lock_guard<std::mutex> g(mu);
+    auto key = std::make_pair(kern, dev);
+    auto it = done.find(key);
+    if (it != done.end() && it->second >= bytes) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) done[key] = bytes;
+    return e;
+}
+
 // launchers (explicitly instantiated for PrecF64 / PrecF32 / PrecBF16)
 template <typename P>
 hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* species,
                        Work<P>& w, hipStream_t st, const Timer& tm);
 template <typename P>
 hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
-                             const int32_t* mol_off, const typename P::T* x,
-                             typename P::T* F_zero, Work<P>& w, hipStream_t st, const Timer& tm);
+                             const int32_t* mol_off, const int32_t* species,
+                             const typename P::T* x, typename P::T* F_zero, Work<P>& w,
+                             hipStream_t st, const Timer& tm);
 template <typename P>
 hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
                       const int32_t* species, const typename P::T* x, Work<P>& w,
@@ -155,9 +200,34 @@ template <typename P>
 hipError_t launch_mlp(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipStream_t st,
                       const Timer& tm);
 template <typename P>
+hipError_t launch_aev_jvp(const Shape& sh, const AevConst<typename P::T>& c,
+                          const int32_t* mol_off, const int32_t* species,
+                          const typename P::T* x, const typename P::T* v, Work<P>& w,
+                          typename P::TS* Gd, hipStream_t st, const Timer& tm);
+template <typename P>
 hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
                          const int32_t* mol_off, const int32_t* species, const typename P::T* x,
                          Work<P>& w, typename P::T* F, hipStream_t st, const Timer& tm);
+template <typename P>
+hipError_t launch_train_mlp(const Shape& sh, const DevWeights<P>& wt, Work<P>& w,
+                            TrainWork<P>& tw, const int32_t* mol_of_atom, const double* grad_E,
+                            bool has_gF, hipStream_t st, const Timer& tm);
+template <typename P>
+hipError_t launch_train_mlp_rev(const Shape& sh, const DevWeights<P>& wt, Work<P>& w,
+                                TrainWork<P>& tw, hipStream_t st, const Timer& tm);
+template <typename P>
+hipError_t launch_train_rev3(const Shape& sh, const DevWeights<P>& wt, Work<P>& w,
+                             TrainWork<P>& tw, const int32_t* mol_of_atom, const double* grad_E,
+                             bool has_gF, hipStream_t st, const Timer& tm);
+template <typename P>
+hipError_t launch_train_grads(const Shape& sh, const NetLayout& nl, Work<P>& w, TrainWork<P>& tw,
+                              const int32_t* mol_of_atom, const double* grad_E, bool has_gF,
+                              typename P::TA* grad_params, hipStream_t st, const Timer& tm);
+template <typename P>
+hipError_t launch_fill(typename P::TS* p, size_t n, hipStream_t st);
+template <typename P>
+hipError_t launch_grad_coords(int A, const int32_t* mol_of_atom, const double* grad_E,
+                              const typename P::T* F, typename P::T* gx, hipStream_t st);
 template <typename P>
 hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t* mol_off,
                          const int32_t* species, Work<P>& w, double* E, hipStream_t st,

@@ -54,6 +54,21 @@ struct EventPair {
     hipEvent_t a, b;
 };
 
+// one captured evaluation, valid for exactly these shapes, pointers and stream
+struct GraphEntry {
+    int A = 0, B = 0;
+    const void* ptr[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipStream_t stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool same(int a, int b, const void* const* p, hipStream_t s) const {
+        if (a != A || b != B || s != stream) return false;
+        for (int i = 0; i < 5; ++i)
+            if (p[i] != ptr[i]) return false;
+        return true;
+    }
+};
+constexpr size_t kMaxGraphs = 8;
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -80,6 +95,17 @@ struct nnp_handle {
     Work<PrecBF16> k16{};
     int32_t* flag = nullptr;
     hipStream_t last_stream = nullptr;
+
+    // training backward workspace (allocated on its first call)
+    bool train_ready = false;
+    TrainWork<PrecF64> t64{};
+    TrainWork<PrecF32> t32{};
+    void* train_F = nullptr;      // [max_atoms][3] coordinate type
+    double* train_E = nullptr;    // [max_mols]
+    NetLayout nl{};
+
+    // captured evaluations (most recent last)
+    std::vector<GraphEntry> graphs;
 
     // timing
     bool timing = false;
@@ -250,11 +276,13 @@ template <typename P> nnp_status alloc_work(nnp_handle* h, Work<P>& w) {
     ALLOC(mol_of_atom, sizeof(int32_t) * A);
     ALLOC(tile_species, sizeof(int32_t) * (R / sh.row_tile));
     ALLOC(info, sizeof(BucketInfo));
+    const size_t nblk = (std::max(A, (size_t)h->max_mols) + kPrepBlock - 1) / kPrepBlock + 1;
+    ALLOC(blk, sizeof(int32_t) * 2 * kMaxSpecies * nblk);
     ALLOC(nbr, sizeof(uint16_t) * A * sh.cap_nbr);
     ALLOC(nbr_cnt, sizeof(int32_t) * A);
     ALLOC(G, sizeof(TS) * R * sh.Dp);
-    ALLOC(Z1, sizeof(TS) * R * M * sh.H1);
-    ALLOC(Z2, sizeof(TS) * R * M * sh.H2);
+    ALLOC(H1, sizeof(TS) * R * M * sh.H1);
+    ALLOC(H2, sizeof(TS) * R * M * sh.H2);
     ALLOC(DZ3, sizeof(TS) * R * M * sh.H3);
     ALLOC(DZ2, sizeof(TS) * R * M * sh.H2);
     ALLOC(DZ1, sizeof(TS) * R * M * sh.H1);
@@ -279,7 +307,9 @@ nnp_status check_batch(const nnp_handle* h, const nnp_batch* b) {
     if (b->n_atoms > h->max_atoms) return fail(NNP_E_CAPACITY, "n_atoms exceeds max_atoms");
     if (!b->mol_offsets) return fail(NNP_E_INVALID, "null mol_offsets");
     if (b->n_atoms > 0 && !b->species) return fail(NNP_E_INVALID, "null species");
-    if (b->flags != 0) return fail(NNP_E_INVALID, "flags must be 0");
+    if (b->flags & ~NNP_FLAG_GRAPH) return fail(NNP_E_INVALID, "unknown flags");
+    if ((b->flags & NNP_FLAG_GRAPH) && !b->stream)
+        return fail(NNP_E_INVALID, "graph replay needs a non-null stream");
     return NNP_OK;
 }
 
@@ -291,6 +321,9 @@ template <typename P> DevWeights<P>& weights_of(nnp_handle* h);
 template <> DevWeights<PrecF64>& weights_of<PrecF64>(nnp_handle* h) { return h->w64; }
 template <> DevWeights<PrecF32>& weights_of<PrecF32>(nnp_handle* h) { return h->w32; }
 template <> DevWeights<PrecBF16>& weights_of<PrecBF16>(nnp_handle* h) { return h->w16; }
+template <typename P> TrainWork<P>& train_of(nnp_handle* h);
+template <> TrainWork<PrecF64>& train_of<PrecF64>(nnp_handle* h) { return h->t64; }
+template <> TrainWork<PrecF32>& train_of<PrecF32>(nnp_handle* h) { return h->t32; }
 template <typename T> const AevConst<T>& const_of(nnp_handle* h);
 template <> const AevConst<float>& const_of<float>(nnp_handle* h) { return h->cf; }
 template <> const AevConst<double>& const_of<double>(nnp_handle* h) { return h->cd; }
@@ -309,7 +342,7 @@ nnp_status run_forward(nnp_handle* h, const nnp_batch* b, const typename P::T* x
     Timer tm = make_timer(h);
     HIP_TRY(launch_prep<P>(sh, b->mol_offsets, b->species, w, st, tm));
     if (sh.A > 0) {
-        HIP_TRY(launch_neighbours<P>(sh, c, b->mol_offsets, x, F, w, st, tm));
+        HIP_TRY(launch_neighbours<P>(sh, c, b->mol_offsets, b->species, x, F, w, st, tm));
         HIP_TRY(launch_aev<P>(sh, c, b->mol_offsets, b->species, x, w, aev_out, st, tm));
     }
     if (aev_out) return NNP_OK;
@@ -317,6 +350,129 @@ nnp_status run_forward(nnp_handle* h, const nnp_batch* b, const typename P::T* x
     if (F && sh.A > 0)
         HIP_TRY(launch_forces<P>(sh, c, b->mol_offsets, b->species, x, w, F, st, tm));
     HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), b->mol_offsets, b->species, w, E, st, tm));
+    return NNP_OK;
+}
+
+// Forward evaluation through the graph cache: replay on a hit; on a miss run
+// eagerly (this call's results), then capture the same launch sequence for
+// the next calls.  A failed capture leaves the eager result and no entry.
+template <typename P>
+nnp_status run_forward_graph(nnp_handle* h, const nnp_batch* b, const typename P::T* x, double* E,
+                             typename P::T* F) {
+    hipStream_t st = (hipStream_t)b->stream;
+    const void* key[5] = {b->mol_offsets, b->species, x, E, F};
+    for (size_t i = 0; i < h->graphs.size(); ++i)
+        if (h->graphs[i].same(b->n_atoms, b->n_mols, key, st)) {
+            h->last_stream = st;
+            HIP_TRY(hipGraphLaunch(h->graphs[i].exec, st));
+            return NNP_OK;
+        }
+    nnp_status rc = run_forward<P>(h, b, x, E, F, nullptr);
+    if (rc) return rc;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return NNP_OK;
+    rc = run_forward<P>(h, b, x, E, F, nullptr);
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc != NNP_OK || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        g_err.clear();
+        return NNP_OK;
+    }
+    GraphEntry ge;
+    ge.A = b->n_atoms;
+    ge.B = b->n_mols;
+    for (int i = 0; i < 5; ++i) ge.ptr[i] = key[i];
+    ge.stream = st;
+    e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return NNP_OK;
+    if (h->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(h->graphs.front().exec);
+        h->graphs.erase(h->graphs.begin());
+    }
+    h->graphs.push_back(ge);
+    return NNP_OK;
+}
+
+template <typename P> nnp_status alloc_train(nnp_handle* h) {
+    typedef typename P::TS TS;
+    typedef typename P::T T;
+    if (h->train_ready) return NNP_OK;
+    TrainWork<P>& tw = train_of<P>(h);
+    const Shape& sh = h->shape;
+    const size_t R = sh.Rcap;
+    const int M = sh.M;
+    hipError_t e = hipSuccess;
+#define TALLOC(field, bytes)                                                             \
+    do {                                                                                 \
+        tw.field = (decltype(tw.field))h->dalloc(bytes, e);                              \
+        if (e != hipSuccess)                                                             \
+            return fail(e == hipErrorOutOfMemory ? NNP_E_NOMEM : NNP_E_DEVICE,           \
+                        std::string("training workspace: ") + hipGetErrorString(e));     \
+    } while (0)
+    TALLOC(GD, sizeof(TS) * R * sh.Dp);
+    TALLOC(H3, sizeof(TS) * R * M * sh.H3);
+    TALLOC(TH1, sizeof(TS) * R * M * sh.H1);
+    TALLOC(TH2, sizeof(TS) * R * M * sh.H2);
+    TALLOC(TH3, sizeof(TS) * R * M * sh.H3);
+    TALLOC(ZDB1, sizeof(TS) * R * M * sh.H1);
+    TALLOC(ZDB2, sizeof(TS) * R * M * sh.H2);
+    TALLOC(ZDB3, sizeof(TS) * R * M * sh.H3);
+    TALLOC(TMP, sizeof(TS) * R * M * std::max(sh.H1, sh.H2));
+#undef TALLOC
+    h->train_F = h->dalloc(sizeof(T) * 3 * (size_t)std::max(h->max_atoms, 1), e);
+    if (e != hipSuccess) return fail(NNP_E_NOMEM, "training workspace (forces)");
+    h->train_E = (double*)h->dalloc(sizeof(double) * (size_t)h->max_mols, e);
+    if (e != hipSuccess) return fail(NNP_E_NOMEM, "training workspace (energies)");
+    // padding rows of the AEV tangent are never written by the featuriser
+    HIP_TRY(hipMemset(tw.GD, 0, sizeof(TS) * R * sh.Dp));
+    h->train_ready = true;
+    return NNP_OK;
+}
+
+template <typename P>
+nnp_status run_backward(nnp_handle* h, const nnp_batch* b, const typename P::T* x,
+                        const double* gE, const typename P::T* gF, typename P::TA* gp,
+                        typename P::T* gx) {
+    typedef typename P::T T;
+    nnp_status rc = alloc_train<P>(h);
+    if (rc) return rc;
+    Shape sh = h->shape;
+    sh.A = b->n_atoms;
+    sh.B = b->n_mols;
+    hipStream_t st = (hipStream_t)b->stream;
+    h->last_stream = st;
+    Work<P>& w = work_of<P>(h);
+    TrainWork<P>& tw = train_of<P>(h);
+    const AevConst<T>& c = const_of<T>(h);
+    Timer tm = make_timer(h);
+    if (gx) {
+        // dL/dx of an energy-only loss: -gE_b F_i from one forward evaluation
+        rc = run_forward<P>(h, b, x, h->train_E, (T*)h->train_F, nullptr);
+        if (rc) return rc;
+        HIP_TRY(launch_grad_coords<P>(sh.A, w.mol_of_atom, gE, (const T*)h->train_F, gx, st));
+    }
+    const bool has_gF = gF != nullptr;
+    HIP_TRY(launch_prep<P>(sh, b->mol_offsets, b->species, w, st, tm));
+    if (sh.A > 0) {
+        HIP_TRY(launch_neighbours<P>(sh, c, b->mol_offsets, b->species, x, (T*)nullptr, w, st, tm));
+        HIP_TRY(launch_aev<P>(sh, c, b->mol_offsets, b->species, x, w, (T*)nullptr, st, tm));
+        if (has_gF)
+            HIP_TRY(launch_aev_jvp<P>(sh, c, b->mol_offsets, b->species, x, gF, w, tw.GD, st, tm));
+    }
+    if (!has_gF) {
+        // the reverse steps read the tangent activations: make them exact zeros
+        const size_t R = sh.Rcap;
+        HIP_TRY(launch_fill<P>(tw.TH1, R * sh.M * sh.H1, st));
+        HIP_TRY(launch_fill<P>(tw.TH2, R * sh.M * sh.H2, st));
+        HIP_TRY(launch_fill<P>(tw.TH3, R * sh.M * sh.H3, st));
+    }
+    const DevWeights<P>& wt = weights_of<P>(h);
+    HIP_TRY(launch_train_mlp<P>(sh, wt, w, tw, w.mol_of_atom, gE, has_gF, st, tm));
+    HIP_TRY(launch_train_rev3<P>(sh, wt, w, tw, w.mol_of_atom, gE, has_gF, st, tm));
+    HIP_TRY(launch_train_mlp_rev<P>(sh, wt, w, tw, st, tm));
+    HIP_TRY(launch_train_grads<P>(sh, h->nl, w, tw, w.mol_of_atom, gE, has_gF, gp, st, tm));
     return NNP_OK;
 }
 
@@ -385,6 +541,22 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     int64_t net = 0;
     for (int l = 0; l < 4; ++l) net += (int64_t)p->widths[l + 1] * p->widths[l] + p->widths[l + 1];
     h->n_params = net * S * h->M;
+    {
+        NetLayout& nl = h->nl;
+        nl.D = D;
+        nl.o1 = p->widths[1];
+        nl.o2 = p->widths[2];
+        nl.o3 = p->widths[3];
+        nl.offW1 = 0;
+        nl.offb1 = (long)nl.o1 * D;
+        nl.offW2 = nl.offb1 + nl.o1;
+        nl.offb2 = nl.offW2 + (long)nl.o2 * nl.o1;
+        nl.offW3 = nl.offb2 + nl.o2;
+        nl.offb3 = nl.offW3 + (long)nl.o3 * nl.o2;
+        nl.offw4 = nl.offb3 + nl.o3;
+        nl.offb4 = nl.offw4 + nl.o3;
+        nl.net = nl.offb4 + 1;
+    }
 
     Shape& sh = h->shape;
     sh.S = S;
@@ -394,7 +566,7 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     sh.H1 = pad_to(p->widths[1], 64);
     sh.H2 = pad_to(p->widths[2], 64);
     sh.H3 = pad_to(p->widths[3], 64);
-    sh.row_tile = (p->max_atoms <= 256 || p->precision == NNP_PREC_FP64) ? 16 : 64;
+    sh.row_tile = (p->max_atoms <= 256 || p->precision == NNP_PREC_FP64) ? 16 : 128;
     sh.Rcap = pad_to(p->max_atoms + S * (sh.row_tile - 1), sh.row_tile);
     sh.cap_nbr = std::max(1, std::min(h->max_apm - 1, kMaxNeighbours));
     sh.max_apm = h->max_apm;
@@ -445,6 +617,7 @@ void nnp_destroy(nnp_handle* h) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : h->free_events) (void)hipEventDestroy(e);
+    for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     delete h;
 }
 
@@ -457,9 +630,12 @@ nnp_status nnp_energy_forces(nnp_handle* h, const nnp_batch* b, const float* coo
     if (!out_E || (b->n_atoms > 0 && !coords)) return fail(NNP_E_INVALID, "null coords or out_E");
     DeviceGuard dg(h->device);
     if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    const bool graph = (b->flags & NNP_FLAG_GRAPH) && !h->timing;
     if (h->precision == NNP_PREC_FP32)
-        return run_forward<PrecF32>(h, b, coords, out_E, out_F, nullptr);
-    return run_forward<PrecBF16>(h, b, coords, out_E, out_F, nullptr);
+        return graph ? run_forward_graph<PrecF32>(h, b, coords, out_E, out_F)
+                     : run_forward<PrecF32>(h, b, coords, out_E, out_F, nullptr);
+    return graph ? run_forward_graph<PrecBF16>(h, b, coords, out_E, out_F)
+                 : run_forward<PrecBF16>(h, b, coords, out_E, out_F, nullptr);
 }
 
 nnp_status nnp_energy_forces_f64(nnp_handle* h, const nnp_batch* b, const double* coords,
@@ -471,6 +647,8 @@ nnp_status nnp_energy_forces_f64(nnp_handle* h, const nnp_batch* b, const double
     if (!out_E || (b->n_atoms > 0 && !coords)) return fail(NNP_E_INVALID, "null coords or out_E");
     DeviceGuard dg(h->device);
     if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    if ((b->flags & NNP_FLAG_GRAPH) && !h->timing)
+        return run_forward_graph<PrecF64>(h, b, coords, out_E, out_F);
     return run_forward<PrecF64>(h, b, coords, out_E, out_F, nullptr);
 }
 
@@ -492,8 +670,20 @@ nnp_status nnp_energy_forces_backward(nnp_handle* h, const nnp_batch* b, const v
                                       void* grad_params, void* grad_coords) {
     nnp_status rc = check_batch(h, b);
     if (rc) return rc;
-    (void)coords; (void)grad_E; (void)grad_F; (void)grad_params; (void)grad_coords;
-    return fail(NNP_E_UNSUPPORTED, "training backward is not available in this build");
+    if (!grad_params || (b->n_atoms > 0 && !coords))
+        return fail(NNP_E_INVALID, "null coords or grad_params");
+    if (grad_coords && grad_F)
+        return fail(NNP_E_UNSUPPORTED,
+                    "coordinate gradients of force-dependent losses are not implemented");
+    if (h->precision == NNP_PREC_BF16_MLP)
+        return fail(NNP_E_UNSUPPORTED, "the training backward runs on FP32 or FP64 handles");
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    if (h->precision == NNP_PREC_FP64)
+        return run_backward<PrecF64>(h, b, (const double*)coords, grad_E, (const double*)grad_F,
+                                     (double*)grad_params, (double*)grad_coords);
+    return run_backward<PrecF32>(h, b, (const float*)coords, grad_E, (const float*)grad_F,
+                                 (float*)grad_params, (float*)grad_coords);
 }
 
 nnp_status nnp_set_weights(nnp_handle* h, const double* weights) {

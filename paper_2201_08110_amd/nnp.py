@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnnp_hip.so")
 
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+FLAG_GRAPH = 1
 
 NNP_OK, NNP_E_INVALID, NNP_E_SPECIES, NNP_E_CAPACITY, NNP_E_NOMEM, NNP_E_DEVICE, \
     NNP_E_UNSUPPORTED = range(7)
@@ -163,7 +164,7 @@ class NNP:
         import torch
         return torch.float64 if self.precision == "fp64" else torch.float32
 
-    def _batch(self, species, mol_offsets, stream=None):
+    def _batch(self, species, mol_offsets, stream=None, flags=0):
         import torch
         b = Batch()
         b.n_mols = int(mol_offsets.numel()) - 1
@@ -172,7 +173,7 @@ class NNP:
         b.species = species.data_ptr() if species.numel() else None
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         b.stream = s.cuda_stream
-        b.flags = 0
+        b.flags = flags
         return b
 
     @staticmethod
@@ -184,13 +185,17 @@ class NNP:
             raise TypeError(f"{name} must be contiguous {dtype}")
 
     # -- API ---------------------------------------------------------------
-    def energy_forces(self, coords, species, mol_offsets, forces: bool = True, out=None):
-        """Energies [B] (float64) and forces [A, 3] of a ragged batch."""
+    def energy_forces(self, coords, species, mol_offsets, forces: bool = True, out=None,
+                      graph: bool = False, stream=None):
+        """Energies [B] (float64) and forces [A, 3] of a ragged batch.
+
+        graph=True replays a captured HIP graph while shapes, tensors and the
+        stream stay the same (needs a non-default stream)."""
         import torch
         self._need(coords, self.coord_dtype, "coords")
         self._need(species, torch.int32, "species")
         self._need(mol_offsets, torch.int32, "mol_offsets")
-        b = self._batch(species, mol_offsets)
+        b = self._batch(species, mol_offsets, stream=stream, flags=FLAG_GRAPH if graph else 0)
         if out is None:
             E = torch.empty(b.n_mols, dtype=torch.float64, device=coords.device)
             F = torch.empty_like(coords) if forces else None
@@ -213,6 +218,11 @@ class NNP:
                  want_coords: bool = False):
         """dL/dW (packed like the weights) and optionally dL/dx."""
         import torch
+        self._need(coords, self.coord_dtype, "coords")
+        if grad_E is not None:
+            self._need(grad_E, torch.float64, "grad_E")
+        if grad_F is not None:
+            self._need(grad_F, self.coord_dtype, "grad_F")
         b = self._batch(species, mol_offsets)
         gp = torch.empty(self.num_params, dtype=self.coord_dtype, device=coords.device)
         gx = torch.empty_like(coords) if want_coords else None
@@ -226,6 +236,16 @@ class NNP:
     def set_weights(self, weights):
         w = np.ascontiguousarray(weights, dtype=np.float64)
         _check(self.lib.nnp_set_weights(self.h, _dp(w)))
+        self._synced = None
+
+    def sync_params(self, params):
+        """Upload a torch tensor of packed master weights if it changed since
+        the last upload (tracked by storage pointer and in-place version)."""
+        import torch
+        key = (params.data_ptr(), params._version)
+        if getattr(self, "_synced", None) != key:
+            self.set_weights(params.detach().to("cpu", dtype=torch.float64).numpy())
+            self._synced = key
 
     @property
     def num_params(self) -> int:

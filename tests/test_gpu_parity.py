@@ -141,3 +141,51 @@ def test_device_flags(hp):
     assert h.device_status() == NNP_E_CAPACITY
     h.energy_forces(x, sp, off)
     assert h.device_status() == 0
+
+
+def test_graph_replay_matches_eager(hp):
+    """Captured-graph replays: coordinates change in place between replays,
+    with eager calls and synchronisations in between; each replay must agree
+    with an eager evaluation of the same coordinates."""
+    torch = torch_cuda()
+    b = synth.config_batch(2)
+    w = synth.xavier_weights(8, hp["widths"])
+    h = make_handle(hp, w, 8, "fp32", b)
+    x, sp, off = to_device(torch, b, torch.float32)
+    s = torch.cuda.Stream()
+    E = torch.empty(b.n_mols, dtype=torch.float64, device="cuda")
+    F = torch.empty_like(x)
+    rng = np.random.default_rng(0)
+    for it in range(6):
+        xn = torch.tensor(b.coords + rng.normal(0.0, 0.02, size=b.coords.shape),
+                          dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            x.copy_(xn)
+            h.energy_forces(x, sp, off, out=(E, F), graph=True, stream=s)
+        s.synchronize()
+        Eg, Fg = E.clone(), F.clone()
+        E2, F2 = h.energy_forces(x, sp, off)
+        torch.cuda.synchronize()
+        assert h.device_status() == 0
+        np.testing.assert_allclose(Eg.cpu().numpy(), E2.cpu().numpy(), rtol=1e-6)
+        np.testing.assert_allclose(Fg.cpu().numpy(), F2.cpu().numpy(), rtol=1e-4,
+                                   atol=1e-4 * float(F2.abs().max()))
+
+
+@pytest.mark.parametrize("prec,sizes", [("fp64", [300, 150]), ("fp32", [700, 40, 129])])
+def test_large_molecules_cell_lists(orc, hp, prec, sizes):
+    """Molecules above 128 atoms take the cutoff-cell neighbour path."""
+    torch = torch_cuda()
+    b = synth.random_batch(51 + len(sizes), sizes)
+    M = 2
+    w = synth.xavier_weights(M, hp["widths"], seed=46)
+    _, E, F = _run(torch, hp, w, M, prec, b)
+    Eo, Fo = _oracle(orc, hp, w, M, prec, b)
+    if prec == "fp64":
+        np.testing.assert_allclose(E, Eo, rtol=1e-10)
+        np.testing.assert_allclose(F, Fo, rtol=1e-8, atol=1e-9 * np.abs(Fo).max())
+    else:
+        dE, rmse = errors(E, F, Eo, Fo, b.mol_offsets)
+        print("cells fp32 |dE|/atom", dE, "RMSE", rmse)
+        assert dE.max() <= 1e-4 and rmse.max() <= 1e-3
