@@ -28,6 +28,7 @@
 // works through a contiguous range (its L2 keeps the row block and the
 // weights it shares).
 #include <algorithm>
+#include <type_traits>
 
 #include "nnp_internal.h"
 
@@ -45,8 +46,10 @@ template <> struct MF<float> {
     __device__ static Acc mma(Frag a, Frag b, Acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
-    // accumulator element r of lane l holds C[row(l, r)][l % 16]
-    __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+    // with the operands swapped (B fragment first) accumulator element r of
+    // lane l holds C[l % 16][col0(l) + r * kColStride]
+    static constexpr int kColStride = 1;
+    __device__ static int col0(int l) { return 4 * (l >> 4); }
 };
 template <> struct MF<double> {
     static constexpr int KM = 4, KL = 1;
@@ -55,8 +58,10 @@ template <> struct MF<double> {
     __device__ static Acc mma(Frag a, Frag b, Acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-    // the FP64 16x16x4 accumulator interleaves rows across the lane groups
-    __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
+    // the FP64 16x16x4 accumulator interleaves its rows across the lane
+    // groups, so a lane's four elements are every fourth column
+    static constexpr int kColStride = 4;
+    __device__ static int col0(int l) { return l >> 4; }
 };
 template <> struct MF<bf16_t> {
     static constexpr int KM = 32, KL = 8;
@@ -65,27 +70,18 @@ template <> struct MF<bf16_t> {
     __device__ static Acc mma(Frag a, Frag b, Acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
-    __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+    static constexpr int kColStride = 1;
+    __device__ static int col0(int l) { return 4 * (l >> 4); }
 };
 
-// LDS layout of a [rows][BK] operand slice.  off(r, c) = element offset of
-// the 16-byte chunk c of row r; frag(r, k) = offset of the fragment that
-// starts at column k.
-template <typename TS, int BK> struct Tile {
-    static constexpr int VE = 16 / sizeof(TS);          // elements per 16-byte chunk
-    static constexpr int CH = BK / VE;                  // chunks per row
-    static constexpr int LD = BK + VE;                  // padded row (non-bf16)
-    static constexpr int size(int rows) { return rows * LD; }
-    __device__ static int off(int r, int c) { return r * LD + c * VE; }
-    __device__ static int frag(int r, int k) { return r * LD + k; }
-};
-template <int BK> struct Tile<bf16_t, BK> {
-    static constexpr int VE = 8;
-    static constexpr int CH = BK / VE;
-    static_assert((CH & (CH - 1)) == 0, "chunks per row must be a power of two");
-    static constexpr int size(int rows) { return rows * BK; }
-    __device__ static int off(int r, int c) { return r * BK + ((c ^ (r & (CH - 1))) << 3); }
-    __device__ static int frag(int r, int k) { return off(r, k >> 3); }
+// LDS layout of one K slice of an operand: [rows][128 bytes], i.e. BK =
+// 128 / sizeof(TS) elements per row in eight 16-byte chunks; chunk c of row r
+// sits at position c ^ (r & 7), so the sixteen rows a fragment read touches
+// and the eight rows one direct-to-LDS load writes spread over all banks.
+template <typename TS> struct Slice {
+    static constexpr int VE = 16 / (int)sizeof(TS);     // elements per chunk
+    static constexpr int BK = 8 * VE;                   // elements per row
+    __device__ static int at(int r, int k) { return r * BK + ((((k / VE) ^ r) & 7) * VE) + (k % VE); }
 };
 
 enum { EPI_CELU = 0, EPI_L3F = 1, EPI_DSIG = 2, EPI_ACC = 3, EPI_RAW = 4, EPI_REV = 5 };
@@ -121,40 +117,90 @@ template <typename P> struct GemmArgs {
     int nm, nn, nz;                          // tiles along M, N and models
 };
 
-typedef int i32x4 __attribute__((ext_vector_type(4)));   // one 16-byte chunk
+// Four output elements of one row held by one lane: columns c, c+ST, c+2ST,
+// c+3ST (ST = 1 for the f32 / bf16 MFMAs, 4 for f64).
+template <typename TS, int ST> struct Quad {
+    typedef typename std::conditional<sizeof(TS) == 8, double, float>::type TA;
+    __device__ static void ld(const TS* p, TA v[4]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = Store<TS>::ld(p[r * ST]);
+    }
+    __device__ static void st(TS* p, const TA v[4]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p[r * ST] = Store<TS>::st(v[r]);
+    }
+};
+template <> struct Quad<float, 1> {
+    __device__ static void ld(const float* p, float v[4]) {
+        const float4 q = *(const float4*)p;
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    }
+    __device__ static void st(float* p, const float v[4]) { *(float4*)p = make_float4(v[0], v[1], v[2], v[3]); }
+};
+template <> struct Quad<bf16_t, 1> {
+    __device__ static void ld(const bf16_t* p, float v[4]) {
+        const uint2 q = *(const uint2*)p;
+        v[0] = bf2f((bf16_t)(q.x & 0xffffu)); v[1] = bf2f((bf16_t)(q.x >> 16));
+        v[2] = bf2f((bf16_t)(q.y & 0xffffu)); v[3] = bf2f((bf16_t)(q.y >> 16));
+    }
+    __device__ static void st(bf16_t* p, const float v[4]) {
+        uint2 q;
+        q.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+        q.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+        *(uint2*)p = q;
+    }
+};
 
 // Row tiles are grouped kGroupM at a time: within a group the schedule runs
 // M-fastest, so the tiles an XCD has in flight share both a few row blocks
 // and a few weight column blocks in its L2.
 constexpr int kGroupM = 8;
 
-template <typename P, int BM, int BN, int BK, int WM, int WN>
+template <typename P, int BM, int BN, int WM, int WN, int S>
 struct GemmShape {
     typedef typename P::TS TS;
-    typedef Tile<TS, BK> L;
     static constexpr size_t lds_bytes() {
-        return sizeof(TS) * 2 * ((size_t)L::size(BM) + (size_t)L::size(BN)) +
-               sizeof(typename P::TA) * BM * WN;
+        return (size_t)S * (BM + BN) * 128 + sizeof(typename P::TA) * BM * WN;
     }
 };
 
-template <typename P, int BM, int BN, int BK, int WM, int WN, int EPI>
+#define NNP_GPTR(p) ((const void __attribute__((address_space(1)))*)(p))
+#define NNP_LPTR(p) ((void __attribute__((address_space(3)))*)(p))
+
+// Wait until at most N of this wave's vector-memory operations are still in
+// flight and all its LDS operations have completed, then meet the other
+// waves.  Direct-to-LDS loads count as vector-memory operations and complete
+// in issue order, so N = loads issued for later slices leaves exactly those
+// in flight.  The memory clobber keeps the compiler from moving LDS accesses
+// across the barrier (a plain __syncthreads would wait for every load).
+template <int N> __device__ inline void vm_wait_barrier() {
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+// One workgroup of 4 waves computes a BM x BN tile of C = A B^T (A [rows][K],
+// B [N][K], both K-contiguous).  K streams through S LDS stages of 128-byte
+// rows, filled by direct global->LDS loads (no register staging) issued S-1
+// slices ahead.  The MFMA operands are swapped (B fragment first), so every
+// lane ends up owning four columns of one output row and the epilogue reads
+// and writes 8- or 16-byte vectors.
+template <typename P, int BM, int BN, int WM, int WN, int S, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
     typedef typename P::TS TS;
     typedef typename P::TA TA;
     typedef MF<TS> mf;
     typedef typename mf::Acc Acc;
-    typedef Tile<TS, BK> L;
+    typedef Slice<TS> L;
+    constexpr int BK = L::BK;
     constexpr int WTM = BM / WM, WTN = BN / WN, FM = WTM / 16, FN = WTN / 16;
     static_assert(WM * WN == 4 && FM >= 1 && FN >= 1, "tile");
-    constexpr int NVA = BM * L::CH, NVB = BN * L::CH;          // 16-byte chunks per slice
-    constexpr int RA = (NVA + 255) / 256, RB = (NVB + 255) / 256;
+    static_assert(S >= 2 && BM % 8 == 0 && BN % 8 == 0, "stages / rows");
+    constexpr int NQA = BM / 8, NQB = BN / 8;              // 8-row (1 KiB) loads per slice
+    constexpr int QA = (NQA + 3) / 4, QB = (NQB + 3) / 4;  // per wave (at most)
+    constexpr int QMIN = NQA / 4 + NQB / 4;                // per wave (at least)
+    constexpr int ST = mf::kColStride;
     extern __shared__ __align__(16) char smem_raw[];
-    TS* As0 = (TS*)smem_raw;
-    TS* As1 = As0 + L::size(BM);
-    TS* Bs0 = As1 + L::size(BM);
-    TS* Bs1 = Bs0 + L::size(BN);
-    TA* red = (TA*)(Bs1 + L::size(BN));                         // [BM][WN] (L3F only)
+    TS* const stage0 = (TS*)smem_raw;                      // stage s: A rows then B rows
+    TA* red = (TA*)(smem_raw + (size_t)S * (BM + BN) * 128);   // [BM][WN] (L3F only)
 
     // ---- tile schedule.  Block ids are dealt round-robin to the 8 XCDs;
     // XCD x gets the contiguous logical range it would own in order, and
@@ -173,11 +219,33 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
     if (tile_m * BM >= rows) return;
     const int s = g.tile_species[(tile_m * BM) / g.row_tile];
     if (s < 0) return;
-    const int tid = threadIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave / WN, wn = wave % WN;
 
     const TS* A = g.A + (size_t)tile_m * BM * g.lda + (size_t)z * g.a_z;
     const TS* B = g.B + (size_t)s * g.b_s + (size_t)z * g.b_z + (size_t)tile_n * BN * g.ldb;
+
+    // this lane's part of every 8-row load: row lane/8 of the group, the
+    // chunk that lands at position lane%8 of it
+    const int ld_row = lane >> 3, ld_chunk = (lane & 7) ^ (lane >> 3);
+    auto issue = [&](int kt) {
+        TS* st_ = stage0 + (size_t)(kt % S) * (BM + BN) * BK;
+        const int k0 = kt * BK + ld_chunk * L::VE;
+#pragma unroll
+        for (int u = 0; u < QA; ++u) {
+            const int q = wave + 4 * u;
+            if (NQA % 4 == 0 || q < NQA)
+                __builtin_amdgcn_global_load_lds(NNP_GPTR(A + (size_t)(q * 8 + ld_row) * g.lda + k0),
+                                                 NNP_LPTR(st_ + q * 8 * BK), 16, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < QB; ++u) {
+            const int q = wave + 4 * u;
+            if (NQB % 4 == 0 || q < NQB)
+                __builtin_amdgcn_global_load_lds(NNP_GPTR(B + (size_t)(q * 8 + ld_row) * g.ldb + k0),
+                                                 NNP_LPTR(st_ + (BM + q * 8) * BK), 16, 0, 0);
+        }
+    };
 
     Acc acc[FM][FN];
 #pragma unroll
@@ -187,124 +255,93 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-    // two register sets of prefetched K slices (slice k+2 is fetched while
-    // slice k is consumed and slice k+1 is parked in LDS)
-    i32x4 pa0[RA], pb0[RB], pa1[RA], pb1[RB];
-#define NNP_FETCH(PA, PB, kslice)                                                             \
-    {                                                                                         \
-        const int k0_ = (kslice) * BK;                                                        \
-        _Pragma("unroll") for (int u = 0; u < RA; ++u) {                                      \
-            const int v = tid + 256 * u;                                                      \
-            if (v < NVA)                                                                      \
-                PA[u] = *(const i32x4*)(A + (size_t)(v / L::CH) * g.lda + k0_ + (v % L::CH) * L::VE); \
-        }                                                                                     \
-        _Pragma("unroll") for (int u = 0; u < RB; ++u) {                                      \
-            const int v = tid + 256 * u;                                                      \
-            if (v < NVB)                                                                      \
-                PB[u] = *(const i32x4*)(B + (size_t)(v / L::CH) * g.ldb + k0_ + (v % L::CH) * L::VE); \
-        }                                                                                     \
-    }
-#define NNP_STASH(PA, PB, AS, BS)                                                             \
-    {                                                                                         \
-        _Pragma("unroll") for (int u = 0; u < RA; ++u) {                                      \
-            const int v = tid + 256 * u;                                                      \
-            if (v < NVA) *(i32x4*)(&AS[L::off(v / L::CH, v % L::CH)]) = PA[u];                \
-        }                                                                                     \
-        _Pragma("unroll") for (int u = 0; u < RB; ++u) {                                      \
-            const int v = tid + 256 * u;                                                      \
-            if (v < NVB) *(i32x4*)(&BS[L::off(v / L::CH, v % L::CH)]) = PB[u];                \
-        }                                                                                     \
-    }
-#define NNP_COMPUTE(AS, BS)                                                                   \
-    {                                                                                         \
-        _Pragma("unroll") for (int kk = 0; kk < BK; kk += mf::KM) {                          \
-            typename mf::Frag af[FM];                                                         \
-            const int kf = kk + (lane >> 4) * mf::KL;                                         \
-            _Pragma("unroll") for (int i = 0; i < FM; ++i)                                    \
-                af[i] = *(const typename mf::Frag*)(&AS[L::frag(wm * WTM + i * 16 + (lane & 15), kf)]); \
-            _Pragma("unroll") for (int j = 0; j < FN; ++j) {                                  \
-                const typename mf::Frag bfr =                                                 \
-                    *(const typename mf::Frag*)(&BS[L::frag(wn * WTN + j * 16 + (lane & 15), kf)]); \
-                _Pragma("unroll") for (int i = 0; i < FM; ++i)                                \
-                    acc[i][j] = mf::mma(af[i], bfr, acc[i][j]);                               \
-            }                                                                                 \
-        }                                                                                     \
-    }
-
     const int nk = g.K / BK;
-    NNP_FETCH(pa0, pb0, 0)
-    if (nk > 1) NNP_FETCH(pa1, pb1, 1)
-    NNP_STASH(pa0, pb0, As0, Bs0)
-    __syncthreads();
-    for (int kt = 0; kt < nk; kt += 2) {
-        // even slice kt in buffer 0; slice kt+1 waits in (pa1, pb1)
-        if (kt + 2 < nk) NNP_FETCH(pa0, pb0, kt + 2)
-        NNP_COMPUTE(As0, Bs0)
-        if (kt + 1 < nk) NNP_STASH(pa1, pb1, As1, Bs1)
-        __syncthreads();
-        if (kt + 1 >= nk) break;
-        // odd slice kt+1 in buffer 1; slice kt+2 waits in (pa0, pb0)
-        if (kt + 3 < nk) NNP_FETCH(pa1, pb1, kt + 3)
-        NNP_COMPUTE(As1, Bs1)
-        if (kt + 2 < nk) NNP_STASH(pa0, pb0, As0, Bs0)
-        __syncthreads();
+#pragma unroll
+    for (int p = 0; p < S - 1; ++p)
+        if (p < nk) issue(p);
+    for (int kt = 0; kt < nk; ++kt) {
+        // slice kt must have landed; the S-2 slices after it may stay in flight
+        if (kt + S - 2 < nk) vm_wait_barrier<QMIN * (S - 2)>();
+        else vm_wait_barrier<0>();
+        // every wave is past slice kt-1, so its stage can be refilled
+        if (kt + S - 1 < nk) issue(kt + S - 1);
+        const TS* As = stage0 + (size_t)(kt % S) * (BM + BN) * BK;
+        const TS* Bs = As + BM * BK;
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += mf::KM) {
+            const int kf = kk + (lane >> 4) * mf::KL;
+            typename mf::Frag af[FM];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                af[i] = *(const typename mf::Frag*)(&As[L::at(wm * WTM + i * 16 + (lane & 15), kf)]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const typename mf::Frag bfr =
+                    *(const typename mf::Frag*)(&Bs[L::at(wn * WTN + j * 16 + (lane & 15), kf)]);
+#pragma unroll
+                for (int i = 0; i < FM; ++i) acc[i][j] = mf::mma(bfr, af[i], acc[i][j]);
+            }
+        }
     }
-#undef NNP_FETCH
-#undef NNP_STASH
-#undef NNP_COMPUTE
 
-    // ---- epilogue: fragment element r of lane l is C[mf::row(l, r)][l % 16]
-    const int row_base = tile_m * BM + wm * WTM;
-    const int col_base = tile_n * BN + wn * WTN + (lane & 15);
+    // ---- epilogue: acc[i][j][r] of lane l is C[row_i][col_j + r * ST]
+    const int row0 = tile_m * BM + wm * WTM + (lane & 15);
+    const int col0 = tile_n * BN + wn * WTN + mf::col0(lane);
+    typedef Quad<TS, ST> Q;
     if (EPI == EPI_CELU) {
         TS* C = (TS*)g.C + (size_t)z * g.c_z;
         const TA* bias = g.bias + (size_t)s * g.bias_s + (size_t)z * g.bias_z;
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int col = col_base + j * 16;
-            const TA bb = bias[col];
+            const int col = col0 + j * 16;
+            TA bb[4];
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+            for (int r = 0; r < 4; ++r) bb[r] = bias[col + r * ST];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = row_base + i * 16 + mf::row(lane, r);
-                    C[(size_t)row * g.ldc + col] = Store<TS>::st(celu((TA)acc[i][j][r] + bb, g.alpha));
-                }
+            for (int i = 0; i < FM; ++i) {
+                TA v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = celu((TA)acc[i][j][r] + bb[r], g.alpha);
+                Q::st(C + (size_t)(row0 + i * 16) * g.ldc + col, v);
+            }
         }
     } else if (EPI == EPI_ACC) {
         TA* C = (TA*)g.C + (size_t)z * g.c_z;
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FM; ++i) {
+                TA v[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    C[(size_t)(row_base + i * 16 + mf::row(lane, r)) * g.ldc + col_base + j * 16] =
-                        (TA)acc[i][j][r];
+                for (int r = 0; r < 4; ++r) v[r] = (TA)acc[i][j][r];
+                Quad<TA, ST>::st(C + (size_t)(row0 + i * 16) * g.ldc + col0 + j * 16, v);
+            }
     } else if (EPI == EPI_DSIG) {
         TS* C = (TS*)g.C + (size_t)z * g.c_z;
         const TS* Hr = g.Hr + (size_t)z * g.h_z;
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FM; ++i) {
+                const size_t row = row0 + i * 16;
+                const int col = col0 + j * 16;
+                TA hh[4], v[4];
+                Q::ld(Hr + row * g.ldh + col, hh);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const size_t row = row_base + i * 16 + mf::row(lane, r);
-                    const int col = col_base + j * 16;
-                    const TA hh = Store<TS>::ld(Hr[row * g.ldh + col]);
-                    C[row * g.ldc + col] = Store<TS>::st((TA)acc[i][j][r] * dcelu_h(hh, g.alpha));
-                }
+                for (int r = 0; r < 4; ++r) v[r] = (TA)acc[i][j][r] * dcelu_h(hh[r], g.alpha);
+                Q::st(C + row * g.ldc + col, v);
+            }
     } else if (EPI == EPI_RAW) {
         TS* C = (TS*)g.C + (size_t)z * g.c_z;
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FM; ++i) {
+                TA v[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    C[(size_t)(row_base + i * 16 + mf::row(lane, r)) * g.ldc + col_base + j * 16] =
-                        Store<TS>::st((TA)acc[i][j][r]);
+                for (int r = 0; r < 4; ++r) v[r] = (TA)acc[i][j][r];
+                Q::st(C + (size_t)(row0 + i * 16) * g.ldc + col0 + j * 16, v);
+            }
     } else if (EPI == EPI_REV) {
         // reverse step through h = CELU(z) and its tangent hdot = CELU'(z) zdot:
         //   zbar    = abar CELU'(z) + acheck (CELU''/CELU')(z) hdot
@@ -319,54 +356,60 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FM; ++i) {
+                const size_t row = row0 + i * 16;
+                const int col = col0 + j * 16;
+                TA hh[4], ac[4], hd[4], v[4], v2[4];
+                Q::ld(Hr + row * g.ldh + col, hh);
+                Q::ld(X + row * g.ldx + col, ac);
+                Q::ld(Tr + row * g.ldt + col, hd);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const size_t row = row_base + i * 16 + mf::row(lane, r);
-                    const int col = col_base + j * 16;
-                    const TA hh = Store<TS>::ld(Hr[row * g.ldh + col]);
-                    const TA ac = Store<TS>::ld(X[row * g.ldx + col]);
-                    const TA hd = Store<TS>::ld(Tr[row * g.ldt + col]);
-                    const TA d1 = dcelu_h(hh, g.alpha);
-                    const TA rho = hh < TA(0) ? TA(1) / g.alpha : TA(0);
-                    C[row * g.ldc + col] = Store<TS>::st((TA)acc[i][j][r] * d1 + ac * rho * hd);
-                    C2[row * g.ldc + col] = Store<TS>::st(ac * d1);
+                    const TA d1 = dcelu_h(hh[r], g.alpha);
+                    const TA rho = hh[r] < TA(0) ? TA(1) / g.alpha : TA(0);
+                    v[r] = (TA)acc[i][j][r] * d1 + ac[r] * rho * hd[r];
+                    v2[r] = ac[r] * d1;
                 }
+                Q::st(C + row * g.ldc + col, v);
+                Q::st(C2 + row * g.ldc + col, v2);
+            }
     } else {   // EPI_L3F
         TS* C = (TS*)g.C + (size_t)z * g.c_z;
         const TA* bias = g.bias + (size_t)s * g.bias_s + (size_t)z * g.bias_z;
         const TA* w4 = g.w4 + (size_t)s * g.w4_s + (size_t)z * g.w4_z;
-        TA part[FM][4];
+        TA part[FM];
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) part[i][r] = 0;
+        for (int i = 0; i < FM; ++i) part[i] = 0;
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int col = col_base + j * 16;
-            const TA bb = bias[col], ww = w4[col];
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = row_base + i * 16 + mf::row(lane, r);
-                    const TA zz = (TA)acc[i][j][r] + bb;
-                    part[i][r] += ww * celu(zz, g.alpha);
-                    C[(size_t)row * g.ldc + col] = Store<TS>::st(dcelu_z(zz, g.alpha) * ww * g.gscale);
-                }
-        }
-        // sum over the 16 columns held by lanes with equal lane/16
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
+            const int col = col0 + j * 16;
+            TA bb[4], ww[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                TA v = part[i][r];
-                v += __shfl_xor(v, 1);
-                v += __shfl_xor(v, 2);
-                v += __shfl_xor(v, 4);
-                v += __shfl_xor(v, 8);
-                if ((lane & 15) == 0) red[(wm * WTM + i * 16 + mf::row(lane, r)) * WN + wn] = v;
+                bb[r] = bias[col + r * ST];
+                ww[r] = w4[col + r * ST];
             }
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                TA v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const TA zz = (TA)acc[i][j][r] + bb[r];
+                    part[i] += ww[r] * celu(zz, g.alpha);
+                    v[r] = dcelu_z(zz, g.alpha) * ww[r] * g.gscale;
+                }
+                Q::st(C + (size_t)(row0 + i * 16) * g.ldc + col, v);
+            }
+        }
+        // sum over the four lane groups (same row, different columns), then
+        // over the WN waves that share the row
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            TA v = part[i];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < 16) red[(wm * WTM + i * 16 + lane) * WN + wn] = v;
+        }
         __syncthreads();
         for (int rr = tid; rr < BM; rr += 256) {
             TA v = 0;
@@ -379,15 +422,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename P, int BM, int BN, int BK, int WM, int WN, int EPI>
+template <typename P, int BM, int BN, int WM, int WN, int S, int EPI>
 static hipError_t run_gemm(GemmArgs<P> a, int Rcap, int N, int nz, hipStream_t st,
                            const Timer& tm, const char* name) {
     a.nm = Rcap / BM;
     a.nn = N / BN;
     a.nz = nz;
+    if (a.K % Slice<typename P::TS>::BK != 0 || N % BN != 0 || Rcap % BM != 0) return hipErrorInvalidValue;
     const int T = a.nm * a.nn * a.nz;
-    const size_t lds = GemmShape<P, BM, BN, BK, WM, WN>::lds_bytes();
-    auto kern = k_gemm<P, BM, BN, BK, WM, WN, EPI>;
+    const size_t lds = GemmShape<P, BM, BN, WM, WN, S>::lds_bytes();
+    auto kern = k_gemm<P, BM, BN, WM, WN, S, EPI>;
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b(name, st);
@@ -396,21 +440,14 @@ static hipError_t run_gemm(GemmArgs<P> a, int Rcap, int N, int nz, hipStream_t s
     return hipGetLastError();
 }
 
-// tile shapes per precision and row tile: BM = row tile; wide N tiles for
-// the layer-1 GEMMs, 64-wide for the per-model layers (widths 192 / 256)
+// tile shapes per row tile: BM = row tile; wide N tiles for the layer-1
+// GEMMs, 64-wide for the per-model layers (widths 192 / 256); S LDS stages
 template <typename P, int BM> struct Cfg;
-template <> struct Cfg<PrecBF16, 128> {
-    static constexpr int BK = 64, BNW = 128, BNN = 64, WM = 2, WN = 2;
-};
-template <> struct Cfg<PrecF32, 128> {
-    static constexpr int BK = 32, BNW = 128, BNN = 64, WM = 2, WN = 2;
-};
-template <> struct Cfg<PrecF64, 128> {
-    static constexpr int BK = 16, BNW = 64, BNN = 64, WM = 2, WN = 2;
+template <typename P> struct Cfg<P, 128> {
+    static constexpr int BNW = sizeof(typename P::TS) == 8 ? 64 : 128, BNN = 64, WM = 2, WN = 2, S = 3;
 };
 template <typename P> struct Cfg<P, 16> {
-    static constexpr int BK = sizeof(typename P::TS) == 2 ? 64 : (sizeof(typename P::TS) == 4 ? 32 : 16);
-    static constexpr int BNW = 64, BNN = 64, WM = 1, WN = 4;
+    static constexpr int BNW = 64, BNN = 64, WM = 1, WN = 4, S = 3;
 };
 
 template <typename P, int BM>
@@ -438,9 +475,9 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     a.C = w.H1; a.ldc = M * H1; a.c_z = 0;
     a.K = Dp;
     if ((M * H1) % C::BNW == 0)
-        e = run_gemm<P, BM, C::BNW, C::BK, C::WM, C::WN, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd");
+        e = run_gemm<P, BM, C::BNW, C::WM, C::WN, C::S, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd");
     else
-        e = run_gemm<P, BM, C::BNN, C::BK, C::WM, C::WN, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd");
+        e = run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd");
     if (e) return e;
     // L2f
     a = base;
@@ -449,7 +486,7 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     a.bias = wt.b2; a.bias_s = (long)M * H2; a.bias_z = H2;
     a.C = w.H2; a.ldc = M * H2; a.c_z = H2;
     a.K = H1;
-    if ((e = run_gemm<P, BM, C::BNN, C::BK, C::WM, C::WN, EPI_CELU>(a, R, H2, M, st, tm, "mlp_l2_fwd")))
+    if ((e = run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_CELU>(a, R, H2, M, st, tm, "mlp_l2_fwd")))
         return e;
     // L3f (+ output layer, + dE/dz3)
     a = base;
@@ -460,7 +497,7 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     a.C = w.DZ3; a.ldc = M * H3; a.c_z = H3;
     a.epart = w.Epart;
     a.K = H2;
-    if ((e = run_gemm<P, BM, 64, C::BK, C::WM, C::WN, EPI_L3F>(a, R, H3, M, st, tm, "mlp_l3_fwd")))
+    if ((e = run_gemm<P, BM, 64, C::WM, C::WN, C::S, EPI_L3F>(a, R, H3, M, st, tm, "mlp_l3_fwd")))
         return e;
     // L3b
     a = base;
@@ -469,7 +506,7 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     a.Hr = w.H2; a.ldh = M * H2; a.h_z = H2;
     a.C = w.DZ2; a.ldc = M * H2; a.c_z = H2;
     a.K = H3;
-    if ((e = run_gemm<P, BM, C::BNN, C::BK, C::WM, C::WN, EPI_DSIG>(a, R, H2, M, st, tm, "mlp_l3_bwd")))
+    if ((e = run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_DSIG>(a, R, H2, M, st, tm, "mlp_l3_bwd")))
         return e;
     // L2b
     a = base;
@@ -479,9 +516,9 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     a.C = w.DZ1; a.ldc = M * H1; a.c_z = H1;
     a.K = H2;
     if (H1 % C::BNW == 0)
-        e = run_gemm<P, BM, C::BNW, C::BK, C::WM, C::WN, EPI_DSIG>(a, R, H1, M, st, tm, "mlp_l2_bwd");
+        e = run_gemm<P, BM, C::BNW, C::WM, C::WN, C::S, EPI_DSIG>(a, R, H1, M, st, tm, "mlp_l2_bwd");
     else
-        e = run_gemm<P, BM, C::BNN, C::BK, C::WM, C::WN, EPI_DSIG>(a, R, H1, M, st, tm, "mlp_l2_bwd");
+        e = run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_DSIG>(a, R, H1, M, st, tm, "mlp_l2_bwd");
     if (e) return e;
     // L1b
     a = base;
@@ -490,9 +527,9 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     a.C = w.dG; a.ldc = Dp; a.c_z = 0;
     a.K = M * H1;
     if (Dp % C::BNW == 0)
-        e = run_gemm<P, BM, C::BNW, C::BK, C::WM, C::WN, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
+        e = run_gemm<P, BM, C::BNW, C::WM, C::WN, C::S, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
     else
-        e = run_gemm<P, BM, C::BNN, C::BK, C::WM, C::WN, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
+        e = run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
     return e;
 }
 
@@ -521,7 +558,7 @@ static hipError_t train_mlp(const Shape& sh, const DevWeights<P>& wt, Work<P>& w
     base.nt = H3 / 64;
     GemmArgs<P> a;
 #define NNP_RUN(EPI, N, NZ, NAME)                                                               \
-    if ((e = run_gemm<P, BM, BN, C::BK, C::WM, C::WN, EPI>(a, R, N, NZ, st, tm, NAME))) return e;
+    if ((e = run_gemm<P, BM, BN, C::WM, C::WN, C::S, EPI>(a, R, N, NZ, st, tm, NAME))) return e;
 
     // forward: H1, H2, H3
     a = base;

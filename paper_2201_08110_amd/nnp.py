@@ -239,13 +239,18 @@ class NNP:
         self._synced = None
 
     def sync_params(self, params):
-        """Upload a torch tensor of packed master weights if it changed since
-        the last upload (tracked by storage pointer and in-place version)."""
+        """Upload a torch tensor of packed master weights unless it is the very
+        tensor object uploaded last time with no in-place change since (torch's
+        version counter).  The handle keeps a reference to that tensor, so a
+        new tensor can never be mistaken for it through a reused address.
+        Writes that bypass the version counter (through `.data`) are not seen:
+        call set_weights after those."""
         import torch
-        key = (params.data_ptr(), params._version)
-        if getattr(self, "_synced", None) != key:
-            self.set_weights(params.detach().to("cpu", dtype=torch.float64).numpy())
-            self._synced = key
+        last = getattr(self, "_synced", None)
+        if last is not None and last[0] is params and last[1] == params._version:
+            return
+        self.set_weights(params.detach().to("cpu", dtype=torch.float64).numpy())
+        self._synced = (params, params._version)
 
     @property
     def num_params(self) -> int:
