@@ -203,6 +203,48 @@ nnp_status nnp_set_timing(nnp_handle* h, int32_t enable);
 int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t* counts,
                          double* total_ms);
 
+/* ---- tunable variants (the autotuner) -------------------------------------
+ * Kernel variants that compute the same quantities (results differ only by
+ * floating-point summation order) and differ in speed.  Every knob starts at
+ * 0, the built-in automatic choice; nnp_get_knob reports the value in effect.
+ *
+ *   NNP_KNOB_MLP_PATH     1 = layers 2-3 forward and backward fused in one
+ *                             kernel per row tile and model (hidden widths
+ *                             256-192-{160..192} only),
+ *                         2 = one GEMM per layer and direction.
+ *                         auto: 1 when supported and the handle batches
+ *                         (max_atoms > 256, not FP64), else 2.
+ *   NNP_KNOB_GEMM_STAGES  LDS pipeline depth of the layer-1 GEMMs: 2 or 3
+ *                         (auto 3).
+ *   NNP_KNOB_CELL_MIN     molecules with more atoms than this build their
+ *                         neighbour lists through cutoff cells, smaller ones
+ *                         scan all atoms: 16..1024 (auto 128).
+ *
+ * Setting a knob drops the handle's captured graphs.  Invalid knob ids or
+ * values return NNP_E_INVALID (a fused path on unsupported widths returns
+ * NNP_E_UNSUPPORTED). */
+enum {
+    NNP_KNOB_MLP_PATH = 0,
+    NNP_KNOB_GEMM_STAGES = 1,
+    NNP_KNOB_CELL_MIN = 2,
+    NNP_N_KNOBS = 3
+};
+nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value);
+nnp_status nnp_get_knob(nnp_handle* h, int32_t knob, int32_t* value);
+
+/* Autotuner: times the candidates of every knob on this batch (one warm-up
+ * and `reps` evaluations each, HIP events on the batch's stream), knob by
+ * knob, and keeps the fastest on the handle.  coords are float (double for
+ * FP64 handles).  If cache_path is non-NULL the choice is looked up first in
+ * that file (JSON lines, one object per key: device architecture, precision,
+ * model shape and capacity) and, when tuned afresh, appended to it.  If
+ * report is non-NULL a JSON object with the key, the chosen values and the
+ * timings of every candidate (microseconds per evaluation) is written into it
+ * (truncated to report_cap bytes).  Allocates temporary outputs; synchronises
+ * the stream; not for use under graph capture. */
+nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, int32_t reps,
+                        const char* cache_path, char* report, int32_t report_cap);
+
 /* Message of the calling thread's last host-side error ("" if none). */
 const char* nnp_last_error(void);
 

@@ -242,7 +242,6 @@ constexpr int kChunk = 16;     // central atoms per AEV / force workgroup
 constexpr int kWaves = 4;
 constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
 
-constexpr int kCellMin = 128;       // molecules larger than this use cutoff cells
 constexpr int kMaxCellsPerDim = 6;  // cells per dimension (cell edge >= rcr)
 
 template <typename T>
@@ -257,7 +256,8 @@ __device__ inline T wave_max(T v) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, int cap, T rcr, T rca2,
+__global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, int cell_min, int cap,
+                                                   T rcr, T rca2,
                                                    T rcr2, const int32_t* __restrict__ mol_off,
                                                    const int32_t* __restrict__ species,
                                                    const T* __restrict__ x, T* __restrict__ F,
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
     const int i0 = blockIdx.y * kNbrChunk;
     if (i0 >= n) return;
     const int lane = lane_id();
-    const bool cells = n > kCellMin;
+    const bool cells = n > cell_min;   // larger molecules use cutoff cells
     LdsBump lb(smem);
     T* sx = lb.take<T>(4 * (size_t)max_apm);            // staged atoms: x y z
     int* sid = lb.take<int>(max_apm);                   // local index of the k-th staged atom
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
     int* kstart = nullptr;                              // [nkeys+1] bucket starts (cells)
     int* kcur = nullptr;                                // [nkeys]   scatter cursors
     int* akey = nullptr;                                // [max_apm] key of every atom
-    if (max_apm > kCellMin) {
+    if (max_apm > cell_min) {
         kstart = lb.take<int>(kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim + 1);
         kcur = lb.take<int>(kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim);
         akey = lb.take<int>(max_apm);
@@ -445,14 +445,14 @@ hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
     const int nkeys = kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim;
     size_t lds = lds_bytes<T>(4 * (size_t)sh.max_apm) + lds_bytes<int>(sh.max_apm) +
                  lds_bytes<uint16_t>((size_t)kNbrChunk * sh.cap_nbr);
-    if (sh.max_apm > kCellMin)
+    if (sh.max_apm > sh.cell_min)
         lds += lds_bytes<int>(nkeys + 1) + lds_bytes<int>(nkeys) + lds_bytes<int>(sh.max_apm);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     hipError_t e = ensure_lds((const void*)k_neighbours<T>, lds);
     if (e != hipSuccess) return e;
     tm.b("neighbours", st);
     hipLaunchKernelGGL(k_neighbours<T>, grid, dim3(64), lds, st, sh.A, sh.S, sh.max_apm,
-                       sh.cap_nbr, c.rcr, c.rca2, c.rcr2, mol_off, species, x, F, w.nbr,
+                       sh.cell_min, sh.cap_nbr, c.rcr, c.rca2, c.rcr2, mol_off, species, x, F, w.nbr,
                        w.nbr_cnt, w.flag);
     tm.e("neighbours", st);
     return hipGetLastError();
@@ -1157,7 +1157,7 @@ hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t
                          const Timer& tm) {
     tm.b("energy", st);
     hipLaunchKernelGGL(k_energy<P>, dim3((sh.B + 3) / 4), dim3(256), 0, st, sh.A, sh.B, sh.M,
-                       sh.H3 / 64, sh.energy_scale, mol_off, species, sh.S, w.row_of_atom,
+                       w.epart_nt, sh.energy_scale, mol_off, species, sh.S, w.row_of_atom,
                        w.Epart, wt.b4, wt.sae, E);
     tm.e("energy", st);
     return hipGetLastError();

@@ -112,7 +112,8 @@ template <typename P> struct Work {
     TS* DZ3;                // [Rcap][M*H3]
     TS* DZ2;                // [Rcap][M*H2]
     TS* DZ1;                // [Rcap][M*H1]
-    TA* Epart;              // [Rcap][M][H3/64]
+    TA* Epart;              // [Rcap][M][epart_nt]  per-row energy partials
+    int epart_nt;           // partials per row and model (set by launch_mlp)
     TA* dG;                 // [Rcap][Dp]
 };
 
@@ -156,6 +157,10 @@ struct Shape {
     int max_apm;
     double energy_scale;
     double celu_alpha;
+    // kernel variants in effect (resolved tunable knobs)
+    int mlp_fused;                     // 1: fused layers 2-3 kernel, 0: per-layer GEMMs
+    int gemm_stages;                   // LDS stages of the layer-1 GEMMs (2 or 3)
+    int cell_min;                      // molecules above this many atoms use cutoff cells
 };
 
 // kernel timing hook (runtime-side); launchers call these around launches
@@ -196,6 +201,9 @@ template <typename P>
 hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
                       const int32_t* species, const typename P::T* x, Work<P>& w,
                       typename P::T* aev_out, hipStream_t st, const Timer& tm);
+// hidden widths (padded) the fused layers 2-3 kernel is compiled for
+bool mlp_fused_supported(int H1, int H2, int H3);
+
 template <typename P>
 hipError_t launch_mlp(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipStream_t st,
                       const Timer& tm);

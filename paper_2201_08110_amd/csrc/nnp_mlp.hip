@@ -450,6 +450,342 @@ template <typename P> struct Cfg<P, 16> {
     static constexpr int BNW = 64, BNN = 64, WM = 1, WN = 4, S = 3;
 };
 
+// ---------------------------------------------------------------------------
+// Fused tail of the ensemble for energies and forces: for one row tile of one
+// element bucket and one model it runs layers 2 and 3, the output layer, and
+// the backward through layers 3 and 2, keeping every intermediate in LDS:
+//
+//   H2  = celu(H1 W2^T + b2)                 -> LDS
+//   z3  = H2 W3^T + b3;  e = w4 . celu(z3)   -> per-row energy partial
+//   DZ3 = celu'(z3) w4 gscale                -> LDS
+//   DZ2 = (DZ3 W3) celu'(H2)                 -> LDS (over H2)
+//   DZ1 = (DZ2 W2) celu'(H1)                 -> HBM
+//
+// so HBM sees H1 once and DZ1 once per row and model.  The four waves split
+// every product 1 x 4 along N: each wave needs only its own columns of the
+// weights, so weight fragments go from L2 straight into registers (no LDS
+// staging), while the activation operand is shared through LDS.  LDS tiles
+// use the sliced layout of the GEMMs: [K / BK][rows][BK], 16-byte chunks
+// XOR-swizzled by row.
+template <typename TS> struct Sliced {
+    static constexpr int VE = 16 / (int)sizeof(TS);
+    static constexpr int BK = 8 * VE;
+    __device__ static int at(int rows, int r, int k) {
+        return (k / BK) * rows * BK + r * BK + ((((k % BK) / VE) ^ r) & 7) * VE + (k % VE);
+    }
+};
+
+// acc = A (LDS, sliced, BM rows, K columns) x B^T, B rows n0 + [0, 16 FN)
+// of a K-contiguous matrix in global memory (leading dimension ldb).  The B
+// fragments of k-step t+2 are requested before the MFMAs of step t; the empty
+// asm with a memory clobber keeps the compiler from sinking those loads next
+// to their use, so about two k-steps of MFMAs cover the L2 latency.
+template <typename TS, int FM, int FN, int K>
+__device__ inline void tail_product(typename MF<TS>::Acc (&acc)[FM][FN], const TS* As,
+                                    const TS* __restrict__ Bg, int ldb, int n0, int lane) {
+    typedef MF<TS> mf;
+    typedef Sliced<TS> L;
+    typedef typename mf::Frag Frag;
+    constexpr int BM = 16 * FM, NS = K / mf::KM, PD = 2;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+    const TS* Brow = Bg + (size_t)(n0 + (lane & 15)) * ldb + (lane >> 4) * mf::KL;
+    Frag bq[PD + 1][FN];
+#pragma unroll
+    for (int t = 0; t < PD && t < NS; ++t)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bq[t][j] = *(const Frag*)(Brow + (size_t)j * 16 * ldb + t * mf::KM);
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        if (t + PD < NS) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                bq[(t + PD) % (PD + 1)][j] = *(const Frag*)(Brow + (size_t)j * 16 * ldb + (t + PD) * mf::KM);
+        }
+        asm volatile("" ::: "memory");
+        const int kf = t * mf::KM + (lane >> 4) * mf::KL;
+        Frag af[FM];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) af[i] = *(const Frag*)(&As[L::at(BM, i * 16 + (lane & 15), kf)]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int i = 0; i < FM; ++i) acc[i][j] = mf::mma(bq[t % (PD + 1)][j], af[i], acc[i][j]);
+    }
+}
+
+// four values of one row at columns c, c+ST, c+2ST, c+3ST of a sliced LDS tile
+template <typename TS, int ST> struct LdsQuad {
+    typedef typename std::conditional<sizeof(TS) == 8, double, float>::type TA;
+    __device__ static void ld(const TS* T, int rows, int r, int c, TA v[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = Store<TS>::ld(T[Sliced<TS>::at(rows, r, c + q * ST)]);
+    }
+    __device__ static void st(TS* T, int rows, int r, int c, const TA v[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) T[Sliced<TS>::at(rows, r, c + q * ST)] = Store<TS>::st(v[q]);
+    }
+};
+// contiguous case: c % 4 == 0 keeps the four values inside one 16-byte chunk
+template <typename TS> struct LdsQuad<TS, 1> {
+    typedef float TA;
+    __device__ static void ld(const TS* T, int rows, int r, int c, TA v[4]) {
+        Quad<TS, 1>::ld(T + Sliced<TS>::at(rows, r, c), v);
+    }
+    __device__ static void st(TS* T, int rows, int r, int c, const TA v[4]) {
+        Quad<TS, 1>::st(T + Sliced<TS>::at(rows, r, c), v);
+    }
+};
+
+template <typename P> struct TailArgs {
+    typedef typename P::TS TS;
+    typedef typename P::TA TA;
+    const TS* H1; TS* DZ1; int ldh;          // [Rcap][M*H1]
+    const TS* W2; const TS* W2T; const TA* b2;
+    const TS* W3; const TS* W3T; const TA* b3; const TA* w4;
+    TA* epart;                                // [Rcap][M]
+    TA gscale, alpha;
+    int M;
+    const int32_t* tile_species; int row_tile;
+    const BucketInfo* info;
+    int nm;                                   // row tiles
+};
+
+template <typename P, int BM, int H1, int H2, int H3>
+struct TailShape {
+    typedef typename P::TS TS;
+    static constexpr size_t hs = (size_t)BM * H2 * sizeof(TS);
+    static constexpr size_t u1 = (size_t)BM * H1 * sizeof(TS), u2 = (size_t)BM * H3 * sizeof(TS);
+    static constexpr size_t lds_bytes() { return hs + (u1 > u2 ? u1 : u2) + sizeof(typename P::TA) * BM * 4; }
+};
+
+template <typename P, int BM, int H1, int H2, int H3>
+__global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
+    typedef typename P::TS TS;
+    typedef typename P::TA TA;
+    typedef MF<TS> mf;
+    typedef typename mf::Acc Acc;
+    typedef Sliced<TS> L;
+    constexpr int FM = BM / 16, ST = mf::kColStride;
+    static_assert(H1 % 64 == 0 && H2 % 64 == 0 && H3 % 64 == 0 && BM % 16 == 0, "widths");
+    typedef TailShape<P, BM, H1, H2, H3> Sh;
+    extern __shared__ __align__(16) char smem_raw[];
+    TS* Hs = (TS*)smem_raw;                              // H2, later DZ2   [BM][H2]
+    TS* Us = (TS*)(smem_raw + Sh::hs);                   // H1 tile, later DZ3
+    TA* red = (TA*)(smem_raw + Sh::hs + (Sh::u1 > Sh::u2 ? Sh::u1 : Sh::u2));   // [BM][4]
+
+    // XCD-contiguous ranges over (model, row tile): an XCD works through
+    // consecutive tiles of one model and keeps that model's weights in L2
+    const int T = g.nm * g.M;
+    const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
+    const int q8 = T >> 3, r8 = T & 7;
+    const int lin = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+    const int z = lin / g.nm, tile_m = lin % g.nm;
+    const int row0 = tile_m * BM;
+    if (row0 >= g.info->rows) return;
+    const int s = g.tile_species[row0 / g.row_tile];
+    if (s < 0) return;
+    const int tid = threadIdx.x, lane = threadIdx.x & 63;
+    const int wn = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const size_t sz = (size_t)s * g.M + z;
+
+    // H1 tile -> LDS (sliced), direct loads: per K slice BM/8 loads of 8 rows
+    {
+        const TS* src0 = g.H1 + (size_t)row0 * g.ldh + (size_t)z * H1;
+        const int lr = lane >> 3, lc = (lane & 7) ^ (lane >> 3);
+        constexpr int NQ = (H1 / L::BK) * (BM / 8);
+#pragma unroll
+        for (int u = 0; u < (NQ + 3) / 4; ++u) {
+            const int q = wn + 4 * u;
+            if (NQ % 4 == 0 || q < NQ) {
+                const int t = q / (BM / 8), rq = q % (BM / 8);
+                const TS* src = src0 + (size_t)(rq * 8 + lr) * g.ldh + t * L::BK + lc * L::VE;
+                __builtin_amdgcn_global_load_lds(NNP_GPTR(src), NNP_LPTR(Us + (t * BM + rq * 8) * L::BK), 16, 0, 0);
+            }
+        }
+        vm_wait_barrier<0>();
+    }
+    const int rl = lane & 15;                 // this lane's row within each 16-row fragment
+    const int cl = mf::col0(lane);            // and its first column within each 16 columns
+
+    // ---- layer 2 forward
+    {
+        constexpr int FN = H2 / 64;
+        Acc acc[FM][FN];
+        const int n0 = wn * (H2 / 4);
+        tail_product<TS, FM, FN, H1>(acc, Us, g.W2 + sz * H2 * H1, H1, n0, lane);
+        const TA* b2 = g.b2 + sz * H2;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int c = n0 + j * 16 + cl;
+            TA bb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bb[q] = b2[c + q * ST];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                TA v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = celu((TA)acc[i][j][q] + bb[q], g.alpha);
+                LdsQuad<TS, ST>::st(Hs, BM, i * 16 + rl, c, v);
+            }
+        }
+    }
+    __syncthreads();   // H2 complete; the H1 tile is dead from here on
+    // ---- layer 3 forward, output layer, dE/dz3
+    {
+        constexpr int FN = H3 / 64;
+        Acc acc[FM][FN];
+        const int n0 = wn * (H3 / 4);
+        tail_product<TS, FM, FN, H2>(acc, Hs, g.W3 + sz * H3 * H2, H2, n0, lane);
+        const TA* b3 = g.b3 + sz * H3;
+        const TA* w4 = g.w4 + sz * H3;
+        TA part[FM];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) part[i] = 0;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int c = n0 + j * 16 + cl;
+            TA bb[4], ww[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                bb[q] = b3[c + q * ST];
+                ww[q] = w4[c + q * ST];
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                TA v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const TA zz = (TA)acc[i][j][q] + bb[q];
+                    part[i] += ww[q] * celu(zz, g.alpha);
+                    v[q] = dcelu_z(zz, g.alpha) * ww[q] * g.gscale;
+                }
+                LdsQuad<TS, ST>::st(Us, BM, i * 16 + rl, c, v);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            TA v = part[i];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < 16) red[(i * 16 + lane) * 4 + wn] = v;
+        }
+    }
+    __syncthreads();   // DZ3 and the energy partials complete
+    if (tid < BM) {
+        const TA e = red[tid * 4] + red[tid * 4 + 1] + red[tid * 4 + 2] + red[tid * 4 + 3];
+        g.epart[(size_t)(row0 + tid) * g.M + z] = e;
+    }
+    // ---- layer 3 backward: DZ2 = (DZ3 W3) celu'(H2), in place of H2 (each
+    // lane reads and then overwrites only its own elements; every wave is done
+    // reading H2 as an operand)
+    {
+        constexpr int FN = H2 / 64;
+        Acc acc[FM][FN];
+        const int n0 = wn * (H2 / 4);
+        tail_product<TS, FM, FN, H3>(acc, Us, g.W3T + sz * H2 * H3, H3, n0, lane);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int c = n0 + j * 16 + cl;
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                TA hh[4], v[4];
+                LdsQuad<TS, ST>::ld(Hs, BM, i * 16 + rl, c, hh);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = (TA)acc[i][j][q] * dcelu_h(hh[q], g.alpha);
+                LdsQuad<TS, ST>::st(Hs, BM, i * 16 + rl, c, v);
+            }
+        }
+    }
+    __syncthreads();   // DZ2 complete
+    // ---- layer 2 backward: DZ1 = (DZ2 W2) celu'(H1) -> HBM
+    {
+        constexpr int FN = H1 / 64;
+        Acc acc[FM][FN];
+        const int n0 = wn * (H1 / 4);
+        const TS* Hr = g.H1 + (size_t)row0 * g.ldh + (size_t)z * H1;
+        TS* Out = g.DZ1 + (size_t)row0 * g.ldh + (size_t)z * H1;
+        // CELU'(H1) operands of the epilogue, fetched ahead of the product
+        TA hh[FM][FN][4];
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                Quad<TS, ST>::ld(Hr + (size_t)(i * 16 + rl) * g.ldh + n0 + j * 16 + cl, hh[i][j]);
+        tail_product<TS, FM, FN, H2>(acc, Hs, g.W2T + sz * H1 * H2, H2, n0, lane);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int c = n0 + j * 16 + cl;
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                TA v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = (TA)acc[i][j][q] * dcelu_h(hh[i][j][q], g.alpha);
+                Quad<TS, ST>::st(Out + (size_t)(i * 16 + rl) * g.ldh + c, v);
+            }
+        }
+    }
+}
+
+// the fused tail is compiled for the ANI-2x hidden widths (256, 192, 160
+// padded to 192); other widths take the per-layer GEMMs
+constexpr int kTailH1 = 256, kTailH2 = 192, kTailH3 = 192;
+
+template <typename P, int BM>
+static hipError_t run_tail(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipStream_t st,
+                           const Timer& tm) {
+    typedef typename P::TA TA;
+    TailArgs<P> a{};
+    a.H1 = w.H1; a.DZ1 = w.DZ1; a.ldh = sh.M * sh.H1;
+    a.W2 = wt.W2; a.W2T = wt.W2T; a.b2 = wt.b2;
+    a.W3 = wt.W3; a.W3T = wt.W3T; a.b3 = wt.b3; a.w4 = wt.w4;
+    a.epart = w.Epart;
+    a.gscale = (TA)(sh.energy_scale / sh.M);
+    a.alpha = (TA)sh.celu_alpha;
+    a.M = sh.M;
+    a.tile_species = w.tile_species; a.row_tile = sh.row_tile;
+    a.info = w.info;
+    a.nm = sh.Rcap / BM;
+    const int T = a.nm * sh.M;
+    const size_t lds = TailShape<P, BM, kTailH1, kTailH2, kTailH3>::lds_bytes();
+    auto kern = k_tail<P, BM, kTailH1, kTailH2, kTailH3>;
+    hipError_t e = ensure_lds((const void*)kern, lds);
+    if (e != hipSuccess) return e;
+    tm.b("mlp_tail", st);
+    hipLaunchKernelGGL(kern, dim3(T), dim3(256), lds, st, a);
+    tm.e("mlp_tail", st);
+    return hipGetLastError();
+}
+
+bool mlp_fused_supported(int H1, int H2, int H3) {
+    return H1 == kTailH1 && H2 == kTailH2 && H3 == kTailH3;
+}
+
+// tail row tile per precision: equal LDS bytes (H1 tile of 32 KiB)
+template <typename P> struct TailBM { static constexpr int v = 128 / (int)sizeof(typename P::TS); };
+
+// L1b: dG = DZ1cat W1cat (models summed along K)
+template <typename P, int BM>
+static hipError_t mlp_l1_bwd(const Shape& sh, const DevWeights<P>& wt, Work<P>& w,
+                             const GemmArgs<P>& base, hipStream_t st, const Timer& tm) {
+    typedef Cfg<P, BM> C;
+    const int M = sh.M, H1 = sh.H1, Dp = sh.Dp, R = sh.Rcap;
+    GemmArgs<P> a = base;
+    a.A = w.DZ1; a.lda = M * H1; a.a_z = 0;
+    a.B = wt.W1T; a.ldb = M * H1; a.b_s = (long)Dp * M * H1; a.b_z = 0;
+    a.C = w.dG; a.ldc = Dp; a.c_z = 0;
+    a.K = M * H1;
+    if (Dp % C::BNW == 0)
+        return sh.gemm_stages == 2
+                   ? run_gemm<P, BM, C::BNW, C::WM, C::WN, 2, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd")
+                   : run_gemm<P, BM, C::BNW, C::WM, C::WN, 3, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
+    return run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
+}
+
 template <typename P, int BM>
 static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipStream_t st,
                           const Timer& tm) {
@@ -475,10 +811,21 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     a.C = w.H1; a.ldc = M * H1; a.c_z = 0;
     a.K = Dp;
     if ((M * H1) % C::BNW == 0)
-        e = run_gemm<P, BM, C::BNW, C::WM, C::WN, C::S, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd");
+        e = sh.gemm_stages == 2
+                ? run_gemm<P, BM, C::BNW, C::WM, C::WN, 2, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd")
+                : run_gemm<P, BM, C::BNW, C::WM, C::WN, 3, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd");
     else
         e = run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd");
     if (e) return e;
+    if (sh.mlp_fused) {
+        if (!mlp_fused_supported(H1, H2, H3)) return hipErrorInvalidValue;
+        // fused layers 2-3 forward and backward
+        w.epart_nt = 1;
+        e = BM == 16 ? run_tail<P, 16>(sh, wt, w, st, tm) : run_tail<P, TailBM<P>::v>(sh, wt, w, st, tm);
+        if (e) return e;
+        return mlp_l1_bwd<P, BM>(sh, wt, w, base, st, tm);
+    }
+    w.epart_nt = H3 / 64;
     // L2f
     a = base;
     a.A = w.H1; a.lda = M * H1; a.a_z = H1;
@@ -520,17 +867,7 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     else
         e = run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_DSIG>(a, R, H1, M, st, tm, "mlp_l2_bwd");
     if (e) return e;
-    // L1b
-    a = base;
-    a.A = w.DZ1; a.lda = M * H1; a.a_z = 0;
-    a.B = wt.W1T; a.ldb = M * H1; a.b_s = (long)Dp * M * H1; a.b_z = 0;
-    a.C = w.dG; a.ldc = Dp; a.c_z = 0;
-    a.K = M * H1;
-    if (Dp % C::BNW == 0)
-        e = run_gemm<P, BM, C::BNW, C::WM, C::WN, C::S, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
-    else
-        e = run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
-    return e;
+    return mlp_l1_bwd<P, BM>(sh, wt, w, base, st, tm);
 }
 
 // ---------------------------------------------------------------------------

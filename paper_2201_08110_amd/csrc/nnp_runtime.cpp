@@ -107,6 +107,9 @@ struct nnp_handle {
     // captured evaluations (most recent last)
     std::vector<GraphEntry> graphs;
 
+    // tunable knobs as set by the caller (0 = automatic)
+    int32_t knob[NNP_N_KNOBS] = {0, 0, 0};
+
     // timing
     bool timing = false;
     std::vector<EventPair> pending;
@@ -289,6 +292,7 @@ template <typename P> nnp_status alloc_work(nnp_handle* h, Work<P>& w) {
     ALLOC(Epart, sizeof(TA) * R * M * (sh.H3 / 64));
     ALLOC(dG, sizeof(TA) * R * sh.Dp);
 #undef ALLOC
+    w.epart_nt = sh.H3 / 64;
     w.flag = h->flag;
     // every row index the kernels may read must be in range from the start
     HIP_TRY(hipMemset(w.row_of_atom, 0, sizeof(int32_t) * A));
@@ -327,6 +331,29 @@ template <> TrainWork<PrecF32>& train_of<PrecF32>(nnp_handle* h) { return h->t32
 template <typename T> const AevConst<T>& const_of(nnp_handle* h);
 template <> const AevConst<float>& const_of<float>(nnp_handle* h) { return h->cf; }
 template <> const AevConst<double>& const_of<double>(nnp_handle* h) { return h->cd; }
+
+// value in effect of a knob (automatic choices resolved)
+int32_t knob_value(const nnp_handle* h, int k) {
+    const Shape& sh = h->shape;
+    const int32_t v = h->knob[k];
+    switch (k) {
+    case NNP_KNOB_MLP_PATH:
+        if (v) return v;
+        return (mlp_fused_supported(sh.H1, sh.H2, sh.H3) && sh.row_tile == 128) ? 1 : 2;
+    case NNP_KNOB_GEMM_STAGES: return v ? v : 3;
+    case NNP_KNOB_CELL_MIN: return v ? v : 128;
+    }
+    return 0;
+}
+
+// copy the resolved knobs into the handle's shape and drop captured graphs
+void apply_knobs(nnp_handle* h) {
+    h->shape.mlp_fused = knob_value(h, NNP_KNOB_MLP_PATH) == 1;
+    h->shape.gemm_stages = knob_value(h, NNP_KNOB_GEMM_STAGES);
+    h->shape.cell_min = knob_value(h, NNP_KNOB_CELL_MIN);
+    for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+}
 
 template <typename P>
 nnp_status run_forward(nnp_handle* h, const nnp_batch* b, const typename P::T* x, double* E,
@@ -476,6 +503,131 @@ nnp_status run_backward(nnp_handle* h, const nnp_batch* b, const typename P::T* 
     return NNP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner
+
+const char* prec_name(int p) { return p == NNP_PREC_FP64 ? "fp64" : p == NNP_PREC_FP32 ? "fp32" : "bf16"; }
+const char* knob_name(int k) {
+    return k == NNP_KNOB_MLP_PATH ? "mlp_path" : k == NNP_KNOB_GEMM_STAGES ? "gemm_stages" : "cell_min";
+}
+
+std::string tune_key(const nnp_handle* h) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s|%s|S%d M%d w%d-%d-%d-%d|atoms%d mols%d apm%d", arch.c_str(),
+                  prec_name(h->precision), h->S, h->M, h->widths[0], h->widths[1], h->widths[2],
+                  h->widths[3], h->max_atoms, h->max_mols, h->max_apm);
+    return buf;
+}
+
+// integer value of "name": in a flat JSON object, or false if absent
+bool json_int(const std::string& line, const char* name, int32_t& v) {
+    const std::string pat = std::string("\"") + name + "\":";
+    size_t at = line.find(pat);
+    if (at == std::string::npos) return false;
+    return std::sscanf(line.c_str() + at + pat.size(), " %d", &v) == 1;
+}
+
+// look the key up in a JSON-lines cache; fills knobs on a hit
+bool cache_lookup(const char* path, const std::string& key, int32_t knobs[NNP_N_KNOBS]) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    std::string line;
+    bool hit = false;
+    char buf[1024];
+    while (!hit && std::fgets(buf, sizeof(buf), f)) {
+        line = buf;
+        if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
+        int32_t v[NNP_N_KNOBS];
+        bool ok = true;
+        for (int k = 0; k < NNP_N_KNOBS; ++k) ok = ok && json_int(line, knob_name(k), v[k]);
+        if (ok) {
+            for (int k = 0; k < NNP_N_KNOBS; ++k) knobs[k] = v[k];
+            hit = true;
+        }
+    }
+    std::fclose(f);
+    return hit;
+}
+
+template <typename P>
+nnp_status time_eval(nnp_handle* h, const nnp_batch* b, const typename P::T* x, double* E,
+                     typename P::T* F, int reps, double& us) {
+    hipStream_t st = (hipStream_t)b->stream;
+    nnp_status rc = run_forward<P>(h, b, x, E, F, nullptr);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(NNP_E_DEVICE, "hipEventCreate failed");
+    }
+    hipError_t e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && rc == NNP_OK && e == hipSuccess; ++r) rc = run_forward<P>(h, b, x, E, F, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(NNP_E_DEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+    us = 1e3 * ms / reps;
+    return NNP_OK;
+}
+
+template <typename P>
+nnp_status autotune(nnp_handle* h, const nnp_batch* b, const typename P::T* x, int reps,
+                    std::string& timings) {
+    typedef typename P::T T;
+    hipError_t e = hipSuccess;
+    double* E = nullptr;
+    T* F = nullptr;
+    e = hipMalloc(&E, sizeof(double) * std::max(b->n_mols, 1));
+    if (e == hipSuccess) e = hipMalloc(&F, sizeof(T) * 3 * std::max(b->n_atoms, 1));
+    nnp_status rc = e == hipSuccess ? NNP_OK : fail(NNP_E_NOMEM, "autotune outputs");
+    for (int k = 0; k < NNP_N_KNOBS && rc == NNP_OK; ++k) {
+        std::vector<int32_t> cand;
+        if (k == NNP_KNOB_MLP_PATH) {
+            if (mlp_fused_supported(h->shape.H1, h->shape.H2, h->shape.H3)) cand = {1, 2};
+        } else if (k == NNP_KNOB_GEMM_STAGES) {
+            cand = {2, 3};
+        } else {
+            for (int c : {32, 64, 128, 256})
+                if (c < h->max_apm) cand.push_back(c);
+            if (!cand.empty()) cand.push_back(1024);
+        }
+        if (cand.size() < 2) {
+            h->knob[k] = knob_value(h, k);
+            continue;
+        }
+        double best = 1e300;
+        int32_t best_v = cand[0];
+        for (int32_t v : cand) {
+            h->knob[k] = v;
+            apply_knobs(h);
+            double us = 0;
+            rc = time_eval<P>(h, b, x, E, F, reps, us);
+            if (rc) break;
+            char buf[96];
+            std::snprintf(buf, sizeof(buf), "%s\"%s=%d\": %.2f", timings.empty() ? "" : ", ",
+                          knob_name(k), v, us);
+            timings += buf;
+            if (us < best) {
+                best = us;
+                best_v = v;
+            }
+        }
+        h->knob[k] = best_v;
+        apply_knobs(h);
+    }
+    if (E) (void)hipFree(E);
+    if (F) (void)hipFree(F);
+    return rc;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -572,6 +724,7 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     sh.max_apm = h->max_apm;
     sh.energy_scale = p->energy_scale;
     sh.celu_alpha = p->celu_alpha;
+    apply_knobs(h);
     fill_const(h->cf, p, D, sh.Dp);
     fill_const(h->cd, p, D, sh.Dp);
 
@@ -756,6 +909,77 @@ int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t
         ++n;
     }
     return n;
+}
+
+nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value) {
+    if (!h) return fail(NNP_E_INVALID, "null handle");
+    if (knob < 0 || knob >= NNP_N_KNOBS) return fail(NNP_E_INVALID, "unknown knob");
+    bool ok = value == 0;
+    if (knob == NNP_KNOB_MLP_PATH) {
+        if (value == 1 && !mlp_fused_supported(h->shape.H1, h->shape.H2, h->shape.H3))
+            return fail(NNP_E_UNSUPPORTED, "the fused layers 2-3 kernel needs hidden widths 256-192-(160..192)");
+        ok = ok || value == 1 || value == 2;
+    } else if (knob == NNP_KNOB_GEMM_STAGES) {
+        ok = ok || value == 2 || value == 3;
+    } else {
+        ok = ok || (value >= 16 && value <= kMaxAtomsPerMol);
+    }
+    if (!ok) return fail(NNP_E_INVALID, "knob value out of range");
+    DeviceGuard dg(h->device);
+    if (!h->graphs.empty()) (void)hipDeviceSynchronize();
+    h->knob[knob] = value;
+    apply_knobs(h);
+    return NNP_OK;
+}
+
+nnp_status nnp_get_knob(nnp_handle* h, int32_t knob, int32_t* value) {
+    if (!h || !value) return fail(NNP_E_INVALID, "null handle or value");
+    if (knob < 0 || knob >= NNP_N_KNOBS) return fail(NNP_E_INVALID, "unknown knob");
+    *value = knob_value(h, knob);
+    return NNP_OK;
+}
+
+nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, int32_t reps,
+                        const char* cache_path, char* report, int32_t report_cap) {
+    nnp_status rc = check_batch(h, b);
+    if (rc) return rc;
+    if (reps < 1 || reps > 1000) return fail(NNP_E_INVALID, "reps must be in 1..1000");
+    if (b->n_atoms > 0 && !coords) return fail(NNP_E_INVALID, "null coords");
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    const std::string key = tune_key(h);
+    int32_t cached[NNP_N_KNOBS];
+    bool hit = cache_path && cache_lookup(cache_path, key, cached);
+    std::string timings;
+    if (hit) {
+        if (!h->graphs.empty()) (void)hipDeviceSynchronize();
+        for (int k = 0; k < NNP_N_KNOBS; ++k) h->knob[k] = cached[k];
+        apply_knobs(h);
+    } else {
+        if (!h->graphs.empty()) (void)hipDeviceSynchronize();
+        if (h->precision == NNP_PREC_FP64)
+            rc = autotune<PrecF64>(h, b, (const double*)coords, reps, timings);
+        else if (h->precision == NNP_PREC_FP32)
+            rc = autotune<PrecF32>(h, b, (const float*)coords, reps, timings);
+        else
+            rc = autotune<PrecBF16>(h, b, (const float*)coords, reps, timings);
+        if (rc) return rc;
+    }
+    char vals[160];
+    std::snprintf(vals, sizeof(vals), "\"mlp_path\": %d, \"gemm_stages\": %d, \"cell_min\": %d",
+                  knob_value(h, 0), knob_value(h, 1), knob_value(h, 2));
+    if (!hit && cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f) return fail(NNP_E_INVALID, std::string("cannot append to tune cache ") + cache_path);
+        std::fprintf(f, "{\"key\": \"%s\", %s}\n", key.c_str(), vals);
+        std::fclose(f);
+    }
+    if (report && report_cap > 0) {
+        std::string r = "{\"key\": \"" + key + "\", \"cached\": " + (hit ? "true" : "false") +
+                        ", \"chosen\": {" + vals + "}, \"timings_us\": {" + timings + "}}";
+        std::snprintf(report, (size_t)report_cap, "%s", r.c_str());
+    }
+    return NNP_OK;
 }
 
 }  // extern "C"

@@ -54,7 +54,12 @@ _lib = None
 #: every symbol include/nnp.h declares
 EXPORTS = ("nnp_create", "nnp_destroy", "nnp_energy_forces", "nnp_energy_forces_f64", "nnp_aev",
            "nnp_energy_forces_backward", "nnp_set_weights", "nnp_num_params", "nnp_aev_dim",
-           "nnp_get_device_status", "nnp_set_timing", "nnp_kernel_times", "nnp_last_error")
+           "nnp_get_device_status", "nnp_set_timing", "nnp_kernel_times", "nnp_last_error",
+           "nnp_set_knob", "nnp_get_knob", "nnp_autotune")
+
+#: tunable knobs (include/nnp.h)
+KNOB_MLP_PATH, KNOB_GEMM_STAGES, KNOB_CELL_MIN = range(3)
+KNOBS = {"mlp_path": KNOB_MLP_PATH, "gemm_stages": KNOB_GEMM_STAGES, "cell_min": KNOB_CELL_MIN}
 
 
 def load_library(path: str = LIB_PATH):
@@ -93,6 +98,12 @@ def load_library(path: str = LIB_PATH):
     lib.nnp_kernel_times.restype = i32
     lib.nnp_last_error.argtypes = []
     lib.nnp_last_error.restype = C.c_char_p
+    lib.nnp_set_knob.argtypes = [vp, i32, i32]
+    lib.nnp_set_knob.restype = i32
+    lib.nnp_get_knob.argtypes = [vp, i32, P(i32)]
+    lib.nnp_get_knob.restype = i32
+    lib.nnp_autotune.argtypes = [vp, P(Batch), vp, i32, C.c_char_p, C.c_char_p, i32]
+    lib.nnp_autotune.restype = i32
     _lib = lib
     return lib
 
@@ -267,6 +278,30 @@ class NNP:
 
     def set_timing(self, on: bool):
         _check(self.lib.nnp_set_timing(self.h, 1 if on else 0))
+
+    def set_knob(self, name: str, value: int):
+        """Select a kernel variant (0 = automatic); see include/nnp.h."""
+        _check(self.lib.nnp_set_knob(self.h, KNOBS[name], int(value)))
+
+    def get_knob(self, name: str) -> int:
+        v = C.c_int32(0)
+        _check(self.lib.nnp_get_knob(self.h, KNOBS[name], C.byref(v)))
+        return int(v.value)
+
+    def autotune(self, coords, species, mol_offsets, reps: int = 5, cache_path=None) -> dict:
+        """Time every variant on this batch, keep the fastest; returns the
+        tuner's report (key, chosen values, microseconds per candidate)."""
+        import json
+        import torch
+        self._need(coords, self.coord_dtype, "coords")
+        self._need(species, torch.int32, "species")
+        self._need(mol_offsets, torch.int32, "mol_offsets")
+        b = self._batch(species, mol_offsets)
+        buf = C.create_string_buffer(8192)
+        path = os.fsencode(cache_path) if cache_path is not None else None
+        _check(self.lib.nnp_autotune(self.h, C.byref(b), coords.data_ptr(), int(reps), path, buf,
+                                     len(buf)))
+        return json.loads(buf.value.decode())
 
     def kernel_times(self) -> dict:
         n = self.lib.nnp_kernel_times(self.h, 0, None, None, None)

@@ -76,7 +76,20 @@ def test_null_arguments():
     assert lib.nnp_set_weights(None, None) == nnp.NNP_E_INVALID
     assert lib.nnp_num_params(None) == -1
     assert lib.nnp_aev_dim(None) == -1
+    v = C.c_int32(0)
+    assert lib.nnp_set_knob(None, 0, 0) == nnp.NNP_E_INVALID
+    assert lib.nnp_get_knob(None, 0, C.byref(v)) == nnp.NNP_E_INVALID
+    assert lib.nnp_autotune(None, None, None, 1, None, None, 0) == nnp.NNP_E_INVALID
     lib.nnp_destroy(None)
+
+
+def test_knob_ids_match_header():
+    nnp, _ = _lib()
+    hdr = open(os.path.join(ROOT, "include", "nnp.h")).read()
+    ids = dict((k, int(v)) for k, v in re.findall(r"\bNNP_KNOB_([A-Z_]+)\s*=\s*(\d+)", hdr))
+    assert ids == {"MLP_PATH": nnp.KNOB_MLP_PATH, "GEMM_STAGES": nnp.KNOB_GEMM_STAGES,
+                   "CELL_MIN": nnp.KNOB_CELL_MIN}
+    assert set(nnp.KNOBS.values()) == set(ids.values())
 
 
 def test_product_path_has_no_oracle_dependency():
