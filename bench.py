@@ -50,7 +50,11 @@ def mlp_flops_per_atom(hp, M):
     return f
 
 
-def run_form(torch, h, batch, steps, warmup, timing, graph=False):
+def run_form(torch, h, batch, steps, warmup, timing, graph=False, per_step=False):
+    """Time `steps` evaluations after `warmup` (inputs already on the device).
+    Returns mean seconds per evaluation, per-kernel totals (timing=True),
+    the last E and F, and (per_step=True) per-evaluation milliseconds from
+    HIP events recorded between evaluations on the evaluation stream."""
     dev = torch.device("cuda:0")
     x = torch.tensor(batch.coords, dtype=torch.float32, device=dev)
     sp = torch.tensor(batch.species, dtype=torch.int32, device=dev)
@@ -66,16 +70,55 @@ def run_form(torch, h, batch, steps, warmup, timing, graph=False):
     if h.device_status() != 0:
         raise RuntimeError("device flagged an error during warmup")
     h.set_timing(timing)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if per_step else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        for _ in range(steps):
+        for i in range(steps):
+            if ev:
+                ev[i].record(stream)
             h.energy_forces(x, sp, off, out=(E, F), graph=graph, stream=stream)
+        if ev:
+            ev[steps].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = h.kernel_times() if timing else {}
     h.set_timing(False)
-    return (t1 - t0) / steps, kt, E.cpu().numpy(), F.double().cpu().numpy()
+    steps_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)] if ev else None
+    return (t1 - t0) / steps, kt, E.cpu().numpy(), F.double().cpu().numpy(), steps_ms
+
+
+def source_digest(files):
+    """sha256 over kernel source files (ties stored counter readings to the
+    exact code they were taken from)."""
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, normalised by a plain copy of
+    known size), or None if absent or taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_bf16_replicas_1024x48.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    meta = dict(l.split(":", 1) for l in txt.splitlines() if l.startswith(("sources:", "sha256:")))
+    files = meta.get("sources", "").split()
+    if not files or source_digest(files) != meta.get("sha256", "").strip():
+        return None
+    for line in txt.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 5 and cells[0] == kernel:
+            try:
+                return float(cells[4])
+            except ValueError:
+                return None
+    return None
 
 
 def cpu_baseline(hp, w, M, make_sample, budget_s=12.0):
@@ -101,6 +144,7 @@ def main():
     ap.add_argument("--replicas", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 form")
+    ap.add_argument("--no-forms", action="store_true", help="skip the like-for-like batched forms")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a reference "
                          "dispatch for HBM traffic counters)")
@@ -128,7 +172,10 @@ def main():
     # ---- headline: batched BF16-MLP replicas -----------------------------
     b5 = synth.config_batch(5, n_mols=args.replicas)
     h5 = nnp.NNP(hp, w, M, "bf16", max_atoms=b5.n_atoms, max_mols=b5.n_mols, max_atoms_per_mol=48)
-    sec, kt, E5, F5 = run_form(torch, h5, b5, args.steps, args.warmup, timing=True)
+    # per-kernel HIP events (recorded by the library on the evaluation
+    # stream) and per-evaluation events, all inside the timed region
+    sec, kt, E5, F5, steps_ms = run_form(torch, h5, b5, args.steps, args.warmup, timing=True,
+                                         per_step=True)
     value = b5.n_atoms / sec
 
     flops = mlp_flops_per_atom(hp, M)
@@ -140,7 +187,7 @@ def main():
         achieved = flops[dom] * b5.n_atoms / (per_kernel[dom]["avg_us"] * 1e-6)
         roof = {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12,
                 "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["bf16"], "traffic": None,
+                "frac": achieved / PEAK["bf16"], "traffic": stored_traffic(dom),
                 "flops_per_launch": flops[dom] * b5.n_atoms}
     mlp_total_us = sum(v["avg_us"] for v in gemms.values())
     mlp_flops = sum(flops[k] for k in gemms) * b5.n_atoms
@@ -157,6 +204,7 @@ def main():
                                "sigma 0.05 A, 8-model ensemble, BF16 MLP / FP32 AEV+forces",
                    "atoms_per_eval": int(b5.n_atoms), "precision": "bf16-mlp"},
         "roofline": roof,
+        "ms_per_eval_p10_p50_p90": [float(np.percentile(steps_ms, q)) for q in (10, 50, 90)],
         "kernels": per_kernel,
         "mlp_gemm_tflops": mlp_flops / (mlp_total_us * 1e-6) / 1e12 if mlp_total_us else None,
     }
@@ -165,14 +213,33 @@ def main():
     if not args.no_plain:
         b2 = synth.config_batch(2)
         h2 = nnp.NNP(hp, w, M, "fp32", max_atoms=b2.n_atoms, max_mols=1, max_atoms_per_mol=64)
-        sec2, kt2, E2, F2 = run_form(torch, h2, b2, max(args.steps, 200), args.warmup, timing=False)
-        sec2g, _, _, _ = run_form(torch, h2, b2, max(args.steps, 200), args.warmup, timing=False,
-                                  graph=True)
+        sec2, _, _, _, _ = run_form(torch, h2, b2, max(args.steps, 200), args.warmup, timing=False)
+        sec2g, _, _, _, _ = run_form(torch, h2, b2, max(args.steps, 200), args.warmup,
+                                     timing=False, graph=True)
         out["plain_fp32"] = {"workload": "single 64-atom ligand, 8-model ensemble, FP32",
                              "value": b2.n_atoms / sec2g, "unit": "atom-evals/s",
                              "us_per_eval": sec2g * 1e6, "us_per_eval_eager": sec2 * 1e6,
                              "launch": "one captured HIP graph per evaluation"}
         h2.close()
+
+    # ---- like-for-like batched forms: both precisions on the replica batch
+    # and on the ragged batch of 512 molecules (10-120 atoms) ---------------
+    if not args.no_forms:
+        forms = {}
+        b3 = synth.config_batch(3)
+        for name, b, apm in (("replicas_1024x48", b5, 48), ("ragged_512", b3, 120)):
+            for prec in ("fp32", "bf16"):
+                if name == "replicas_1024x48" and prec == "bf16":
+                    forms[f"{name}_{prec}"] = {"atom_evals_per_s": value, "ms_per_eval": sec * 1e3,
+                                               "atoms": int(b.n_atoms), "note": "the headline"}
+                    continue
+                hf = nnp.NNP(hp, w, M, prec, max_atoms=b.n_atoms, max_mols=b.n_mols,
+                             max_atoms_per_mol=apm)
+                secf, _, _, _, _ = run_form(torch, hf, b, 20, 3, timing=False)
+                forms[f"{name}_{prec}"] = {"atom_evals_per_s": b.n_atoms / secf,
+                                           "ms_per_eval": secf * 1e3, "atoms": int(b.n_atoms)}
+                hf.close()
+        out["batched_forms"] = forms
 
     # ---- CPU baseline + accuracy on the sample ---------------------------
     if not args.no_cpu:

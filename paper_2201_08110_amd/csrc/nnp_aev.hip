@@ -530,15 +530,146 @@ __device__ inline void load_neighbours(const AevConst<T>& c, const T* __restrict
     }
 }
 
+// 16-byte row pieces: zero four values of an LDS row; store 16 bytes of
+// output elements converted from the featuriser type
+__device__ inline void zero4(float* p) { *(float4*)p = make_float4(0.f, 0.f, 0.f, 0.f); }
+__device__ inline void zero4(double* p) {
+    *(double2*)p = make_double2(0.0, 0.0);
+    *(double2*)(p + 2) = make_double2(0.0, 0.0);
+}
+template <typename TS> __device__ inline void store16(TS* out, const float* v);
+template <> __device__ inline void store16<float>(float* out, const float* v) {
+    *(float4*)out = *(const float4*)v;
+}
+template <> __device__ inline void store16<bf16_t>(bf16_t* out, const float* v) {
+    const float4 a = *(const float4*)v, b = *(const float4*)(v + 4);
+    uint4 q;
+    q.x = pack_bf16x2(a.x, a.y);
+    q.y = pack_bf16x2(a.z, a.w);
+    q.z = pack_bf16x2(b.x, b.y);
+    q.w = pack_bf16x2(b.z, b.w);
+    *(uint4*)out = q;
+}
+template <typename TS> __device__ inline void store16(TS* out, const double* v) {
+    *(double2*)out = *(const double2*)v;
+}
+
 // --------------------------------------------------------------------------
-// AEV forward.  Output row of atom a goes to G[row_of_atom[a]] in the GEMM
-// operand type; optionally also to aev_out[a] (atom order, unpadded).
-//
-// Per wave LDS: neighbour cache [cap][8] T + elements + indices [cap]; the
-// atom's AEV row [Dp] T; pair factors [64][NA + NZ] T + blocks [64].
-// Lanes accumulate runs of equal element (radial) or element pair (angular)
-// in registers and flush a run with one LDS atomic add, so only run
-// boundaries touch shared memory.
+// Per-atom structure of an element-sorted neighbour list.  The angular run
+// (r < rca) and the radial-only run are each sorted by element, so the
+// neighbours of element s form one contiguous range in each run, and the
+// angular pairs {j < k} whose elements make the unordered pair (a, b) form a
+// rectangle (a < b) or a triangle (a == b) of index space.  Pairs are
+// numbered block by block (blocks in AEV order, i.e. by pair_index(a, b)), so
+// every 32-slot angular block of the AEV is a contiguous pair range and can
+// be summed by the lanes that own its slots, with no atomics.
+template <typename T> struct AtomLists {
+    int* aoff;   // [kMaxSpecies + 1]  angular-run start of each element
+    int* roff;   // [kMaxSpecies + 1]  radial-only-run start of each element
+    int* bst;    // [kMaxBlocks + 1]   first pair of each angular block
+    static constexpr int kMaxBlocks = kMaxSpecies * (kMaxSpecies + 1) / 2;
+    __device__ void take(LdsBump& lb) {
+        aoff = lb.take<int>(kMaxSpecies + 1);
+        roff = lb.take<int>(kMaxSpecies + 1);
+        bst = lb.take<int>(kMaxBlocks + 1);
+    }
+    static constexpr size_t bytes() {
+        return 2 * (((kMaxSpecies + 1) * sizeof(int) + 15) & ~size_t(15)) +
+               (((kMaxBlocks + 1) * sizeof(int) + 15) & ~size_t(15));
+    }
+};
+
+// elements (a, b), a <= b, of the angular block with triangular index L
+__device__ inline void block_elements(int L, int S, int& a, int& b) {
+    int base = 0, aa = 0;
+    while (aa < S - 1 && L >= base + (S - aa)) {
+        base += S - aa;
+        ++aa;
+    }
+    a = aa;
+    b = aa + (L - base);
+}
+
+// Fill aoff / roff / bst for one atom (wave-wide); nsp[t] = element of
+// neighbour t.  Returns the number of angular pairs.
+template <typename T>
+__device__ inline int atom_lists(const AtomLists<T>& al, const int* __restrict__ nsp, int nang,
+                                 int nall, int S) {
+    const int lane = lane_id();
+    int ca = 0, cr = 0;   // lane s (< S): neighbours of element s in each run
+    for (int t0 = 0; t0 < nall; t0 += 64) {
+        const int t = t0 + lane;
+        const int sp = t < nall ? nsp[t] : -1;
+        for (int s = 0; s < S; ++s) {
+            const int na = __popcll(__ballot(sp == s && t < nang));
+            const int nr = __popcll(__ballot(sp == s && t >= nang));
+            if (lane == s) {
+                ca += na;
+                cr += nr;
+            }
+        }
+    }
+    // exclusive prefix over the elements
+    int pa = ca, pr = cr;
+    for (int o = 1; o < 8; o <<= 1) {
+        const int va = __shfl_up(pa, o), vr = __shfl_up(pr, o);
+        if (lane >= o) {
+            pa += va;
+            pr += vr;
+        }
+    }
+    if (lane <= S) {
+        al.aoff[lane] = lane < S ? pa - ca : nang;
+        al.roff[lane] = lane < S ? nang + pr - cr : nall;
+    }
+    // angular block sizes and their prefix
+    const int NB = S * (S + 1) / 2;
+    int a = 0, b = 0;
+    if (lane < NB) block_elements(lane, S, a, b);
+    const int na = __shfl(ca, a), nb = __shfl(ca, b);
+    const int cnt = lane < NB ? (a < b ? na * nb : na * (na - 1) / 2) : 0;
+    int inc = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(inc, o);
+        if (lane >= o) inc += v;
+    }
+    if (lane < NB) al.bst[lane + 1] = inc;
+    if (lane == 0) al.bst[0] = 0;
+    return __shfl(inc, NB - 1);
+}
+
+// neighbour indices (j, k) of angular pair p (block-ordered numbering)
+template <typename T>
+__device__ inline void pair_of(const AtomLists<T>& al, int NB, int S, int p, int& j, int& k) {
+    int lo = 0;   // last block with bst[lo] <= p
+    for (int step = 32; step > 0; step >>= 1)
+        if (lo + step < NB && al.bst[lo + step] <= p) lo += step;
+    int a, b;
+    block_elements(lo, S, a, b);
+    const int u = p - al.bst[lo];
+    if (a < b) {
+        const int nb = al.aoff[b + 1] - al.aoff[b];
+        const int q = u / nb;
+        j = al.aoff[a] + q;
+        k = al.aoff[b] + (u - q * nb);
+    } else {
+        int jj, kk;
+        decode_pair(u, al.aoff[a + 1] - al.aoff[a], jj, kk);
+        j = al.aoff[a] + jj;
+        k = al.aoff[a] + kk;
+    }
+}
+
+// --------------------------------------------------------------------------
+// AEV forward.  One wave per central atom; the output row of atom a goes to
+// G[row_of_atom[a]] in the GEMM operand type, optionally also to aev_out[a]
+// (atom order, unpadded).  Every AEV slot is owned by one lane: radial slot
+// (s, k) by lane (group s % 4, shift k) summing over the neighbours of
+// element s; angular slot q of block b by the lane pair (q, q + 32), which
+// split block b's pair range by parity and combine with one shuffle.  Pair
+// factors (NA distance terms, NZ angle terms) are computed once per pair,
+// 64 pairs at a time, into LDS.  The row is assembled in LDS and leaves in
+// 16-byte stores.
 template <typename P, int NZ>
 __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
                                              int cap, const int32_t* __restrict__ mol_off,
@@ -561,7 +692,7 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
     if (i0 >= n) return;
     const int nc = min(kChunk, n - i0);
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
-    const int S = c.S, RL = kNR * S;
+    const int S = c.S, RL = kNR * S, NB = S * (S + 1) / 2;
 
     LdsBump lb(smem);
     ChunkStage<T> cs;
@@ -571,59 +702,49 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
     int* nid = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
     T* row = lb.take<T>((size_t)nw * c.Dp) + (size_t)wave * c.Dp;
     T* pf = lb.take<T>((size_t)nw * 64 * PF) + (size_t)wave * 64 * PF;
-    int* pb = lb.take<int>((size_t)nw * 64) + (size_t)wave * 64;
+    AtomLists<T> al;
+    {
+        LdsBump lw(lb.p + (size_t)wave * AtomLists<T>::bytes());
+        al.take(lw);
+    }
     cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, row_of_atom);
     __syncthreads();
 
+    const int h = lane >> 5, q = lane & 31, qa = q / NZ, qz = q % NZ;
     for (int ic = wave; ic < nc; ic += nw) {
         const int il = i0 + ic;
         const int cnt = cs.ccnt[ic];
         const int nang = cnt & 0xffff, nall = cnt >> 16;
         load_neighbours(c, cs.sx, cs.ssp, cs.clst + (size_t)ic * cap, nang, nall, il, nb, nsp, nid);
-        for (int e = lane; e < c.Dp; e += 64) row[e] = T(0);
+        // zero the angular blocks and the padding (radial slots are all written)
+        for (int e = RL + 4 * lane; e < c.Dp; e += 256) zero4(row + e);
+        wave_sync();
+        const int npair = atom_lists(al, nsp, nang, nall, S);
         wave_sync();
 
-        // ---- radial: lane (group g, shift k); neighbours t = g, g+4, ...
+        // ---- radial: lane (group g, shift k) owns slots (s, k), s = g mod 4
         {
             const int g = lane >> 4, k = lane & 15;
             const T sk = c.shf_r[k];
-            T acc = T(0);
-            int cur = -1;
-            for (int t0 = g; t0 < nall; t0 += 16) {
-                int sv[4];
-                T vv[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int t = t0 + 4 * u;
-                    sv[u] = t < nall ? nsp[t] : -2;
-                    const T d = (t < nall ? nb[kNbStride * t + 3] : T(0)) - sk;
-                    vv[u] = t < nall ? c.radial_pref * m_exp(-c.eta_r * d * d) * nb[kNbStride * t + 4]
-                                     : T(0);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (sv[u] >= 0 && sv[u] != cur) {
-                        if (cur >= 0) lds_add(row + kNR * cur + k, acc);
-                        acc = T(0);
-                        cur = sv[u];
+            for (int s = g; s < S; s += 4) {
+                T acc = T(0);
+                for (int run = 0; run < 2; ++run) {
+                    const int t1 = run ? al.roff[s + 1] : al.aoff[s + 1];
+                    for (int t = run ? al.roff[s] : al.aoff[s]; t < t1; ++t) {
+                        const T d = nb[kNbStride * t + 3] - sk;
+                        acc += m_exp(-c.eta_r * d * d) * nb[kNbStride * t + 4];
                     }
-                    acc += vv[u];
                 }
+                row[kNR * s + k] = c.radial_pref * acc;
             }
-            if (cur >= 0) lds_add(row + kNR * cur + k, acc);
         }
 
-        // ---- angular, in batches of 64 neighbour pairs
-        const int npair = nang * (nang - 1) / 2;
-        const int h = lane >> 5, q = lane & 31, qa = q / NZ, qz = q % NZ;
-        T acc = T(0);
-        int cur = -1;
+        // ---- angular, 64 pairs at a time
         for (int p0 = 0; p0 < npair; p0 += 64) {
             const int nbat = min(64, npair - p0);
-            // phase A: one lane per pair computes the 12 factors
             if (lane < nbat) {
                 int j, k;
-                decode_pair(p0 + lane, nang, j, k);
+                pair_of(al, NB, S, p0 + lane, j, k);
                 const T* ej = nb + kNbStride * j;
                 const T* ek = nb + kNbStride * k;
                 const T rj = ej[3], rk = ek[3];
@@ -644,41 +765,31 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
                     const T cz = cp * c.cos_z[z] + sn * c.sin_z[z];
                     f[NA + z] = T(2) * m_powu(T(0.5) * (T(1) + cz), c.zeta);
                 }
-                pb[lane] = RL + kNAZ * pair_index(nsp[j], nsp[k], S);
             }
             wave_sync();
-            // phase B: lane (half h, slot q) expands pairs t = h, h+2, ...
-            for (int t0 = h; t0 < nbat; t0 += 8) {
-                int bk[4];
-                T vv[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int t = t0 + 2 * u;
-                    bk[u] = t < nbat ? pb[t] : -2;
-                    vv[u] = t < nbat ? pf[PF * t + qa] * pf[PF * t + NA + qz] : T(0);
+            // blocks meeting this batch; lanes q and q + 32 take alternate pairs
+            for (int bl = 0; bl < NB; ++bl) {
+                const int s0 = max(al.bst[bl], p0), e0 = min(al.bst[bl + 1], p0 + nbat);
+                if (s0 >= e0) continue;
+                T acc = T(0);
+                for (int p = s0 + h; p < e0; p += 2) {
+                    const T* f = pf + PF * (p - p0);
+                    acc += f[qa] * f[NA + qz];
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (bk[u] >= 0 && bk[u] != cur) {
-                        if (cur >= 0) lds_add(row + cur + q, acc);
-                        acc = T(0);
-                        cur = bk[u];
-                    }
-                    acc += vv[u];
-                }
+                acc += __shfl_xor(acc, 32);
+                if (h == 0) row[RL + kNAZ * bl + q] += acc;
             }
             wave_sync();
         }
-        if (cur >= 0) lds_add(row + cur + q, acc);
-        wave_sync();
 
-        // ---- write the row (zero padding beyond D)
+        // ---- write the row in 16-byte pieces
+        wave_sync();
         const size_t grow = (size_t)cs.crow[ic];
-        const size_t ai = (size_t)a0 + il;
-        for (int e = lane; e < c.Dp; e += 64) {
-            const T v = row[e];
-            G[grow * c.Dp + e] = Store<TS>::st(v);
-            if (aev_out && e < c.D) aev_out[ai * c.D + e] = v;
+        constexpr int VE = 16 / (int)sizeof(TS);
+        for (int e = VE * lane; e < c.Dp; e += 64 * VE) store16<TS>(G + grow * c.Dp + e, row + e);
+        if (aev_out) {
+            const size_t ai = (size_t)a0 + il;
+            for (int e = lane; e < c.D; e += 64) aev_out[ai * c.D + e] = row[e];
         }
         wave_sync();
     }
@@ -689,7 +800,7 @@ static size_t aev_lds(int max_apm, int cap, int Dp, int NZ, int nw) {
     const int PF = kNAZ / NZ + NZ;
     return ChunkStage<T>::bytes(max_apm, cap) + lds_bytes<T>((size_t)nw * cap * kNbStride) +
            2 * lds_bytes<int>((size_t)nw * cap) + lds_bytes<T>((size_t)nw * Dp) +
-           lds_bytes<T>((size_t)nw * 64 * PF) + lds_bytes<int>((size_t)nw * 64);
+           lds_bytes<T>((size_t)nw * 64 * PF) + (size_t)nw * AtomLists<T>::bytes();
 }
 
 template <typename P>

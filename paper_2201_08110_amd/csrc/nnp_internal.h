@@ -41,6 +41,15 @@ __host__ __device__ inline float bf2f(bf16_t h) {
     return f;
 }
 
+// device conversion of two floats to packed bf16 (low half = a): the
+// hardware's round-to-nearest-even conversion, the same rounding as f2bf
+typedef float nnp_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 nnp_bf16x2 __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t pack_bf16x2(float a, float b) {
+    const nnp_f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, nnp_bf16x2));
+}
+
 // conversion between storage type S and arithmetic type A
 template <typename S> struct Store;
 template <> struct Store<float> {
@@ -53,7 +62,7 @@ template <> struct Store<double> {
 };
 template <> struct Store<bf16_t> {
     __device__ static float ld(bf16_t v) { return bf2f(v); }
-    __device__ static bf16_t st(float v) { return f2bf(v); }
+    __device__ static bf16_t st(float v) { return (bf16_t)(pack_bf16x2(v, 0.f) & 0xffffu); }
 };
 
 // ---------------------------------------------------------------------------

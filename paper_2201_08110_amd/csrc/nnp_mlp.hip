@@ -86,16 +86,26 @@ template <typename TS> struct Slice {
 
 enum { EPI_CELU = 0, EPI_L3F = 1, EPI_DSIG = 2, EPI_ACC = 3, EPI_RAW = 4, EPI_REV = 5 };
 
-__device__ inline float celu(float z, float al) {
-    return z >= 0.f ? z : al * (__builtin_amdgcn_exp2f(z * (1.44269504088896341f / al)) - 1.f);
+// CELU and its derivative, branch-free (the exponential is taken of min(z, 0)
+// and always finite); ial = 1 / alpha.  CELU'(z) is recovered from a stored
+// h = CELU(z): h >= 0 <=> z >= 0, and exp(z / alpha) = 1 + h / alpha.
+__device__ inline float celu(float z, float al, float ial) {
+    const float e = __builtin_amdgcn_exp2f(fminf(z, 0.f) * (ial * 1.44269504088896341f));
+    return z >= 0.f ? z : al * (e - 1.f);
 }
-__device__ inline double celu(double z, double al) { return z >= 0.0 ? z : al * expm1(z / al); }
-__device__ inline float dcelu_z(float z, float al) {
-    return z >= 0.f ? 1.f : __builtin_amdgcn_exp2f(z * (1.44269504088896341f / al));
+__device__ inline double celu(double z, double al, double ial) {
+    const double e = expm1(fmin(z, 0.0) * ial);
+    return z >= 0.0 ? z : al * e;
 }
-__device__ inline double dcelu_z(double z, double al) { return z >= 0.0 ? 1.0 : exp(z / al); }
-// CELU'(z) from h = CELU(z): h >= 0 <=> z >= 0, and exp(z/alpha) = 1 + h/alpha
-template <typename TA> __device__ inline TA dcelu_h(TA h, TA al) { return h >= TA(0) ? TA(1) : TA(1) + h / al; }
+__device__ inline float dcelu_z(float z, float ial) {
+    const float e = __builtin_amdgcn_exp2f(fminf(z, 0.f) * (ial * 1.44269504088896341f));
+    return z >= 0.f ? 1.f : e;
+}
+__device__ inline double dcelu_z(double z, double ial) {
+    const double e = exp(fmin(z, 0.0) * ial);
+    return z >= 0.0 ? 1.0 : e;
+}
+template <typename TA> __device__ inline TA dcelu_h(TA h, TA ial) { return h >= TA(0) ? TA(1) : TA(1) + h * ial; }
 
 template <typename P> struct GemmArgs {
     typedef typename P::TS TS;
@@ -110,7 +120,7 @@ template <typename P> struct GemmArgs {
     const TS* Tr; int ldt; long t_z;         // tangent activations (EPI_REV)
     const TA* w4; long w4_s, w4_z;
     TA* epart; int n_models, nt;
-    TA gscale, alpha;
+    TA gscale, alpha, inv_alpha;
     int K;
     const int32_t* tile_species; int row_tile;
     const BucketInfo* info;
@@ -145,8 +155,8 @@ template <> struct Quad<bf16_t, 1> {
     }
     __device__ static void st(bf16_t* p, const float v[4]) {
         uint2 q;
-        q.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-        q.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+        q.x = pack_bf16x2(v[0], v[1]);
+        q.y = pack_bf16x2(v[2], v[3]);
         *(uint2*)p = q;
     }
 };
@@ -301,7 +311,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
             for (int i = 0; i < FM; ++i) {
                 TA v[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = celu((TA)acc[i][j][r] + bb[r], g.alpha);
+                for (int r = 0; r < 4; ++r) v[r] = celu((TA)acc[i][j][r] + bb[r], g.alpha, g.inv_alpha);
                 Q::st(C + (size_t)(row0 + i * 16) * g.ldc + col, v);
             }
         }
@@ -328,7 +338,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
                 TA hh[4], v[4];
                 Q::ld(Hr + row * g.ldh + col, hh);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = (TA)acc[i][j][r] * dcelu_h(hh[r], g.alpha);
+                for (int r = 0; r < 4; ++r) v[r] = (TA)acc[i][j][r] * dcelu_h(hh[r], g.inv_alpha);
                 Q::st(C + row * g.ldc + col, v);
             }
     } else if (EPI == EPI_RAW) {
@@ -365,8 +375,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
                 Q::ld(Tr + row * g.ldt + col, hd);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const TA d1 = dcelu_h(hh[r], g.alpha);
-                    const TA rho = hh[r] < TA(0) ? TA(1) / g.alpha : TA(0);
+                    const TA d1 = dcelu_h(hh[r], g.inv_alpha);
+                    const TA rho = hh[r] < TA(0) ? g.inv_alpha : TA(0);
                     v[r] = (TA)acc[i][j][r] * d1 + ac[r] * rho * hd[r];
                     v2[r] = ac[r] * d1;
                 }
@@ -395,8 +405,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const TA zz = (TA)acc[i][j][r] + bb[r];
-                    part[i] += ww[r] * celu(zz, g.alpha);
-                    v[r] = dcelu_z(zz, g.alpha) * ww[r] * g.gscale;
+                    part[i] += ww[r] * celu(zz, g.alpha, g.inv_alpha);
+                    v[r] = dcelu_z(zz, g.inv_alpha) * ww[r] * g.gscale;
                 }
                 Q::st(C + (size_t)(row0 + i * 16) * g.ldc + col, v);
             }
@@ -548,7 +558,7 @@ template <typename P> struct TailArgs {
     const TS* W2; const TS* W2T; const TA* b2;
     const TS* W3; const TS* W3T; const TA* b3; const TA* w4;
     TA* epart;                                // [Rcap][M]
-    TA gscale, alpha;
+    TA gscale, alpha, inv_alpha;
     int M;
     const int32_t* tile_species; int row_tile;
     const BucketInfo* info;
@@ -629,7 +639,7 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
             for (int i = 0; i < FM; ++i) {
                 TA v[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = celu((TA)acc[i][j][q] + bb[q], g.alpha);
+                for (int q = 0; q < 4; ++q) v[q] = celu((TA)acc[i][j][q] + bb[q], g.alpha, g.inv_alpha);
                 LdsQuad<TS, ST>::st(Hs, BM, i * 16 + rl, c, v);
             }
         }
@@ -661,8 +671,8 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const TA zz = (TA)acc[i][j][q] + bb[q];
-                    part[i] += ww[q] * celu(zz, g.alpha);
-                    v[q] = dcelu_z(zz, g.alpha) * ww[q] * g.gscale;
+                    part[i] += ww[q] * celu(zz, g.alpha, g.inv_alpha);
+                    v[q] = dcelu_z(zz, g.inv_alpha) * ww[q] * g.gscale;
                 }
                 LdsQuad<TS, ST>::st(Us, BM, i * 16 + rl, c, v);
             }
@@ -696,7 +706,7 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
                 TA hh[4], v[4];
                 LdsQuad<TS, ST>::ld(Hs, BM, i * 16 + rl, c, hh);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = (TA)acc[i][j][q] * dcelu_h(hh[q], g.alpha);
+                for (int q = 0; q < 4; ++q) v[q] = (TA)acc[i][j][q] * dcelu_h(hh[q], g.inv_alpha);
                 LdsQuad<TS, ST>::st(Hs, BM, i * 16 + rl, c, v);
             }
         }
@@ -724,7 +734,7 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
             for (int i = 0; i < FM; ++i) {
                 TA v[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = (TA)acc[i][j][q] * dcelu_h(hh[i][j][q], g.alpha);
+                for (int q = 0; q < 4; ++q) v[q] = (TA)acc[i][j][q] * dcelu_h(hh[i][j][q], g.inv_alpha);
                 Quad<TS, ST>::st(Out + (size_t)(i * 16 + rl) * g.ldh + c, v);
             }
         }
@@ -746,6 +756,7 @@ static hipError_t run_tail(const Shape& sh, const DevWeights<P>& wt, Work<P>& w,
     a.epart = w.Epart;
     a.gscale = (TA)(sh.energy_scale / sh.M);
     a.alpha = (TA)sh.celu_alpha;
+    a.inv_alpha = (TA)(1.0 / sh.celu_alpha);
     a.M = sh.M;
     a.tile_species = w.tile_species; a.row_tile = sh.row_tile;
     a.info = w.info;
@@ -798,6 +809,7 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     base.row_tile = sh.row_tile;
     base.info = w.info;
     base.alpha = (TA)sh.celu_alpha;
+    base.inv_alpha = (TA)(1.0 / sh.celu_alpha);
     base.gscale = (TA)(sh.energy_scale / M);
     base.n_models = M;
     base.nt = H3 / 64;
@@ -890,6 +902,7 @@ static hipError_t train_mlp(const Shape& sh, const DevWeights<P>& wt, Work<P>& w
     base.row_tile = sh.row_tile;
     base.info = w.info;
     base.alpha = (TA)sh.celu_alpha;
+    base.inv_alpha = (TA)(1.0 / sh.celu_alpha);
     base.gscale = (TA)(sh.energy_scale / M);
     base.n_models = M;
     base.nt = H3 / 64;
@@ -950,6 +963,7 @@ static hipError_t train_mlp_rev(const Shape& sh, const DevWeights<P>& wt, Work<P
     base.row_tile = sh.row_tile;
     base.info = w.info;
     base.alpha = (TA)sh.celu_alpha;
+    base.inv_alpha = (TA)(1.0 / sh.celu_alpha);
     base.n_models = M;
     GemmArgs<P> a;
     const int ldt = M * (H1 > H2 ? H1 : H2);
