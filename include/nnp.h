@@ -215,7 +215,7 @@ int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t
  *                         auto: 1 when supported and the handle batches
  *                         (max_atoms > 256, not FP64), else 2.
  *   NNP_KNOB_GEMM_STAGES  LDS pipeline depth of the layer-1 GEMMs: 2 or 3
- *                         (auto 3).
+ *                         (auto 2: two workgroups fit a compute unit).
  *   NNP_KNOB_CELL_MIN     molecules with more atoms than this build their
  *                         neighbour lists through cutoff cells, smaller ones
  *                         scan all atoms: 16..1024 (auto 128).

@@ -1018,8 +1018,25 @@ hipError_t launch_aev_jvp(const Shape& sh, const AevConst<typename P::T>& c,
 // AEV backward: dE/dx contracted from dE/dAEV rows (dG, already scaled to
 // energy units), forces F = -dE/dx accumulated per molecule in LDS and added
 // to F (zeroed by the neighbour kernel) once per workgroup.
-constexpr int kBlkPad = kNAZ + 1;   // LDS stride of one element-pair block of dG
-constexpr int kMaxDpOverLanes = 20; // Dp <= 1280 = 20 * 64
+// LDS stride of one element-pair block of dG: 16-byte aligned, and 9 16-byte
+// granules apart (mod the 16 granules of the banks), so lanes reading the same
+// offset of different blocks spread over the banks
+constexpr int kBlkPad = kNAZ + 4;
+
+// four consecutive values of an LDS row (16-byte aligned)
+__device__ inline void ld4(const float* p, float v[4]) {
+    const float4 q = *(const float4*)p;
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+__device__ inline void ld4(const double* p, double v[4]) {
+    const double2 a = *(const double2*)p, b = *(const double2*)(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ inline void st4(float* p, const float v[4]) { *(float4*)p = make_float4(v[0], v[1], v[2], v[3]); }
+__device__ inline void st4(double* p, const double v[4]) {
+    *(double2*)p = make_double2(v[0], v[1]);
+    *(double2*)(p + 2) = make_double2(v[2], v[3]);
+}
 
 template <typename P, int NZ>
 __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A, int max_apm,
@@ -1061,21 +1078,28 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
         const int il = i0 + ic;
         const int cnt = cs.ccnt[ic];
         const int nang = cnt & 0xffff, nall = cnt >> 16;
-        // the atom's dE/dAEV row: all loads in flight before the first use
+        // the atom's dE/dAEV row: 16 values per lane and load, all in flight
+        // before the first use; groups of 16 never straddle a block
         {
             const TA* src = dG + (size_t)cs.crow[ic] * c.Dp;
-            TA v[kMaxDpOverLanes];
+            TA v[2][16];
 #pragma unroll
-            for (int u = 0; u < kMaxDpOverLanes; ++u) {
-                const int e = lane + 64 * u;
-                v[u] = e < c.D ? src[e] : TA(0);
+            for (int u = 0; u < 2; ++u) {
+                const int e = 16 * (lane + 64 * u);
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4)
+                    if (e < c.D) ld4(src + e + 4 * q4, &v[u][4 * q4]);
             }
 #pragma unroll
-            for (int u = 0; u < kMaxDpOverLanes; ++u) {
-                const int e = lane + 64 * u;
+            for (int u = 0; u < 2; ++u) {
+                const int e = 16 * (lane + 64 * u);
                 if (e < c.D) {
                     const int le = e < RL ? e : RL + kBlkPad * ((e - RL) / kNAZ) + (e - RL) % kNAZ;
-                    g[le] = (T)v[u];
+                    T w[16];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) w[q] = (T)v[u][q];
+#pragma unroll
+                    for (int q4 = 0; q4 < 4; ++q4) st4(g + le + 4 * q4, &w[4 * q4]);
                 }
             }
         }
@@ -1090,7 +1114,8 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
             if (act) {
                 const T* e = nb + kNbStride * t;
                 const T r = e[3], fc = e[4], dfc = e[5];
-                const T* gg = g + kNR * nsp[t] + 4 * q;
+                T gg[4];
+                ld4(g + kNR * nsp[t] + 4 * q, gg);
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const T d = r - c.shf_r[4 * q + kk];
@@ -1153,10 +1178,14 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
                 const T dfa_half = -c.eta_a * d * fa;   // d fa / d r_ij (= d/d r_ik)
                 T sg = 0, sgd = 0;
 #pragma unroll
-                for (int z = 0; z < NZ; ++z) {
-                    const T gg = gb[NZ * a + z];
-                    sg += gg * fz[z];
-                    sgd += gg * dfz[z];
+                for (int z4 = 0; z4 < NZ; z4 += 4) {
+                    T gg[4];
+                    ld4(gb + NZ * a + z4, gg);
+#pragma unroll
+                    for (int z = 0; z < 4; ++z) {
+                        sg += gg[z] * fz[z4 + z];
+                        sgd += gg[z] * dfz[z4 + z];
+                    }
                 }
                 Dc += sgd * fa * fcc;
                 Drj += sg * (dfa_half * fcc + fa * dfcj * fck);
@@ -1212,7 +1241,7 @@ hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
                          const int32_t* mol_off, const int32_t* species, const typename P::T* x,
                          Work<P>& w, typename P::T* F, hipStream_t st, const Timer& tm) {
     typedef typename P::T T;
-    if (c.Dp > 64 * kMaxDpOverLanes) return hipErrorInvalidValue;
+    if (c.Dp > 2 * 16 * 64) return hipErrorInvalidValue;
     dim3 grid(sh.B, (sh.max_apm + kChunk - 1) / kChunk);
     int nw = kWaves;
     size_t lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw);

@@ -146,6 +146,22 @@ struct NetLayout {
     long offW1, offb1, offW2, offb2, offW3, offb3, offw4, offb4, net;
 };
 
+// MFMA operand fragment of the network kernels: KM = K extent of one MFMA,
+// KL = consecutive K elements one lane holds (bf16 16x16x32: 32, 8; f32 and
+// f64 16x16x4: 4, 1).  Lane l holds row l % 16, K elements (l / 16) KL ...
+template <typename TS> struct FragK { static constexpr int KM = 4, KL = 1; };
+template <> struct FragK<bf16_t> { static constexpr int KM = 32, KL = 8; };
+
+// A [N][K] row-major matrix in fragment order: fragment (n-tile t, k-step q)
+// occupies 64 KL consecutive elements, lane l's KL elements at l KL, so one
+// wave reads a fragment with one contiguous load.
+template <typename TS> inline size_t frag_index(int n, int k, int K) {
+    constexpr int KM = FragK<TS>::KM, KL = FragK<TS>::KL;
+    const int t = n / 16, r = n % 16, q = k / KM, kk = k % KM;
+    const int lane = r + 16 * (kk / KL);
+    return (((size_t)t * (K / KM) + q) * 64 + lane) * KL + kk % KL;
+}
+
 // packed device weights (per precision)
 template <typename P> struct DevWeights {
     typedef typename P::TS TS;
@@ -154,6 +170,9 @@ template <typename P> struct DevWeights {
     TS* W2;   TS* W2T;   TA* b2;   // [S][M][H2][H1], [S][M][H1][H2], [S][M][H2]
     TS* W3;   TS* W3T;   TA* b3;   // [S][M][H3][H2], [S][M][H2][H3], [S][M][H3]
     TA* w4;   TA* b4;              // [S][M][H3], [S][M]
+    // the fused layers 2-3 kernel's operands in fragment order (per element
+    // and model: W2 [H2][H1], W3 [H3][H2], W3^T [H2][H3], W2^T [H1][H2])
+    TS* W2f;  TS* W3f;  TS* W3Tf;  TS* W2Tf;
     TA* sae;                       // [S] (already multiplied by energy_scale)
 };
 

@@ -40,7 +40,7 @@ typedef short bf16x8 __attribute__((ext_vector_type(8)));
 
 template <typename TS> struct MF;
 template <> struct MF<float> {
-    static constexpr int KM = 4, KL = 1;
+    static constexpr int KM = FragK<float>::KM, KL = FragK<float>::KL;
     typedef float Frag;
     typedef f32x4 Acc;
     __device__ static Acc mma(Frag a, Frag b, Acc c) {
@@ -52,7 +52,7 @@ template <> struct MF<float> {
     __device__ static int col0(int l) { return 4 * (l >> 4); }
 };
 template <> struct MF<double> {
-    static constexpr int KM = 4, KL = 1;
+    static constexpr int KM = FragK<double>::KM, KL = FragK<double>::KL;
     typedef double Frag;
     typedef f64x4 Acc;
     __device__ static Acc mma(Frag a, Frag b, Acc c) {
@@ -64,7 +64,7 @@ template <> struct MF<double> {
     __device__ static int col0(int l) { return l >> 4; }
 };
 template <> struct MF<bf16_t> {
-    static constexpr int KM = 32, KL = 8;
+    static constexpr int KM = FragK<bf16_t>::KM, KL = FragK<bf16_t>::KL;
     typedef bf16x8 Frag;
     typedef f32x4 Acc;
     __device__ static Acc mma(Frag a, Frag b, Acc c) {
@@ -184,7 +184,11 @@ struct GemmShape {
 // in flight.  The memory clobber keeps the compiler from moving LDS accesses
 // across the barrier (a plain __syncthreads would wait for every load).
 template <int N> __device__ inline void vm_wait_barrier() {
-    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    // s_waitcnt vmcnt(N) expcnt(7) lgkmcnt(0), issued through the builtin so
+    // that the compiler's own wait tracking sees it
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+    asm volatile("s_barrier" ::: "memory");
 }
 
 // One workgroup of 4 waves computes a BM x BN tile of C = A B^T (A [rows][K],
@@ -238,9 +242,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
     // this lane's part of every 8-row load: row lane/8 of the group, the
     // chunk that lands at position lane%8 of it
     const int ld_row = lane >> 3, ld_chunk = (lane & 7) ^ (lane >> 3);
-    auto issue = [&](int kt) {
-        TS* st_ = stage0 + (size_t)(kt % S) * (BM + BN) * BK;
-        const int k0 = kt * BK + ld_chunk * L::VE;
+    // direct loads of K slice `src` into LDS stage `slot`
+    auto issue = [&](int src, int slot) {
+        TS* st_ = stage0 + (size_t)slot * (BM + BN) * BK;
+        const int k0 = src * BK + ld_chunk * L::VE;
 #pragma unroll
         for (int u = 0; u < QA; ++u) {
             const int q = wave + 4 * u;
@@ -265,34 +270,74 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
+    // Software pipeline: the fragments of k-step t+1 are read from LDS while
+    // the MFMAs of step t run; the last step of a slice first waits for the
+    // next slice and the barrier that frees the oldest stage, refills that
+    // stage, then reads the next slice's first fragments.  Every step issues
+    // the same number of direct loads (past the end the last slice is loaded
+    // again into the free stage, an L2 hit), so one wait count fits all steps
+    // and the loop body has no branches (a join would make the compiler wait
+    // for every LDS read).  Scheduling barriers keep the compiler from
+    // moving the MFMAs of a step above the reads issued for the next one.
+    typedef typename mf::Frag Frag;
+    constexpr int NSTEP = BK / mf::KM;
+    static_assert(NSTEP % 2 == 0, "k-steps per slice");
+    auto stage = [&](int kt) { return stage0 + (size_t)(kt % S) * (BM + BN) * BK; };
+    Frag af[2][FM], bq[2][FN];
+    auto read_frags = [&](Frag(&fa)[FM], Frag(&fb)[FN], const TS* As, int kk) {
+        const TS* Bs = As + BM * BK;
+        const int kf = kk + (lane >> 4) * mf::KL;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) fa[i] = *(const Frag*)(&As[L::at(wm * WTM + i * 16 + (lane & 15), kf)]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) fb[j] = *(const Frag*)(&Bs[L::at(wn * WTN + j * 16 + (lane & 15), kf)]);
+    };
+    auto mma_step = [&](const Frag(&fa)[FM], const Frag(&fb)[FN]) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int i = 0; i < FM; ++i) acc[i][j] = mf::mma(fb[j], fa[i], acc[i][j]);
+    };
+
     const int nk = g.K / BK;
 #pragma unroll
-    for (int p = 0; p < S - 1; ++p)
-        if (p < nk) issue(p);
-    for (int kt = 0; kt < nk; ++kt) {
-        // slice kt must have landed; the S-2 slices after it may stay in flight
-        if (kt + S - 2 < nk) vm_wait_barrier<QMIN * (S - 2)>();
-        else vm_wait_barrier<0>();
-        // every wave is past slice kt-1, so its stage can be refilled
-        if (kt + S - 1 < nk) issue(kt + S - 1);
-        const TS* As = stage0 + (size_t)(kt % S) * (BM + BN) * BK;
-        const TS* Bs = As + BM * BK;
+    for (int p = 0; p < S - 1; ++p) issue(min(p, nk - 1), p);
+    vm_wait_barrier<QMIN * (S - 2)>();   // slice 0 landed
+    issue(min(S - 1, nk - 1), S - 1);
+    // retire the scalar loads of the kernel arguments here: scalar loads
+    // return out of order, and one still pending at the loop head would make
+    // the compiler wait for all LDS reads before the first MFMA of a slice
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    read_frags(af[0], bq[0], stage(0), 0);
+    for (int kt = 0; kt < nk - 1; ++kt) {
+        const TS* As = stage(kt);
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += mf::KM) {
-            const int kf = kk + (lane >> 4) * mf::KL;
-            typename mf::Frag af[FM];
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-                af[i] = *(const typename mf::Frag*)(&As[L::at(wm * WTM + i * 16 + (lane & 15), kf)]);
-#pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const typename mf::Frag bfr =
-                    *(const typename mf::Frag*)(&Bs[L::at(wn * WTN + j * 16 + (lane & 15), kf)]);
-#pragma unroll
-                for (int i = 0; i < FM; ++i) acc[i][j] = mf::mma(bfr, af[i], acc[i][j]);
+        for (int t = 0; t < NSTEP; ++t) {
+            if (t + 1 < NSTEP) {
+                read_frags(af[(t + 1) & 1], bq[(t + 1) & 1], As, (t + 1) * mf::KM);
+            } else {
+                vm_wait_barrier<QMIN * (S - 2)>();          // slice kt+1 landed
+                issue(min(kt + S, nk - 1), kt % S);          // stage of slice kt is free
+                read_frags(af[0], bq[0], stage(kt + 1), 0);
             }
+            __builtin_amdgcn_sched_barrier(0);
+            mma_step(af[t & 1], bq[t & 1]);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
+    {
+        const TS* As = stage(nk - 1);
+#pragma unroll
+        for (int t = 0; t < NSTEP; ++t) {
+            if (t + 1 < NSTEP) read_frags(af[(t + 1) & 1], bq[(t + 1) & 1], As, (t + 1) * mf::KM);
+            __builtin_amdgcn_sched_barrier(0);
+            mma_step(af[t & 1], bq[t & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // no direct load may still be writing LDS when the epilogue reuses it or
+    // the workgroup ends
+    vm_wait_barrier<0>();
 
     // ---- epilogue: acc[i][j][r] of lane l is C[row_i][col_j + r * ST]
     const int row0 = tile_m * BM + wm * WTM + (lane & 15);
@@ -485,42 +530,43 @@ template <typename TS> struct Sliced {
     }
 };
 
-// acc = A (LDS, sliced, BM rows, K columns) x B^T, B rows n0 + [0, 16 FN)
-// of a K-contiguous matrix in global memory (leading dimension ldb).  The B
-// fragments of k-step t+2 are requested before the MFMAs of step t; the empty
-// asm with a memory clobber keeps the compiler from sinking those loads next
-// to their use, so about two k-steps of MFMAs cover the L2 latency.
-template <typename TS, int FM, int FN, int K>
-__device__ inline void tail_product(typename MF<TS>::Acc (&acc)[FM][FN], const TS* As,
-                                    const TS* __restrict__ Bg, int ldb, int n0, int lane) {
+// acc = A rows m0 + [0, 16 FM) (LDS, sliced, BM rows, K columns) x B^T, B
+// n-tiles nt0 + [0, FN) of a matrix in fragment order (one contiguous 64-lane
+// load per fragment).  The B fragments of k-step t+2 are requested before the
+// MFMAs of step t; the empty asm with a memory clobber keeps the compiler from
+// sinking those loads next to their use, so two k-steps of MFMAs (and the
+// other waves) cover the L2 latency.
+template <typename TS, int BM, int FM, int FN, int K>
+__device__ inline void tail_product(typename MF<TS>::Acc (&acc)[FM][FN], const TS* As, int m0,
+                                    const TS* __restrict__ Bf, int nt0, int lane) {
     typedef MF<TS> mf;
     typedef Sliced<TS> L;
     typedef typename mf::Frag Frag;
-    constexpr int BM = 16 * FM, NS = K / mf::KM, PD = 2;
+    constexpr int NS = K / mf::KM, PD = 2;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
-    const TS* Brow = Bg + (size_t)(n0 + (lane & 15)) * ldb + (lane >> 4) * mf::KL;
+    const TS* Bl = Bf + (size_t)nt0 * NS * 64 * mf::KL + lane * mf::KL;
     Frag bq[PD + 1][FN];
 #pragma unroll
     for (int t = 0; t < PD && t < NS; ++t)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) bq[t][j] = *(const Frag*)(Brow + (size_t)j * 16 * ldb + t * mf::KM);
+        for (int j = 0; j < FN; ++j) bq[t][j] = *(const Frag*)(Bl + ((size_t)j * NS + t) * 64 * mf::KL);
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
         if (t + PD < NS) {
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-                bq[(t + PD) % (PD + 1)][j] = *(const Frag*)(Brow + (size_t)j * 16 * ldb + (t + PD) * mf::KM);
+                bq[(t + PD) % (PD + 1)][j] = *(const Frag*)(Bl + ((size_t)j * NS + t + PD) * 64 * mf::KL);
         }
         asm volatile("" ::: "memory");
         const int kf = t * mf::KM + (lane >> 4) * mf::KL;
         Frag af[FM];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) af[i] = *(const Frag*)(&As[L::at(BM, i * 16 + (lane & 15), kf)]);
+        for (int i = 0; i < FM; ++i) af[i] = *(const Frag*)(&As[L::at(BM, m0 + i * 16 + (lane & 15), kf)]);
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
@@ -555,8 +601,8 @@ template <typename P> struct TailArgs {
     typedef typename P::TS TS;
     typedef typename P::TA TA;
     const TS* H1; TS* DZ1; int ldh;          // [Rcap][M*H1]
-    const TS* W2; const TS* W2T; const TA* b2;
-    const TS* W3; const TS* W3T; const TA* b3; const TA* w4;
+    const TS* W2f; const TS* W2Tf; const TA* b2;      // fragment order
+    const TS* W3f; const TS* W3Tf; const TA* b3; const TA* w4;
     TA* epart;                                // [Rcap][M]
     TA gscale, alpha, inv_alpha;
     int M;
@@ -570,23 +616,27 @@ struct TailShape {
     typedef typename P::TS TS;
     static constexpr size_t hs = (size_t)BM * H2 * sizeof(TS);
     static constexpr size_t u1 = (size_t)BM * H1 * sizeof(TS), u2 = (size_t)BM * H3 * sizeof(TS);
-    static constexpr size_t lds_bytes() { return hs + (u1 > u2 ? u1 : u2) + sizeof(typename P::TA) * BM * 4; }
+    static constexpr size_t par = sizeof(typename P::TA) * (H2 + 2 * H3);   // b2, b3, w4
+    static constexpr size_t lds_bytes() { return hs + (u1 > u2 ? u1 : u2) + sizeof(typename P::TA) * BM * 4 + par; }
 };
 
-template <typename P, int BM, int H1, int H2, int H3>
-__global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
+template <typename P, int BM, int TW, int H1, int H2, int H3>
+__global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
     typedef typename P::TS TS;
     typedef typename P::TA TA;
     typedef MF<TS> mf;
     typedef typename mf::Acc Acc;
     typedef Sliced<TS> L;
-    constexpr int FM = BM / 16, ST = mf::kColStride;
+    constexpr int NT = 256 * TW, FM = BM / 16 / TW, ST = mf::kColStride;
     static_assert(H1 % 64 == 0 && H2 % 64 == 0 && H3 % 64 == 0 && BM % 16 == 0, "widths");
     typedef TailShape<P, BM, H1, H2, H3> Sh;
     extern __shared__ __align__(16) char smem_raw[];
     TS* Hs = (TS*)smem_raw;                              // H2, later DZ2   [BM][H2]
     TS* Us = (TS*)(smem_raw + Sh::hs);                   // H1 tile, later DZ3
     TA* red = (TA*)(smem_raw + Sh::hs + (Sh::u1 > Sh::u2 ? Sh::u1 : Sh::u2));   // [BM][4]
+    TA* sb2 = red + BM * 4;            // b2 [H2], b3 [H3], w4 [H3] of this element and model
+    TA* sb3 = sb2 + H2;
+    TA* sw4 = sb3 + H3;
 
     // XCD-contiguous ranges over (model, row tile): an XCD works through
     // consecutive tiles of one model and keeps that model's weights in L2
@@ -600,7 +650,8 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
     const int s = g.tile_species[row0 / g.row_tile];
     if (s < 0) return;
     const int tid = threadIdx.x, lane = threadIdx.x & 63;
-    const int wn = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wn = wave & 3, m0 = (wave >> 2) * (BM / TW);   // column quarter, first row
     const size_t sz = (size_t)s * g.M + z;
 
     // H1 tile -> LDS (sliced), direct loads: per K slice BM/8 loads of 8 rows
@@ -608,14 +659,21 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
         const TS* src0 = g.H1 + (size_t)row0 * g.ldh + (size_t)z * H1;
         const int lr = lane >> 3, lc = (lane & 7) ^ (lane >> 3);
         constexpr int NQ = (H1 / L::BK) * (BM / 8);
+        constexpr int NW = 4 * TW;
 #pragma unroll
-        for (int u = 0; u < (NQ + 3) / 4; ++u) {
-            const int q = wn + 4 * u;
-            if (NQ % 4 == 0 || q < NQ) {
+        for (int u = 0; u < (NQ + NW - 1) / NW; ++u) {
+            const int q = wave + NW * u;
+            if (NQ % NW == 0 || q < NQ) {
                 const int t = q / (BM / 8), rq = q % (BM / 8);
                 const TS* src = src0 + (size_t)(rq * 8 + lr) * g.ldh + t * L::BK + lc * L::VE;
                 __builtin_amdgcn_global_load_lds(NNP_GPTR(src), NNP_LPTR(Us + (t * BM + rq * 8) * L::BK), 16, 0, 0);
             }
+        }
+        // the layer parameters the epilogues read, staged beside the tile
+        for (int t = tid; t < H2 + 2 * H3; t += NT) {
+            const TA v = t < H2 ? g.b2[sz * H2 + t]
+                                : (t < H2 + H3 ? g.b3[sz * H3 + (t - H2)] : g.w4[sz * H3 + (t - H2 - H3)]);
+            sb2[t] = v;
         }
         vm_wait_barrier<0>();
     }
@@ -627,8 +685,8 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
         constexpr int FN = H2 / 64;
         Acc acc[FM][FN];
         const int n0 = wn * (H2 / 4);
-        tail_product<TS, FM, FN, H1>(acc, Us, g.W2 + sz * H2 * H1, H1, n0, lane);
-        const TA* b2 = g.b2 + sz * H2;
+        tail_product<TS, BM, FM, FN, H1>(acc, Us, m0, g.W2f + sz * H2 * H1, n0 / 16, lane);
+        const TA* b2 = sb2;
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int c = n0 + j * 16 + cl;
@@ -640,7 +698,7 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
                 TA v[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v[q] = celu((TA)acc[i][j][q] + bb[q], g.alpha, g.inv_alpha);
-                LdsQuad<TS, ST>::st(Hs, BM, i * 16 + rl, c, v);
+                LdsQuad<TS, ST>::st(Hs, BM, m0 + i * 16 + rl, c, v);
             }
         }
     }
@@ -650,9 +708,9 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
         constexpr int FN = H3 / 64;
         Acc acc[FM][FN];
         const int n0 = wn * (H3 / 4);
-        tail_product<TS, FM, FN, H2>(acc, Hs, g.W3 + sz * H3 * H2, H2, n0, lane);
-        const TA* b3 = g.b3 + sz * H3;
-        const TA* w4 = g.w4 + sz * H3;
+        tail_product<TS, BM, FM, FN, H2>(acc, Hs, m0, g.W3f + sz * H3 * H2, n0 / 16, lane);
+        const TA* b3 = sb3;
+        const TA* w4 = sw4;
         TA part[FM];
 #pragma unroll
         for (int i = 0; i < FM; ++i) part[i] = 0;
@@ -674,7 +732,7 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
                     part[i] += ww[q] * celu(zz, g.alpha, g.inv_alpha);
                     v[q] = dcelu_z(zz, g.inv_alpha) * ww[q] * g.gscale;
                 }
-                LdsQuad<TS, ST>::st(Us, BM, i * 16 + rl, c, v);
+                LdsQuad<TS, ST>::st(Us, BM, m0 + i * 16 + rl, c, v);
             }
         }
 #pragma unroll
@@ -682,7 +740,7 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
             TA v = part[i];
             v += __shfl_xor(v, 16);
             v += __shfl_xor(v, 32);
-            if (lane < 16) red[(i * 16 + lane) * 4 + wn] = v;
+            if (lane < 16) red[(m0 + i * 16 + lane) * 4 + wn] = v;
         }
     }
     __syncthreads();   // DZ3 and the energy partials complete
@@ -697,17 +755,17 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
         constexpr int FN = H2 / 64;
         Acc acc[FM][FN];
         const int n0 = wn * (H2 / 4);
-        tail_product<TS, FM, FN, H3>(acc, Us, g.W3T + sz * H2 * H3, H3, n0, lane);
+        tail_product<TS, BM, FM, FN, H3>(acc, Us, m0, g.W3Tf + sz * H2 * H3, n0 / 16, lane);
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int c = n0 + j * 16 + cl;
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
                 TA hh[4], v[4];
-                LdsQuad<TS, ST>::ld(Hs, BM, i * 16 + rl, c, hh);
+                LdsQuad<TS, ST>::ld(Hs, BM, m0 + i * 16 + rl, c, hh);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v[q] = (TA)acc[i][j][q] * dcelu_h(hh[q], g.inv_alpha);
-                LdsQuad<TS, ST>::st(Hs, BM, i * 16 + rl, c, v);
+                LdsQuad<TS, ST>::st(Hs, BM, m0 + i * 16 + rl, c, v);
             }
         }
     }
@@ -725,8 +783,8 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int i = 0; i < FM; ++i)
-                Quad<TS, ST>::ld(Hr + (size_t)(i * 16 + rl) * g.ldh + n0 + j * 16 + cl, hh[i][j]);
-        tail_product<TS, FM, FN, H2>(acc, Hs, g.W2T + sz * H1 * H2, H2, n0, lane);
+                Quad<TS, ST>::ld(Hr + (size_t)(m0 + i * 16 + rl) * g.ldh + n0 + j * 16 + cl, hh[i][j]);
+        tail_product<TS, BM, FM, FN, H2>(acc, Hs, m0, g.W2Tf + sz * H1 * H2, n0 / 16, lane);
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int c = n0 + j * 16 + cl;
@@ -735,7 +793,7 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
                 TA v[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v[q] = (TA)acc[i][j][q] * dcelu_h(hh[i][j][q], g.inv_alpha);
-                Quad<TS, ST>::st(Out + (size_t)(i * 16 + rl) * g.ldh + c, v);
+                Quad<TS, ST>::st(Out + (size_t)(m0 + i * 16 + rl) * g.ldh + c, v);
             }
         }
     }
@@ -745,14 +803,14 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs<P> g) {
 // padded to 192); other widths take the per-layer GEMMs
 constexpr int kTailH1 = 256, kTailH2 = 192, kTailH3 = 192;
 
-template <typename P, int BM>
+template <typename P, int BM, int TW>
 static hipError_t run_tail(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipStream_t st,
                            const Timer& tm) {
     typedef typename P::TA TA;
     TailArgs<P> a{};
     a.H1 = w.H1; a.DZ1 = w.DZ1; a.ldh = sh.M * sh.H1;
-    a.W2 = wt.W2; a.W2T = wt.W2T; a.b2 = wt.b2;
-    a.W3 = wt.W3; a.W3T = wt.W3T; a.b3 = wt.b3; a.w4 = wt.w4;
+    a.W2f = wt.W2f; a.W2Tf = wt.W2Tf; a.b2 = wt.b2;
+    a.W3f = wt.W3f; a.W3Tf = wt.W3Tf; a.b3 = wt.b3; a.w4 = wt.w4;
     a.epart = w.Epart;
     a.gscale = (TA)(sh.energy_scale / sh.M);
     a.alpha = (TA)sh.celu_alpha;
@@ -763,11 +821,11 @@ static hipError_t run_tail(const Shape& sh, const DevWeights<P>& wt, Work<P>& w,
     a.nm = sh.Rcap / BM;
     const int T = a.nm * sh.M;
     const size_t lds = TailShape<P, BM, kTailH1, kTailH2, kTailH3>::lds_bytes();
-    auto kern = k_tail<P, BM, kTailH1, kTailH2, kTailH3>;
+    auto kern = k_tail<P, BM, TW, kTailH1, kTailH2, kTailH3>;
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("mlp_tail", st);
-    hipLaunchKernelGGL(kern, dim3(T), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(kern, dim3(T), dim3(256 * TW), lds, st, a);
     tm.e("mlp_tail", st);
     return hipGetLastError();
 }
@@ -833,7 +891,8 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
         if (!mlp_fused_supported(H1, H2, H3)) return hipErrorInvalidValue;
         // fused layers 2-3 forward and backward
         w.epart_nt = 1;
-        e = BM == 16 ? run_tail<P, 16>(sh, wt, w, st, tm) : run_tail<P, TailBM<P>::v>(sh, wt, w, st, tm);
+        e = BM == 16 ? run_tail<P, 16, 1>(sh, wt, w, st, tm)
+                     : run_tail<P, TailBM<P>::v, 1>(sh, wt, w, st, tm);
         if (e) return e;
         return mlp_l1_bwd<P, BM>(sh, wt, w, base, st, tm);
     }

@@ -242,6 +242,18 @@ template <typename P> nnp_status upload_weights(nnp_handle* h, DevWeights<P>& dw
             b4[sm] = (TA)p[0];
         }
     for (int s = 0; s < S; ++s) sae[s] = (TA)(h->energy_scale * (h->sae.empty() ? 0.0 : h->sae[s]));
+    // fragment-order copies of the per-model matrices (the fused kernel's
+    // weight operands), one [N][K] matrix per element and model
+    auto fragments = [&](const std::vector<TS>& src, int N, int K) {
+        std::vector<TS> dst(src.size());
+        for (size_t sm = 0; sm < (size_t)S * M; ++sm)
+            for (int n = 0; n < N; ++n)
+                for (int k = 0; k < K; ++k)
+                    dst[sm * N * K + frag_index<TS>(n, k, K)] = src[(sm * N + n) * K + k];
+        return dst;
+    };
+    const std::vector<TS> W2f = fragments(W2, H2, H1), W3f = fragments(W3, H3, H2);
+    const std::vector<TS> W3Tf = fragments(W3T, H2, H3), W2Tf = fragments(W2T, H1, H2);
     hipError_t e = hipSuccess;
     auto put = [&](auto*& dst, const auto& src) -> bool {
         size_t bytes = src.size() * sizeof(src[0]);
@@ -254,7 +266,8 @@ template <typename P> nnp_status upload_weights(nnp_handle* h, DevWeights<P>& dw
     };
     if (!put(dw.W1, W1) || !put(dw.W1T, W1T) || !put(dw.b1, b1) || !put(dw.W2, W2) ||
         !put(dw.W2T, W2T) || !put(dw.b2, b2) || !put(dw.W3, W3) || !put(dw.W3T, W3T) ||
-        !put(dw.b3, b3) || !put(dw.w4, w4) || !put(dw.b4, b4) || !put(dw.sae, sae))
+        !put(dw.b3, b3) || !put(dw.w4, w4) || !put(dw.b4, b4) || !put(dw.sae, sae) ||
+        !put(dw.W2f, W2f) || !put(dw.W3f, W3f) || !put(dw.W3Tf, W3Tf) || !put(dw.W2Tf, W2Tf))
         return fail(e == hipErrorOutOfMemory ? NNP_E_NOMEM : NNP_E_DEVICE,
                     std::string("weight upload: ") + hipGetErrorString(e));
     return NNP_OK;
@@ -340,7 +353,7 @@ int32_t knob_value(const nnp_handle* h, int k) {
     case NNP_KNOB_MLP_PATH:
         if (v) return v;
         return (mlp_fused_supported(sh.H1, sh.H2, sh.H3) && sh.row_tile == 128) ? 1 : 2;
-    case NNP_KNOB_GEMM_STAGES: return v ? v : 3;
+    case NNP_KNOB_GEMM_STAGES: return v ? v : 2;
     case NNP_KNOB_CELL_MIN: return v ? v : 128;
     }
     return 0;
