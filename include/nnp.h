@@ -219,6 +219,11 @@ int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t
  *   NNP_KNOB_CELL_MIN     molecules with more atoms than this build their
  *                         neighbour lists through cutoff cells, smaller ones
  *                         scan all atoms: 16..1024 (auto 128).
+ *   NNP_KNOB_TAIL_TILE    row tile of the fused layers 2-3 kernel (handles
+ *                         with 128-row buckets): 1 = 128 / (operand bytes)
+ *                         rows on 4 waves, 2 = half that (at least 16) on 4
+ *                         waves, 3 = the full tile on 8 waves (2 x 4); 3 is
+ *                         taken as 1 for FP64 (auto 1).
  *
  * Setting a knob drops the handle's captured graphs.  Invalid knob ids or
  * values return NNP_E_INVALID (a fused path on unsupported widths returns
@@ -227,7 +232,8 @@ enum {
     NNP_KNOB_MLP_PATH = 0,
     NNP_KNOB_GEMM_STAGES = 1,
     NNP_KNOB_CELL_MIN = 2,
-    NNP_N_KNOBS = 3
+    NNP_KNOB_TAIL_TILE = 3,
+    NNP_N_KNOBS = 4
 };
 nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value);
 nnp_status nnp_get_knob(nnp_handle* h, int32_t knob, int32_t* value);

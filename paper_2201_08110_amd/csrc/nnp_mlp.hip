@@ -891,8 +891,11 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
         if (!mlp_fused_supported(H1, H2, H3)) return hipErrorInvalidValue;
         // fused layers 2-3 forward and backward
         w.epart_nt = 1;
-        e = BM == 16 ? run_tail<P, 16, 1>(sh, wt, w, st, tm)
-                     : run_tail<P, TailBM<P>::v, 1>(sh, wt, w, st, tm);
+        constexpr int TB = TailBM<P>::v, TH = TB / 2 >= 16 ? TB / 2 : 16;
+        if (BM == 16) e = run_tail<P, 16, 1>(sh, wt, w, st, tm);
+        else if (sh.tail_tile == 2) e = run_tail<P, TH, 1>(sh, wt, w, st, tm);
+        else if (sh.tail_tile == 3 && TB >= 32) e = run_tail<P, TB, TB >= 32 ? 2 : 1>(sh, wt, w, st, tm);
+        else e = run_tail<P, TB, 1>(sh, wt, w, st, tm);
         if (e) return e;
         return mlp_l1_bwd<P, BM>(sh, wt, w, base, st, tm);
     }

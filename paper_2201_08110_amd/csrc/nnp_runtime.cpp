@@ -108,7 +108,7 @@ struct nnp_handle {
     std::vector<GraphEntry> graphs;
 
     // tunable knobs as set by the caller (0 = automatic)
-    int32_t knob[NNP_N_KNOBS] = {0, 0, 0};
+    int32_t knob[NNP_N_KNOBS] = {0, 0, 0, 0};
 
     // timing
     bool timing = false;
@@ -355,6 +355,7 @@ int32_t knob_value(const nnp_handle* h, int k) {
         return (mlp_fused_supported(sh.H1, sh.H2, sh.H3) && sh.row_tile == 128) ? 1 : 2;
     case NNP_KNOB_GEMM_STAGES: return v ? v : 2;
     case NNP_KNOB_CELL_MIN: return v ? v : 128;
+    case NNP_KNOB_TAIL_TILE: return v ? v : 1;
     }
     return 0;
 }
@@ -364,6 +365,7 @@ void apply_knobs(nnp_handle* h) {
     h->shape.mlp_fused = knob_value(h, NNP_KNOB_MLP_PATH) == 1;
     h->shape.gemm_stages = knob_value(h, NNP_KNOB_GEMM_STAGES);
     h->shape.cell_min = knob_value(h, NNP_KNOB_CELL_MIN);
+    h->shape.tail_tile = knob_value(h, NNP_KNOB_TAIL_TILE);
     for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     h->graphs.clear();
 }
@@ -521,7 +523,9 @@ nnp_status run_backward(nnp_handle* h, const nnp_batch* b, const typename P::T* 
 
 const char* prec_name(int p) { return p == NNP_PREC_FP64 ? "fp64" : p == NNP_PREC_FP32 ? "fp32" : "bf16"; }
 const char* knob_name(int k) {
-    return k == NNP_KNOB_MLP_PATH ? "mlp_path" : k == NNP_KNOB_GEMM_STAGES ? "gemm_stages" : "cell_min";
+    return k == NNP_KNOB_MLP_PATH ? "mlp_path"
+         : k == NNP_KNOB_GEMM_STAGES ? "gemm_stages"
+         : k == NNP_KNOB_CELL_MIN ? "cell_min" : "tail_tile";
 }
 
 std::string tune_key(const nnp_handle* h) {
@@ -607,6 +611,8 @@ nnp_status autotune(nnp_handle* h, const nnp_batch* b, const typename P::T* x, i
             if (mlp_fused_supported(h->shape.H1, h->shape.H2, h->shape.H3)) cand = {1, 2};
         } else if (k == NNP_KNOB_GEMM_STAGES) {
             cand = {2, 3};
+        } else if (k == NNP_KNOB_TAIL_TILE) {
+            if (knob_value(h, NNP_KNOB_MLP_PATH) == 1 && h->shape.row_tile == 128) cand = {1, 2, 3};
         } else {
             for (int c : {32, 64, 128, 256})
                 if (c < h->max_apm) cand.push_back(c);
@@ -934,6 +940,8 @@ nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value) {
         ok = ok || value == 1 || value == 2;
     } else if (knob == NNP_KNOB_GEMM_STAGES) {
         ok = ok || value == 2 || value == 3;
+    } else if (knob == NNP_KNOB_TAIL_TILE) {
+        ok = ok || (value >= 1 && value <= 3);
     } else {
         ok = ok || (value >= 16 && value <= kMaxAtomsPerMol);
     }
@@ -978,9 +986,10 @@ nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, i
             rc = autotune<PrecBF16>(h, b, (const float*)coords, reps, timings);
         if (rc) return rc;
     }
-    char vals[160];
-    std::snprintf(vals, sizeof(vals), "\"mlp_path\": %d, \"gemm_stages\": %d, \"cell_min\": %d",
-                  knob_value(h, 0), knob_value(h, 1), knob_value(h, 2));
+    char vals[200];
+    std::snprintf(vals, sizeof(vals),
+                  "\"mlp_path\": %d, \"gemm_stages\": %d, \"cell_min\": %d, \"tail_tile\": %d",
+                  knob_value(h, 0), knob_value(h, 1), knob_value(h, 2), knob_value(h, 3));
     if (!hit && cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(NNP_E_INVALID, std::string("cannot append to tune cache ") + cache_path);

@@ -58,8 +58,9 @@ EXPORTS = ("nnp_create", "nnp_destroy", "nnp_energy_forces", "nnp_energy_forces_
            "nnp_set_knob", "nnp_get_knob", "nnp_autotune")
 
 #: tunable knobs (include/nnp.h)
-KNOB_MLP_PATH, KNOB_GEMM_STAGES, KNOB_CELL_MIN = range(3)
-KNOBS = {"mlp_path": KNOB_MLP_PATH, "gemm_stages": KNOB_GEMM_STAGES, "cell_min": KNOB_CELL_MIN}
+KNOB_MLP_PATH, KNOB_GEMM_STAGES, KNOB_CELL_MIN, KNOB_TAIL_TILE = range(4)
+KNOBS = {"mlp_path": KNOB_MLP_PATH, "gemm_stages": KNOB_GEMM_STAGES, "cell_min": KNOB_CELL_MIN,
+         "tail_tile": KNOB_TAIL_TILE}
 
 
 def load_library(path: str = LIB_PATH):

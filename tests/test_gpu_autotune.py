@@ -16,7 +16,9 @@ pytestmark = pytest.mark.gpu
 
 # molecules above and below the cell thresholds tried, plus a one-atom one
 SIZES = [70, 1, 33, 150]
-VARIANTS = list(itertools.product([1, 2], [2, 3], [32, 1024]))
+VARIANTS = [dict(mlp_path=m, gemm_stages=g, cell_min=c, tail_tile=1)
+            for m, g, c in itertools.product([1, 2], [2, 3], [32, 1024])]
+VARIANTS += [dict(mlp_path=1, gemm_stages=2, cell_min=128, tail_tile=t) for t in (2, 3)]
 
 
 def _batch():
@@ -35,17 +37,15 @@ def test_every_variant_matches_oracle(orc, hp, prec):
     Eo, Fo = orc.energy_forces(hp, wo, M, b.species, xo, b.mol_offsets)
     dt = torch.float64 if prec == "fp64" else torch.float32
     x, sp, off = to_device(torch, b, dt)
-    for mlp, stages, cmin in VARIANTS:
-        h.set_knob("mlp_path", mlp)
-        h.set_knob("gemm_stages", stages)
-        h.set_knob("cell_min", cmin)
-        assert (h.get_knob("mlp_path"), h.get_knob("gemm_stages"), h.get_knob("cell_min")) == \
-            (mlp, stages, cmin)
+    for var in VARIANTS:
+        for k, v in var.items():
+            h.set_knob(k, v)
+        assert {k: h.get_knob(k) for k in var} == var
         E, F = h.energy_forces(x, sp, off)
         torch.cuda.synchronize()
         assert h.device_status() == 0
         E, F = E.cpu().numpy(), F.double().cpu().numpy()
-        case = f"{prec} mlp_path={mlp} gemm_stages={stages} cell_min={cmin}"
+        case = f"{prec} " + " ".join(f"{k}={v}" for k, v in var.items())
         if prec == "fp64":
             np.testing.assert_allclose(E, Eo, rtol=1e-10, err_msg=case)
             np.testing.assert_allclose(F, Fo, rtol=1e-8, atol=1e-9 * np.abs(Fo).max(), err_msg=case)
