@@ -146,8 +146,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 form")
     ap.add_argument("--no-forms", action="store_true", help="skip the like-for-like batched forms")
     ap.add_argument("--copy-mib", type=int, default=0,
-                    help="first run one plain device copy of this many MiB (a reference "
-                         "dispatch for HBM traffic counters)")
+                    help="first run one elementwise copy (negation) of this many MiB (a "
+                         "reference dispatch for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -162,10 +162,13 @@ def main():
     M = 8
     w = synth.xavier_weights(M, hp["widths"])
     if args.copy_mib:
+        # one elementwise pass that reads and writes copy_mib MiB each: a
+        # dispatch of known traffic (its own kernel name) for normalising HBM
+        # byte counters
         src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
 

@@ -90,32 +90,48 @@ __global__ __launch_bounds__(1024) void k_bucket_count(int A, int B, int S, int 
                                                        int32_t* __restrict__ mol_of_atom,
                                                        int32_t* __restrict__ blk_cnt,
                                                        int32_t* __restrict__ flag) {
-    __shared__ int cnt[kMaxSpecies];
-    const int tid = threadIdx.x, blk = blockIdx.x;
-    if (tid < kMaxSpecies) cnt[tid] = 0;
+    __shared__ int wcnt[kPrepBlock / 64][kMaxSpecies];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, blk = blockIdx.x;
     if (blk == 0 && tid == 0 && (mol_off[0] != 0 || mol_off[B] != A)) atomicOr(flag, FLAG_CAPACITY);
-    __syncthreads();
+    // molecule ranges are checked once, by one thread per molecule
     const int b = blk * kPrepBlock + tid;
     if (b < B) {
-        int a0 = mol_off[b], a1 = mol_off[b + 1];
-        if (a0 < 0 || a1 < a0 || a1 > A || a1 - a0 > max_apm)
-            atomicOr(flag, FLAG_CAPACITY);
-        else
-            for (int a = a0; a < a1; ++a) mol_of_atom[a] = b;
+        const int a0 = mol_off[b], a1 = mol_off[b + 1];
+        if (a0 < 0 || a1 < a0 || a1 > A || a1 - a0 > max_apm) atomicOr(flag, FLAG_CAPACITY);
     }
+    // per atom: its molecule (last b with mol_off[b] <= a, by bisection) and
+    // its element, counted per wave with ballots
     const int a = blk * kPrepBlock + tid;
+    int s = -1;
     if (a < A) {
-        int s = species[a];
+        int lo = 0, hi = B;   // mol_off[lo] <= a < mol_off[hi] for valid offsets
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (mol_off[mid] <= a) lo = mid;
+            else hi = mid;
+        }
+        mol_of_atom[a] = lo;
+        s = species[a];
         if (s < 0 || s >= S) {
             atomicOr(flag, FLAG_SPECIES);
             s = 0;
         }
-        atomicAdd(&cnt[s], 1);
+    }
+    for (int q = 0; q < S; ++q) {
+        const int c = __popcll(__ballot(s == q));
+        if (lane == 0) wcnt[wave][q] = c;
     }
     __syncthreads();
-    if (tid < kMaxSpecies) blk_cnt[blk * kMaxSpecies + tid] = cnt[tid];
+    if (tid < S) {
+        int c = 0;
+        for (int w = 0; w < kPrepBlock / 64; ++w) c += wcnt[w][tid];
+        blk_cnt[blk * kMaxSpecies + tid] = c;
+    }
 }
 
+// Per-element exclusive prefix of the per-block counts (two passes over
+// contiguous block ranges, one range per thread), padded bucket starts, the
+// element of every row tile and the padding rows.
 __global__ __launch_bounds__(256) void k_bucket_scan(int nblk, int S, int row_tile, int Rcap,
                                                      const int32_t* __restrict__ blk_cnt,
                                                      int32_t* __restrict__ blk_base,
@@ -123,25 +139,34 @@ __global__ __launch_bounds__(256) void k_bucket_scan(int nblk, int S, int row_ti
                                                      int32_t* __restrict__ tile_species,
                                                      BucketInfo* __restrict__ info,
                                                      int32_t* __restrict__ flag) {
+    __shared__ int part[256][kMaxSpecies + 1];
     __shared__ int tot[kMaxSpecies];
     __shared__ int base[kMaxSpecies + 1];
-    const int tid = threadIdx.x;
-    if (tid < S) {   // one thread per element walks the blocks in order
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int per = (nblk + nt - 1) / nt, k0 = min(tid * per, nblk), k1 = min(k0 + per, nblk);
+    int sum[kMaxSpecies];
+    for (int q = 0; q < kMaxSpecies; ++q) sum[q] = 0;
+    for (int k = k0; k < k1; ++k)
+        for (int q = 0; q < S; ++q) sum[q] += blk_cnt[k * kMaxSpecies + q];
+    for (int q = 0; q < S; ++q) part[tid][q] = sum[q];
+    __syncthreads();
+    if (tid < S) {   // exclusive scan over the threads' ranges, per element
         int run = 0;
-        for (int k = 0; k < nblk; ++k) {
-            blk_base[k * kMaxSpecies + tid] = run;
-            run += blk_cnt[k * kMaxSpecies + tid];
+        for (int t = 0; t < nt; ++t) {
+            const int v = part[t][tid];
+            part[t][tid] = run;
+            run += v;
         }
         tot[tid] = run;
     }
     __syncthreads();
     if (tid == 0) {
         base[0] = 0;
-        for (int s = 0; s < S; ++s) {
-            base[s + 1] = base[s] + ((tot[s] + row_tile - 1) / row_tile) * row_tile;
-            info->count[s] = tot[s];
+        for (int q = 0; q < S; ++q) {
+            base[q + 1] = base[q] + ((tot[q] + row_tile - 1) / row_tile) * row_tile;
+            info->count[q] = tot[q];
         }
-        for (int s = 0; s <= S; ++s) info->off[s] = base[s];
+        for (int q = 0; q <= S; ++q) info->off[q] = base[q];
         int rows = base[S];
         if (rows > Rcap) {
             atomicOr(flag, FLAG_CAPACITY);
@@ -150,21 +175,26 @@ __global__ __launch_bounds__(256) void k_bucket_scan(int nblk, int S, int row_ti
         info->rows = rows;
     }
     __syncthreads();
-    const int rows = base[S] <= Rcap ? base[S] : 0;
-    if (tid < S) {   // bucket starts become absolute
-        for (int k = 0; k < nblk; ++k) blk_base[k * kMaxSpecies + tid] += base[tid];
+    // absolute bucket start of every block's first atom of each element
+    for (int q = 0; q < S; ++q) {
+        int run = base[q] + part[tid][q];
+        for (int k = k0; k < k1; ++k) {
+            blk_base[k * kMaxSpecies + q] = run;
+            run += blk_cnt[k * kMaxSpecies + q];
+        }
     }
-    for (int t = tid; t < Rcap / row_tile; t += blockDim.x) {
-        int r = t * row_tile, s = -1;
+    const int rows = base[S] <= Rcap ? base[S] : 0;
+    for (int t = tid; t < Rcap / row_tile; t += nt) {
+        const int r = t * row_tile;
+        int sp = -1;
         if (r < rows)
             for (int q = 0; q < S; ++q)
-                if (base[q] <= r && r < base[q + 1]) s = q;
-        tile_species[t] = s;
+                if (base[q] <= r && r < base[q + 1]) sp = q;
+        tile_species[t] = sp;
     }
     // padding rows of every bucket
-    for (int s = 0; s < S; ++s)
-        for (int r = base[s] + tot[s] + tid; r < base[s + 1] && r < rows; r += blockDim.x)
-            atom_of_row[r] = -1;
+    for (int q = 0; q < S; ++q)
+        for (int r = base[q] + tot[q] + tid; r < base[q + 1] && r < rows; r += nt) atom_of_row[r] = -1;
 }
 
 __global__ __launch_bounds__(1024) void k_bucket_scatter(int A, int S, const int32_t* __restrict__ species,
