@@ -14,6 +14,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nnp_oracle.c")
+_SRC_COUPLING = os.path.join(_HERE, "coupling_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
@@ -22,7 +23,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, _SRC, _SRC_COUPLING, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -74,6 +75,9 @@ def _load():
         lib.orc_param_grad.argtypes = [P(_AEV), P(_Net), d, i32, P(i32), P(i32), P(d), P(d),
                                        P(d), P(d)]
         lib.orc_num_threads.restype = i32
+        lib.orc_coupling.restype = None
+        lib.orc_coupling.argtypes = [i32, P(d), P(d), i32, P(d), P(d), d, d, P(d), P(d), P(d),
+                                     P(d)]
         _lib = lib
     return _lib
 
@@ -210,3 +214,23 @@ def param_grad(hp: dict, weights, n_models: int, species, coords, mol_offsets, g
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def coupling(x_nnp, par_nnp, x_mm, par_mm, k, cutoff=0.0, with_abs=False):
+    """NNP-MM mechanical-embedding coupling (Methods, Eq. 4): energy, forces
+    on the NNP atoms and on the MM atoms.  par_* are [n][3] = (q, sigma,
+    eps); Lorentz-Berthelot pair parameters; cutoff 0 = every pair."""
+    lib = _load()
+    xn = np.ascontiguousarray(x_nnp, dtype=np.float64).reshape(-1, 3)
+    pn = np.ascontiguousarray(par_nnp, dtype=np.float64).reshape(-1, 3)
+    xm = np.ascontiguousarray(x_mm, dtype=np.float64).reshape(-1, 3)
+    pm = np.ascontiguousarray(par_mm, dtype=np.float64).reshape(-1, 3)
+    E = np.zeros(1)
+    A = np.zeros(1)
+    Fn = np.zeros_like(xn)
+    Fm = np.zeros_like(xm)
+    lib.orc_coupling(len(xn), _dp(xn), _dp(pn), len(xm), _dp(xm), _dp(pm), float(k), float(cutoff),
+                     _dp(E), _dp(Fn), _dp(Fm), _dp(A))
+    if with_abs:
+        return float(E[0]), Fn, Fm, float(A[0])
+    return float(E[0]), Fn, Fm

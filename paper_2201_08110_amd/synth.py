@@ -229,3 +229,61 @@ def random_batch(seed: int, sizes, box_scale: float = 2.2, ratio=LIGAND_RATIO) -
 def round_to_fp32(a: np.ndarray) -> np.ndarray:
     """FP32-rounded values widened back to FP64 (what an FP32 path really sees)."""
     return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# NNP-MM coupling workload (mechanical embedding, Methods, Eq. 4).
+#
+# e^2 / (4 pi eps0) from the SI defining constants, in kcal/mol * A / e^2
+# (the unit system of the energies here): e = 1.602176634e-19 C,
+# eps0 = 8.8541878128e-12 F/m, N_A = 6.02214076e23 /mol, 1 kcal = 4184 J.
+COULOMB_K = (1.602176634e-19 ** 2 / (4.0 * math.pi * 8.8541878128e-12)
+             * 6.02214076e23 / 4184.0 * 1e10)
+
+# atoms of the protein-ligand systems the paper simulates (Results, Table 1:
+# 1HPO has a 64-atom ligand in 47,712 atoms in all)
+COUPLING_TOTAL_ATOMS = 47712
+
+
+@dataclass
+class CouplingSystem:
+    x_nnp: np.ndarray     # [n_nnp, 3] A
+    par_nnp: np.ndarray   # [n_nnp, 3] (charge e, sigma A, epsilon kcal/mol)
+    x_mm: np.ndarray      # [n_mm, 3]
+    par_mm: np.ndarray    # [n_mm, 3]
+
+
+def _neutral_charges(rng, n, scale):
+    q = rng.normal(0.0, scale, size=n)
+    return q - q.mean()
+
+
+def coupling_system(seed: int = BASE_SEED + 100, n_mm: int | None = None,
+                    density: float = 0.1, min_dist: float = 2.2) -> CouplingSystem:
+    """A ligand (the 64-atom ligand of workload 2) at the centre of a cube of
+    MM atoms at liquid density (0.1 atoms per A^3), MM atoms kept at least
+    `min_dist` from every ligand atom.  Charges are seeded normals made
+    neutral per region; Lennard-Jones sigma in U(2.4, 3.6) A and epsilon in
+    U(0.02, 0.2) kcal/mol.  Synthetic stand-ins for the force-field
+    parameters the paper's systems carry."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    lig = config_batch(2)
+    x_nnp = lig.coords - lig.coords.mean(axis=0)
+    n_nnp = len(x_nnp)
+    if n_mm is None:
+        n_mm = COUPLING_TOTAL_ATOMS - n_nnp
+    edge = (n_mm / density) ** (1.0 / 3.0)
+    keep = []
+    total = 0
+    while total < n_mm:
+        cand = rng.uniform(-edge / 2, edge / 2, size=(max(2 * (n_mm - total), 64), 3))
+        d2 = ((cand[:, None, :] - x_nnp[None, :, :]) ** 2).sum(-1).min(axis=1)
+        cand = cand[d2 >= min_dist ** 2]
+        keep.append(cand[: n_mm - total])
+        total += len(keep[-1])
+    x_mm = np.concatenate(keep)[:n_mm]
+    par_nnp = np.stack([_neutral_charges(rng, n_nnp, 0.25), rng.uniform(2.4, 3.6, n_nnp),
+                        rng.uniform(0.02, 0.2, n_nnp)], axis=1)
+    par_mm = np.stack([_neutral_charges(rng, n_mm, 0.35), rng.uniform(2.4, 3.6, n_mm),
+                       rng.uniform(0.02, 0.2, n_mm)], axis=1)
+    return CouplingSystem(x_nnp, par_nnp, x_mm, par_mm)
