@@ -251,6 +251,40 @@ nnp_status nnp_get_knob(nnp_handle* h, int32_t knob, int32_t* value);
 nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, int32_t reps,
                         const char* cache_path, char* report, int32_t report_cap);
 
+/* ---- NNP-MM coupling (mechanical embedding) --------------------------------
+ * The coupling term of an NNP/MM energy (Methods, Eq. 4): every NNP atom i
+ * interacts with every MM atom j through
+ *
+ *   k q_i q_j / r_ij + 4 eps_ij ((sigma_ij / r_ij)^12 - (sigma_ij / r_ij)^6),
+ *
+ * k = 1 / (4 pi eps0) in the caller's units (332.0637133 kcal/mol A / e^2 for
+ * kcal/mol, A, e), with Lorentz-Berthelot pair parameters sigma_ij =
+ * (sigma_i + sigma_j) / 2 and eps_ij = sqrt(eps_i eps_j).  cutoff > 0 drops
+ * every pair with r_ij >= cutoff (a plain truncation); cutoff = 0 keeps all.
+ *
+ * nnp_coupling_create: precision NNP_PREC_FP64 or NNP_PREC_FP32 (the operand
+ * and force type; the energy is always summed in FP64); capacities max_nnp
+ * (1..1024) and max_mm (>= 1); allocates its workspace on `device`.
+ *
+ * nnp_coupling_eval: all arrays are device pointers of the handle's type:
+ * x_nnp [n_nnp][3], par_nnp [n_nnp][3] = (q, sigma, eps), likewise for MM;
+ * out_E one double; F_nnp [n_nnp][3] and F_mm [n_mm][3] receive -dV/dx.
+ * flags: 0 overwrites the outputs, NNP_FLAG_ACCUMULATE adds to them (for
+ * example onto the NNP energy and forces of the same step).  Runs on
+ * `stream` (a hipStream_t); allocates nothing; the result is independent of
+ * launch configuration and bitwise repeatable (no atomics).  Sizes above the
+ * capacities return NNP_E_CAPACITY; null pointers NNP_E_INVALID (n = 0 sides
+ * may pass NULL arrays). */
+#define NNP_FLAG_ACCUMULATE 2u
+
+typedef struct nnp_coupling nnp_coupling;
+nnp_status nnp_coupling_create(int32_t precision, int32_t max_nnp, int32_t max_mm, double coulomb_k,
+                               double cutoff, int32_t device, nnp_coupling** out);
+void nnp_coupling_destroy(nnp_coupling* c);
+nnp_status nnp_coupling_eval(nnp_coupling* c, int32_t n_nnp, const void* x_nnp, const void* par_nnp,
+                             int32_t n_mm, const void* x_mm, const void* par_mm, double* out_E,
+                             void* F_nnp, void* F_mm, void* stream, uint32_t flags);
+
 /* Message of the calling thread's last host-side error ("" if none). */
 const char* nnp_last_error(void);
 

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -216,6 +217,18 @@ inline hipError_t ensure_lds(const void* kern, size_t bytes) {
     if (e == hipSuccess) done[key] = bytes;
     return e;
 }
+
+// NNP-MM coupling (fixed at creation of a coupling handle)
+struct CouplingShape {
+    double coulomb_k;   // 1 / (4 pi eps0) in the caller's units
+    double cutoff;      // 0: every pair
+    int max_nnp, max_mm;
+    int chunk;          // MM atoms per workgroup of the NNP-side force kernel
+};
+template <typename T>
+hipError_t launch_coupling(const CouplingShape& cs, int n_nnp, const T* x_nnp, const T* par_nnp,
+                           int n_mm, const T* x_mm, const T* par_mm, double* E, T* F_nnp, T* F_mm,
+                           double* e_part, T* f_part, bool accumulate, hipStream_t st);
 
 // launchers (explicitly instantiated for PrecF64 / PrecF32 / PrecBF16)
 template <typename P>

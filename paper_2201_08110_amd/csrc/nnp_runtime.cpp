@@ -1004,4 +1004,93 @@ nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, i
     return NNP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// NNP-MM coupling
+
+}  // extern "C"
+
+struct nnp_coupling {
+    nnp::CouplingShape cs{};
+    int precision = NNP_PREC_FP32;
+    int device = 0;
+    double* e_part = nullptr;   // [ceil(max_mm / 256)]
+    void* f_part = nullptr;     // [ceil(max_mm / chunk)][max_nnp][3]
+};
+
+extern "C" {
+
+nnp_status nnp_coupling_create(int32_t precision, int32_t max_nnp, int32_t max_mm, double coulomb_k,
+                               double cutoff, int32_t device, nnp_coupling** out) {
+    if (!out) return fail(NNP_E_INVALID, "null output pointer");
+    *out = nullptr;
+    if (precision != NNP_PREC_FP64 && precision != NNP_PREC_FP32)
+        return fail(NNP_E_INVALID, "coupling precision must be FP64 or FP32");
+    if (max_nnp < 1 || max_nnp > 1024) return fail(NNP_E_INVALID, "max_nnp must be in 1..1024");
+    if (max_mm < 1 || max_mm > (1 << 26)) return fail(NNP_E_INVALID, "max_mm must be in 1..2^26");
+    if (!std::isfinite(coulomb_k) || !(cutoff >= 0.0) || !std::isfinite(cutoff))
+        return fail(NNP_E_INVALID, "coulomb_k must be finite and cutoff >= 0");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(NNP_E_DEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(NNP_E_INVALID, "device ordinal out of range");
+    DeviceGuard dg(device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    nnp_coupling* c = new nnp_coupling();
+    c->precision = precision;
+    c->device = device;
+    c->cs.coulomb_k = coulomb_k;
+    c->cs.cutoff = cutoff;
+    c->cs.max_nnp = max_nnp;
+    c->cs.max_mm = max_mm;
+    // MM atoms per NNP-side workgroup: 64, widened so that at most 1024
+    // chunks (and partial force rows) exist at capacity
+    c->cs.chunk = 64 * std::max(1, (max_mm + 64 * 1024 - 1) / (64 * 1024));
+    const size_t tsz = precision == NNP_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const size_t n_eblk = (size_t)(max_mm + 255) / 256;
+    const size_t n_chunks = (size_t)(max_mm + c->cs.chunk - 1) / c->cs.chunk;
+    hipError_t e = hipMalloc(&c->e_part, sizeof(double) * n_eblk);
+    if (e == hipSuccess) e = hipMalloc(&c->f_part, tsz * 3 * n_chunks * (size_t)max_nnp);
+    if (e != hipSuccess) {
+        nnp_coupling_destroy(c);
+        return fail(NNP_E_NOMEM, "coupling workspace allocation failed");
+    }
+    *out = c;
+    return NNP_OK;
+}
+
+void nnp_coupling_destroy(nnp_coupling* c) {
+    if (!c) return;
+    DeviceGuard dg(c->device);
+    (void)hipDeviceSynchronize();
+    if (c->e_part) (void)hipFree(c->e_part);
+    if (c->f_part) (void)hipFree(c->f_part);
+    delete c;
+}
+
+nnp_status nnp_coupling_eval(nnp_coupling* c, int32_t n_nnp, const void* x_nnp, const void* par_nnp,
+                             int32_t n_mm, const void* x_mm, const void* par_mm, double* out_E,
+                             void* F_nnp, void* F_mm, void* stream, uint32_t flags) {
+    if (!c || !out_E) return fail(NNP_E_INVALID, "null coupling handle or out_E");
+    if (n_nnp < 0 || n_mm < 0) return fail(NNP_E_INVALID, "negative atom count");
+    if (n_nnp > c->cs.max_nnp || n_mm > c->cs.max_mm)
+        return fail(NNP_E_CAPACITY, "coupling system exceeds the capacity given at creation");
+    if (n_nnp > 0 && (!x_nnp || !par_nnp || !F_nnp)) return fail(NNP_E_INVALID, "null NNP array");
+    if (n_mm > 0 && (!x_mm || !par_mm || !F_mm)) return fail(NNP_E_INVALID, "null MM array");
+    if (flags & ~NNP_FLAG_ACCUMULATE) return fail(NNP_E_INVALID, "unknown flag");
+    DeviceGuard dg(c->device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    const bool acc = (flags & NNP_FLAG_ACCUMULATE) != 0;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (c->precision == NNP_PREC_FP64)
+        e = launch_coupling<double>(c->cs, n_nnp, (const double*)x_nnp, (const double*)par_nnp, n_mm,
+                                    (const double*)x_mm, (const double*)par_mm, out_E, (double*)F_nnp,
+                                    (double*)F_mm, c->e_part, (double*)c->f_part, acc, st);
+    else
+        e = launch_coupling<float>(c->cs, n_nnp, (const float*)x_nnp, (const float*)par_nnp, n_mm,
+                                   (const float*)x_mm, (const float*)par_mm, out_E, (float*)F_nnp,
+                                   (float*)F_mm, c->e_part, (float*)c->f_part, acc, st);
+    if (e != hipSuccess) return fail(NNP_E_DEVICE, std::string("coupling launch: ") + hipGetErrorString(e));
+    return NNP_OK;
+}
+
 }  // extern "C"

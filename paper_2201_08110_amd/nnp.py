@@ -55,7 +55,10 @@ _lib = None
 EXPORTS = ("nnp_create", "nnp_destroy", "nnp_energy_forces", "nnp_energy_forces_f64", "nnp_aev",
            "nnp_energy_forces_backward", "nnp_set_weights", "nnp_num_params", "nnp_aev_dim",
            "nnp_get_device_status", "nnp_set_timing", "nnp_kernel_times", "nnp_last_error",
-           "nnp_set_knob", "nnp_get_knob", "nnp_autotune")
+           "nnp_set_knob", "nnp_get_knob", "nnp_autotune",
+           "nnp_coupling_create", "nnp_coupling_destroy", "nnp_coupling_eval")
+
+FLAG_ACCUMULATE = 2
 
 #: tunable knobs (include/nnp.h)
 KNOB_MLP_PATH, KNOB_GEMM_STAGES, KNOB_CELL_MIN, KNOB_TAIL_TILE = range(4)
@@ -105,6 +108,12 @@ def load_library(path: str = LIB_PATH):
     lib.nnp_get_knob.restype = i32
     lib.nnp_autotune.argtypes = [vp, P(Batch), vp, i32, C.c_char_p, C.c_char_p, i32]
     lib.nnp_autotune.restype = i32
+    lib.nnp_coupling_create.argtypes = [i32, i32, i32, d, d, i32, P(vp)]
+    lib.nnp_coupling_create.restype = i32
+    lib.nnp_coupling_destroy.argtypes = [vp]
+    lib.nnp_coupling_destroy.restype = None
+    lib.nnp_coupling_eval.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_uint32]
+    lib.nnp_coupling_eval.restype = i32
     _lib = lib
     return lib
 
@@ -311,3 +320,50 @@ class NNP:
         ms = (C.c_double * max(n, 1))()
         n = self.lib.nnp_kernel_times(self.h, n, names, counts, ms)
         return {names[i].decode(): (int(counts[i]), float(ms[i])) for i in range(n)}
+
+
+class Coupling:
+    """NNP-MM mechanical-embedding coupling (include/nnp.h): energy and
+    forces on both regions, FP64 or FP32, on the device."""
+
+    def __init__(self, max_nnp: int, max_mm: int, coulomb_k: float, cutoff: float = 0.0,
+                 precision: str = "fp32", device: int = 0):
+        lib = load_library()
+        if precision not in ("fp32", "fp64"):
+            raise ValueError("coupling precision is fp32 or fp64")
+        h = C.c_void_p()
+        _check(lib.nnp_coupling_create(PREC[precision], int(max_nnp), int(max_mm), float(coulomb_k),
+                                       float(cutoff), int(device), C.byref(h)))
+        self.h, self.lib, self.precision, self.device = h, lib, precision, device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nnp_coupling_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __call__(self, x_nnp, par_nnp, x_mm, par_mm, out=None, accumulate: bool = False,
+                 stream=None):
+        """E (1-element float64 tensor), F_nnp [n_nnp, 3], F_mm [n_mm, 3]."""
+        import torch
+        dt = torch.float64 if self.precision == "fp64" else torch.float32
+        for t, name in ((x_nnp, "x_nnp"), (par_nnp, "par_nnp"), (x_mm, "x_mm"), (par_mm, "par_mm")):
+            NNP._need(t, dt, name)
+        n_nnp, n_mm = x_nnp.shape[0], x_mm.shape[0]
+        if out is None:
+            E = torch.zeros(1, dtype=torch.float64, device=x_nnp.device)
+            Fn = torch.zeros_like(x_nnp)
+            Fm = torch.zeros_like(x_mm)
+        else:
+            E, Fn, Fm = out
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(self.lib.nnp_coupling_eval(self.h, n_nnp, x_nnp.data_ptr(), par_nnp.data_ptr(), n_mm,
+                                          x_mm.data_ptr(), par_mm.data_ptr(), E.data_ptr(),
+                                          Fn.data_ptr(), Fm.data_ptr(), s.cuda_stream,
+                                          FLAG_ACCUMULATE if accumulate else 0))
+        return E, Fn, Fm

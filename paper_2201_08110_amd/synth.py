@@ -272,16 +272,22 @@ def coupling_system(seed: int = BASE_SEED + 100, n_mm: int | None = None,
     n_nnp = len(x_nnp)
     if n_mm is None:
         n_mm = COUPLING_TOTAL_ATOMS - n_nnp
-    edge = (n_mm / density) ** (1.0 / 3.0)
+    # the cube holds the ligand with room to spare even for a few MM atoms
+    extent = float(np.abs(x_nnp).max())
+    edge = max((n_mm / density) ** (1.0 / 3.0), 2.0 * (extent + min_dist) + 8.0)
     keep = []
     total = 0
-    while total < n_mm:
+    for _ in range(1000):
+        if total >= n_mm:
+            break
         cand = rng.uniform(-edge / 2, edge / 2, size=(max(2 * (n_mm - total), 64), 3))
         d2 = ((cand[:, None, :] - x_nnp[None, :, :]) ** 2).sum(-1).min(axis=1)
         cand = cand[d2 >= min_dist ** 2]
         keep.append(cand[: n_mm - total])
         total += len(keep[-1])
-    x_mm = np.concatenate(keep)[:n_mm]
+    if total < n_mm:
+        raise RuntimeError("could not place the MM atoms")
+    x_mm = np.concatenate(keep)[:n_mm] if keep else np.zeros((0, 3))
     par_nnp = np.stack([_neutral_charges(rng, n_nnp, 0.25), rng.uniform(2.4, 3.6, n_nnp),
                         rng.uniform(0.02, 0.2, n_nnp)], axis=1)
     par_mm = np.stack([_neutral_charges(rng, n_mm, 0.35), rng.uniform(2.4, 3.6, n_mm),

@@ -80,6 +80,17 @@ def test_null_arguments():
     assert lib.nnp_set_knob(None, 0, 0) == nnp.NNP_E_INVALID
     assert lib.nnp_get_knob(None, 0, C.byref(v)) == nnp.NNP_E_INVALID
     assert lib.nnp_autotune(None, None, None, 1, None, None, 0) == nnp.NNP_E_INVALID
+    h2 = C.c_void_p(7)
+    assert lib.nnp_coupling_create(1, 64, 100, 332.0, 0.0, 0, None) == nnp.NNP_E_INVALID
+    for prec, n_nnp, n_mm, k, rc in ((7, 64, 100, 332.0, 0.0), (2, 64, 100, 332.0, 0.0),
+                                     (1, 0, 100, 332.0, 0.0), (1, 2000, 100, 332.0, 0.0),
+                                     (1, 64, 0, 332.0, 0.0), (1, 64, 100, float("nan"), 0.0),
+                                     (1, 64, 100, 332.0, -1.0)):
+        assert lib.nnp_coupling_create(prec, n_nnp, n_mm, k, rc, 0, C.byref(h2)) == nnp.NNP_E_INVALID
+        assert h2.value is None
+    assert lib.nnp_coupling_eval(None, 0, None, None, 0, None, None, None, None, None, None, 0) == \
+        nnp.NNP_E_INVALID
+    lib.nnp_coupling_destroy(None)
     lib.nnp_destroy(None)
 
 
