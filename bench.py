@@ -136,6 +136,55 @@ def cpu_baseline(hp, w, M, make_sample, budget_s=12.0):
     return atoms / elapsed, atoms, elapsed, oracle.num_threads(), first
 
 
+# flops of one coupling pair as counted here: distance (8), reciprocal and
+# reciprocal square root (2), Coulomb (2), Lennard-Jones powers and energy
+# (9), dV/dr (6), force components (6); every pair is evaluated once per side
+COUPLING_FLOPS_PER_PAIR = 33
+
+
+def coupling_form(torch, nnp, synth, args):
+    s = synth.coupling_system()
+    n_pairs = len(s.x_nnp) * len(s.x_mm)
+    res = {"workload": f"{len(s.x_nnp)}-atom ligand in {len(s.x_mm)} MM atoms (all pairs)",
+           "pairs": n_pairs}
+    for prec in ("fp32", "fp64"):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        c = nnp.Coupling(len(s.x_nnp), len(s.x_mm), synth.COULOMB_K, 0.0, prec)
+        xs = [torch.tensor(a, dtype=dt, device="cuda") for a in (s.x_nnp, s.par_nnp, s.x_mm, s.par_mm)]
+        out = c(*xs)
+        # time the C ABI call itself: arguments marshalled once
+        args_ = (c.h, len(s.x_nnp), xs[0].data_ptr(), xs[1].data_ptr(), len(s.x_mm), xs[2].data_ptr(),
+                 xs[3].data_ptr(), out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+                 torch.cuda.current_stream().cuda_stream, 0)
+        fn = c.lib.nnp_coupling_eval
+        for _ in range(5):
+            fn(*args_)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        reps = 200
+        for _ in range(reps):
+            fn(*args_)
+        e1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        fl = 2 * COUPLING_FLOPS_PER_PAIR * n_pairs
+        peak = PEAK["fp32"] if prec == "fp32" else PEAK["fp64"]
+        res[prec] = {"us_per_eval": us, "pair_evals_per_s": n_pairs / (us * 1e-6),
+                     "roofline": {"bound": "alu", "achieved": fl / (us * 1e-6) / 1e12,
+                                  "peak": peak / 1e12, "unit": "TFLOP/s",
+                                  "frac": fl / (us * 1e-6) / peak}}
+        c.close()
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.coupling(s.x_nnp, s.par_nnp, s.x_mm, s.par_mm, synth.COULOMB_K)
+        t = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": n_pairs / t, "unit": "pair-evals/s", "cores": 1,
+                               "kind": "oracle", "sample": "the whole system once, FP64"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +194,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 form")
     ap.add_argument("--no-forms", action="store_true", help="skip the like-for-like batched forms")
+    ap.add_argument("--no-coupling", action="store_true", help="skip the NNP-MM coupling form")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one elementwise copy (negation) of this many MiB (a "
                          "reference dispatch for HBM traffic counters)")
@@ -243,6 +293,10 @@ def main():
                                            "ms_per_eval": secf * 1e3, "atoms": int(b.n_atoms)}
                 hf.close()
         out["batched_forms"] = forms
+
+    # ---- NNP-MM coupling (Eq. 4): the 64-atom ligand in 47,648 MM atoms --
+    if not args.no_coupling:
+        out["coupling"] = coupling_form(torch, nnp, synth, args)
 
     # ---- CPU baseline + accuracy on the sample ---------------------------
     if not args.no_cpu:

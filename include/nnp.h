@@ -264,7 +264,7 @@ nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, i
  *
  * nnp_coupling_create: precision NNP_PREC_FP64 or NNP_PREC_FP32 (the operand
  * and force type; the energy is always summed in FP64); capacities max_nnp
- * (1..1024) and max_mm (>= 1); allocates its workspace on `device`.
+ * (1..1024) and max_mm (1..2^22); allocates its workspace on `device`.
  *
  * nnp_coupling_eval: all arrays are device pointers of the handle's type:
  * x_nnp [n_nnp][3], par_nnp [n_nnp][3] = (q, sigma, eps), likewise for MM;

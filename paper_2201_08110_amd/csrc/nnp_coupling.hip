@@ -7,11 +7,12 @@
 // eps_ij = sqrt(eps_i eps_j) and an optional plain cutoff.  Forces act on both
 // sides.  Both force sums are formed without atomics and in a fixed order:
 //
-//   k_couple_mm   one thread per MM atom, the NNP atoms staged in LDS:
+//   MM side       one thread per MM atom, the NNP atoms staged in LDS:
 //                 F_j and a per-block energy partial;
-//   k_couple_nnp  one thread per NNP atom for one chunk of MM atoms staged
+//   NNP side      one thread per NNP atom for one chunk of MM atoms staged
 //                 in LDS: per-chunk partial F_i;
-//   k_couple_sum  fixed-order sums of the partials into F_i and E.
+//                 (both sides run as the two halves of one launch)
+//   k_couple_sum  fixed-shape sums of the partials into F_i and E.
 //
 // Each pair is therefore evaluated twice (once per side), which costs
 // ~30 flops per pair and saves every cross-thread reduction of the scatter.
@@ -52,16 +53,14 @@ __device__ inline void load_atom(const T* __restrict__ x, const T* __restrict__ 
     out[5] = sqrt(par[3 * (size_t)i + 2]);
 }
 
+// MM side: one thread per MM atom j, the NNP atoms in LDS (s, [6][n_nnp]);
+// F_j and the block's energy partial.  Two accumulator sets over alternate
+// NNP atoms keep two independent dependency chains in flight.
 template <typename T>
-__global__ __launch_bounds__(kMmBlock) void k_couple_mm(int n_nnp, const T* __restrict__ x_nnp,
-                                                        const T* __restrict__ par_nnp, int n_mm,
-                                                        const T* __restrict__ x_mm,
-                                                        const T* __restrict__ par_mm, T k, T rc2,
-                                                        T* __restrict__ F_mm, int accumulate,
-                                                        double* __restrict__ e_part) {
-    extern __shared__ __align__(16) char smem[];
-    T* s = (T*)smem;   // [kCoupleVals][n_nnp]
-    __shared__ double red[kMmBlock / 64];
+__device__ inline void couple_mm_side(int blk, int n_nnp, const T* __restrict__ x_nnp,
+                                      const T* __restrict__ par_nnp, int n_mm, const T* __restrict__ x_mm,
+                                      const T* __restrict__ par_mm, T k, T rc2, T* __restrict__ F_mm,
+                                      int accumulate, double* __restrict__ e_part, T* s, double* red) {
     for (int i = threadIdx.x; i < n_nnp; i += blockDim.x) {
         T a[kCoupleVals];
         load_atom(x_nnp, par_nnp, i, a);
@@ -69,98 +68,141 @@ __global__ __launch_bounds__(kMmBlock) void k_couple_mm(int n_nnp, const T* __re
         for (int v = 0; v < kCoupleVals; ++v) s[v * n_nnp + i] = a[v];
     }
     __syncthreads();
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blk * blockDim.x + threadIdx.x;
     double e = 0.0;
     if (j < n_mm) {
         T b[kCoupleVals];
         load_atom(x_mm, par_mm, j, b);
-        T f0 = 0, f1 = 0, f2 = 0;
-        for (int i = 0; i < n_nnp; ++i) {
+        T f[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        double eh[2] = {0.0, 0.0};
+        int i = 0;
+        for (; i + 1 < n_nnp; i += 2) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int ii = i + u;
+                const T d0 = b[0] - s[ii], d1 = b[1] - s[n_nnp + ii], d2 = b[2] - s[2 * n_nnp + ii];
+                const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                if (rc2 > T(0) && r2 >= rc2) continue;
+                T v, dvr;
+                couple_pair(k, r2, s[3 * n_nnp + ii] * b[3], s[4 * n_nnp + ii] + b[4],
+                            s[5 * n_nnp + ii] * b[5], v, dvr);
+                eh[u] += (double)v;
+                f[u][0] -= dvr * d0;
+                f[u][1] -= dvr * d1;
+                f[u][2] -= dvr * d2;
+            }
+        }
+        if (i < n_nnp) {
             const T d0 = b[0] - s[i], d1 = b[1] - s[n_nnp + i], d2 = b[2] - s[2 * n_nnp + i];
             const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            if (rc2 > T(0) && r2 >= rc2) continue;
-            T v, dvr;
-            couple_pair(k, r2, s[3 * n_nnp + i] * b[3], s[4 * n_nnp + i] + b[4], s[5 * n_nnp + i] * b[5], v, dvr);
-            e += (double)v;
-            f0 -= dvr * d0;
-            f1 -= dvr * d1;
-            f2 -= dvr * d2;
+            if (!(rc2 > T(0) && r2 >= rc2)) {
+                T v, dvr;
+                couple_pair(k, r2, s[3 * n_nnp + i] * b[3], s[4 * n_nnp + i] + b[4], s[5 * n_nnp + i] * b[5],
+                            v, dvr);
+                eh[0] += (double)v;
+                f[0][0] -= dvr * d0;
+                f[0][1] -= dvr * d1;
+                f[0][2] -= dvr * d2;
+            }
         }
+        e = eh[0] + eh[1];
         T* F = F_mm + 3 * (size_t)j;
-        if (accumulate) {
-            F[0] += f0;
-            F[1] += f1;
-            F[2] += f2;
-        } else {
-            F[0] = f0;
-            F[1] = f1;
-            F[2] = f2;
-        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F[c] = (accumulate ? F[c] : T(0)) + (f[0][c] + f[1][c]);
     }
     for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-        e_part[blockIdx.x] = t;
-    }
+    if (threadIdx.x == 0) e_part[blk] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// NNP side: each wave takes one chunk of MM atoms (staged in its own LDS
+// slice) and one group of 64 NNP atoms, a thread per NNP atom; partial F_i of
+// the chunk, stored component-major ([3 n_nnp][n_chunks]).
 template <typename T>
-__global__ __launch_bounds__(64) void k_couple_nnp(int n_nnp, const T* __restrict__ x_nnp,
-                                                   const T* __restrict__ par_nnp, int n_mm,
-                                                   const T* __restrict__ x_mm,
-                                                   const T* __restrict__ par_mm, T k, T rc2,
-                                                   int chunk, T* __restrict__ f_part) {
-    extern __shared__ __align__(16) char smem[];
-    T* s = (T*)smem;   // [kCoupleVals][chunk]
-    const int c = blockIdx.y, j0 = c * chunk, nj = min(chunk, n_mm - j0);
-    for (int t = threadIdx.x; t < nj; t += blockDim.x) {
+__device__ inline void couple_nnp_side(int blk, int n_cg, int n_chunks, int n_nnp, const T* __restrict__ x_nnp,
+                                       const T* __restrict__ par_nnp, int n_mm, const T* __restrict__ x_mm,
+                                       const T* __restrict__ par_mm, T k, T rc2, int chunk,
+                                       T* __restrict__ f_part, T* s_all) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = blk / n_cg, c = (blk % n_cg) * 4 + wave;
+    if (c >= n_chunks) return;
+    T* s = s_all + (size_t)wave * kCoupleVals * chunk;
+    const int j0 = c * chunk, nj = min(chunk, n_mm - j0);
+    for (int t = lane; t < nj; t += 64) {
         T b[kCoupleVals];
         load_atom(x_mm, par_mm, j0 + t, b);
 #pragma unroll
         for (int v = 0; v < kCoupleVals; ++v) s[v * chunk + t] = b[v];
     }
-    __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int i = g * 64 + lane;
     if (i >= n_nnp) return;
     T a[kCoupleVals];
     load_atom(x_nnp, par_nnp, i, a);
-    T f0 = 0, f1 = 0, f2 = 0;
-    for (int t = 0; t < nj; ++t) {
+    T f[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    int t = 0;
+    for (; t < nj; ++t) {
+        const int u = t & 1;
         const T d0 = s[t] - a[0], d1 = s[chunk + t] - a[1], d2 = s[2 * chunk + t] - a[2];
         const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
         if (rc2 > T(0) && r2 >= rc2) continue;
         T v, dvr;
         couple_pair(k, r2, a[3] * s[3 * chunk + t], a[4] + s[4 * chunk + t], a[5] * s[5 * chunk + t], v, dvr);
         // F_i = -dV/dx_i = +(dV/dr)(d/r)
-        f0 += dvr * d0;
-        f1 += dvr * d1;
-        f2 += dvr * d2;
+        f[u][0] += dvr * d0;
+        f[u][1] += dvr * d1;
+        f[u][2] += dvr * d2;
     }
-    T* P = f_part + ((size_t)c * n_nnp + i) * 3;
-    P[0] = f0;
-    P[1] = f1;
-    P[2] = f2;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) f_part[(size_t)(3 * i + q) * n_chunks + c] = f[0][q] + f[1][q];
 }
 
+// both sides in one launch: blocks [0, n_eblk) take the MM side, the rest
+// the NNP side (n_groups x n_cg blocks of four chunks)
+template <typename T>
+__global__ __launch_bounds__(kMmBlock) void k_couple_pairs(int n_eblk, int n_cg, int n_chunks, int n_nnp,
+                                                           const T* __restrict__ x_nnp,
+                                                           const T* __restrict__ par_nnp, int n_mm,
+                                                           const T* __restrict__ x_mm,
+                                                           const T* __restrict__ par_mm, T k, T rc2,
+                                                           int chunk, T* __restrict__ F_mm, int accumulate,
+                                                           double* __restrict__ e_part,
+                                                           T* __restrict__ f_part) {
+    extern __shared__ __align__(16) char smem[];
+    __shared__ double red[kMmBlock / 64];
+    if ((int)blockIdx.x < n_eblk)
+        couple_mm_side(blockIdx.x, n_nnp, x_nnp, par_nnp, n_mm, x_mm, par_mm, k, rc2, F_mm, accumulate,
+                       e_part, (T*)smem, red);
+    else
+        couple_nnp_side(blockIdx.x - n_eblk, n_cg, n_chunks, n_nnp, x_nnp, par_nnp, n_mm, x_mm, par_mm, k,
+                        rc2, chunk, f_part, (T*)smem);
+}
+
+// One workgroup per NNP force component (and one for the energy): the
+// threads stride over the partials, then a fixed-shape tree combines them,
+// so the sum is the same on every run.
 template <typename T>
 __global__ __launch_bounds__(256) void k_couple_sum(int n_nnp, int n_chunks, const T* __restrict__ f_part,
                                                     int n_eblk, const double* __restrict__ e_part,
                                                     T* __restrict__ F_nnp, double* __restrict__ E,
                                                     int accumulate) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < 3 * n_nnp) {
-        double f = 0.0;
-        for (int c = 0; c < n_chunks; ++c) f += (double)f_part[(size_t)c * n_nnp * 3 + t];
-        F_nnp[t] = accumulate ? F_nnp[t] + (T)f : (T)f;
-    }
-    if (blockIdx.x == 0 && threadIdx.x < 64) {
-        double e = 0.0;
-        for (int b = threadIdx.x; b < n_eblk; b += 64) e += e_part[b];
-        for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
-        if (threadIdx.x == 0) *E = accumulate ? *E + e : e;
+    __shared__ double red[4];
+    const int t = blockIdx.x;                 // component (t < 3 n_nnp) or the energy
+    const bool energy = t == 3 * n_nnp;
+    const int n = energy ? n_eblk : n_chunks;
+    double v = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x)
+        v += energy ? e_part[c] : (double)f_part[(size_t)t * n_chunks + c];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        v = (red[0] + red[1]) + (red[2] + red[3]);
+        if (energy) *E = accumulate ? *E + v : v;
+        else F_nnp[t] = accumulate ? F_nnp[t] + (T)v : (T)v;
     }
 }
 
@@ -172,16 +214,15 @@ hipError_t launch_coupling(const CouplingShape& cs, int n_nnp, const T* x_nnp, c
     const int n_eblk = n_mm > 0 ? (n_mm + kMmBlock - 1) / kMmBlock : 0;
     const int n_chunks = n_mm > 0 ? (n_mm + cs.chunk - 1) / cs.chunk : 0;
     if (n_eblk > 0) {
-        hipLaunchKernelGGL(k_couple_mm<T>, dim3(n_eblk), dim3(kMmBlock),
-                           sizeof(T) * kCoupleVals * (size_t)max(n_nnp, 1), st, n_nnp, x_nnp, par_nnp,
-                           n_mm, x_mm, par_mm, k, rc2, F_mm, accumulate ? 1 : 0, e_part);
-        if (n_nnp > 0)
-            hipLaunchKernelGGL(k_couple_nnp<T>, dim3((n_nnp + 63) / 64, n_chunks), dim3(64),
-                               sizeof(T) * kCoupleVals * (size_t)cs.chunk, st, n_nnp, x_nnp, par_nnp,
-                               n_mm, x_mm, par_mm, k, rc2, cs.chunk, f_part);
+        const int n_groups = n_nnp > 0 ? (n_nnp + 63) / 64 : 0, n_cg = (n_chunks + 3) / 4;
+        const size_t lds = sizeof(T) * kCoupleVals * std::max((size_t)std::max(n_nnp, 1), (size_t)4 * cs.chunk);
+        hipError_t e = ensure_lds((const void*)k_couple_pairs<T>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_couple_pairs<T>, dim3(n_eblk + n_groups * n_cg), dim3(kMmBlock), lds, st,
+                           n_eblk, n_cg, n_chunks, n_nnp, x_nnp, par_nnp, n_mm, x_mm, par_mm, k, rc2,
+                           cs.chunk, F_mm, accumulate ? 1 : 0, e_part, f_part);
     }
-    const int nt = std::max(3 * n_nnp, 1);
-    hipLaunchKernelGGL(k_couple_sum<T>, dim3((nt + 255) / 256), dim3(256), 0, st, n_nnp,
+    hipLaunchKernelGGL(k_couple_sum<T>, dim3(3 * n_nnp + 1), dim3(256), 0, st, n_nnp,
                        n_nnp > 0 ? n_chunks : 0, f_part, n_eblk, e_part, F_nnp, E, accumulate ? 1 : 0);
     return hipGetLastError();
 }

@@ -1026,7 +1026,7 @@ nnp_status nnp_coupling_create(int32_t precision, int32_t max_nnp, int32_t max_m
     if (precision != NNP_PREC_FP64 && precision != NNP_PREC_FP32)
         return fail(NNP_E_INVALID, "coupling precision must be FP64 or FP32");
     if (max_nnp < 1 || max_nnp > 1024) return fail(NNP_E_INVALID, "max_nnp must be in 1..1024");
-    if (max_mm < 1 || max_mm > (1 << 26)) return fail(NNP_E_INVALID, "max_mm must be in 1..2^26");
+    if (max_mm < 1 || max_mm > (1 << 22)) return fail(NNP_E_INVALID, "max_mm must be in 1..2^22");
     if (!std::isfinite(coulomb_k) || !(cutoff >= 0.0) || !std::isfinite(cutoff))
         return fail(NNP_E_INVALID, "coulomb_k must be finite and cutoff >= 0");
     int ndev = 0;
@@ -1041,9 +1041,9 @@ nnp_status nnp_coupling_create(int32_t precision, int32_t max_nnp, int32_t max_m
     c->cs.cutoff = cutoff;
     c->cs.max_nnp = max_nnp;
     c->cs.max_mm = max_mm;
-    // MM atoms per NNP-side workgroup: 64, widened so that at most 1024
-    // chunks (and partial force rows) exist at capacity
-    c->cs.chunk = 64 * std::max(1, (max_mm + 64 * 1024 - 1) / (64 * 1024));
+    // MM atoms per NNP-side wave: 64, widened (up to 512, the LDS limit of
+    // four FP64 chunks) so that at most 1024 chunks exist where possible
+    c->cs.chunk = 64 * std::min(8, std::max(1, (max_mm + 64 * 1024 - 1) / (64 * 1024)));
     const size_t tsz = precision == NNP_PREC_FP64 ? sizeof(double) : sizeof(float);
     const size_t n_eblk = (size_t)(max_mm + 255) / 256;
     const size_t n_chunks = (size_t)(max_mm + c->cs.chunk - 1) / c->cs.chunk;
