@@ -219,6 +219,9 @@ int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t
  *   NNP_KNOB_CELL_MIN     molecules with more atoms than this build their
  *                         neighbour lists through cutoff cells, smaller ones
  *                         scan all atoms: 16..1024 (auto 128).
+ *   NNP_KNOB_GEMM_WAVES   waves per workgroup of the layer-1 GEMMs on
+ *                         handles with 128-row buckets: 4 (2 x 2 waves of
+ *                         64 x 64) or 8 (2 x 4 waves of 64 x 32) (auto 4).
  *   NNP_KNOB_TAIL_TILE    row tile of the fused layers 2-3 kernel (handles
  *                         with 128-row buckets): 1 = 128 / (operand bytes)
  *                         rows on 4 waves, 2 = half that (at least 16) on 4
@@ -233,7 +236,8 @@ enum {
     NNP_KNOB_GEMM_STAGES = 1,
     NNP_KNOB_CELL_MIN = 2,
     NNP_KNOB_TAIL_TILE = 3,
-    NNP_N_KNOBS = 4
+    NNP_KNOB_GEMM_WAVES = 4,
+    NNP_N_KNOBS = 5
 };
 nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value);
 nnp_status nnp_get_knob(nnp_handle* h, int32_t knob, int32_t* value);

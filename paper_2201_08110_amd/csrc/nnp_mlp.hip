@@ -198,7 +198,7 @@ template <int N> __device__ inline void vm_wait_barrier() {
 // lane ends up owning four columns of one output row and the epilogue reads
 // and writes 8- or 16-byte vectors.
 template <typename P, int BM, int BN, int WM, int WN, int S, int EPI>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs<P> g) {
     typedef typename P::TS TS;
     typedef typename P::TA TA;
     typedef MF<TS> mf;
@@ -206,11 +206,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
     typedef Slice<TS> L;
     constexpr int BK = L::BK;
     constexpr int WTM = BM / WM, WTN = BN / WN, FM = WTM / 16, FN = WTN / 16;
-    static_assert(WM * WN == 4 && FM >= 1 && FN >= 1, "tile");
+    constexpr int NW = WM * WN;                            // waves per workgroup
+    static_assert((NW == 4 || NW == 8) && FM >= 1 && FN >= 1, "tile");
     static_assert(S >= 2 && BM % 8 == 0 && BN % 8 == 0, "stages / rows");
     constexpr int NQA = BM / 8, NQB = BN / 8;              // 8-row (1 KiB) loads per slice
-    constexpr int QA = (NQA + 3) / 4, QB = (NQB + 3) / 4;  // per wave (at most)
-    constexpr int QMIN = NQA / 4 + NQB / 4;                // per wave (at least)
+    constexpr int QA = (NQA + NW - 1) / NW, QB = (NQB + NW - 1) / NW;   // per wave (at most)
+    constexpr int QMIN = NQA / NW + NQB / NW;                            // per wave (at least)
     constexpr int ST = mf::kColStride;
     extern __shared__ __align__(16) char smem_raw[];
     TS* const stage0 = (TS*)smem_raw;                      // stage s: A rows then B rows
@@ -248,15 +249,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
         const int k0 = src * BK + ld_chunk * L::VE;
 #pragma unroll
         for (int u = 0; u < QA; ++u) {
-            const int q = wave + 4 * u;
-            if (NQA % 4 == 0 || q < NQA)
+            const int q = wave + NW * u;
+            if (NQA % NW == 0 || q < NQA)
                 __builtin_amdgcn_global_load_lds(NNP_GPTR(A + (size_t)(q * 8 + ld_row) * g.lda + k0),
                                                  NNP_LPTR(st_ + q * 8 * BK), 16, 0, 0);
         }
 #pragma unroll
         for (int u = 0; u < QB; ++u) {
-            const int q = wave + 4 * u;
-            if (NQB % 4 == 0 || q < NQB)
+            const int q = wave + NW * u;
+            if (NQB % NW == 0 || q < NQB)
                 __builtin_amdgcn_global_load_lds(NNP_GPTR(B + (size_t)(q * 8 + ld_row) * g.ldb + k0),
                                                  NNP_LPTR(st_ + (BM + q * 8) * BK), 16, 0, 0);
         }
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<P> g) {
             if (lane < 16) red[(wm * WTM + i * 16 + lane) * WN + wn] = v;
         }
         __syncthreads();
-        for (int rr = tid; rr < BM; rr += 256) {
+        for (int rr = tid; rr < BM; rr += 64 * NW) {
             TA v = 0;
 #pragma unroll
             for (int q = 0; q < WN; ++q) v += red[rr * WN + q];
@@ -490,7 +491,7 @@ static hipError_t run_gemm(GemmArgs<P> a, int Rcap, int N, int nz, hipStream_t s
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b(name, st);
-    hipLaunchKernelGGL(kern, dim3(T), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(kern, dim3(T), dim3(64 * WM * WN), lds, st, a);
     tm.e(name, st);
     return hipGetLastError();
 }
@@ -837,6 +838,22 @@ bool mlp_fused_supported(int H1, int H2, int H3) {
 // tail row tile per precision: equal LDS bytes (H1 tile of 32 KiB)
 template <typename P> struct TailBM { static constexpr int v = 128 / (int)sizeof(typename P::TS); };
 
+// the wide layer-1 GEMMs: LDS stages and waves per workgroup from the knobs
+// (8 waves split the 128 x 128 tile 2 x 4, for 128-row buckets only)
+template <typename P, int BM, int EPI>
+static hipError_t run_l1(GemmArgs<P> a, const Shape& sh, int N, hipStream_t st, const Timer& tm,
+                         const char* name) {
+    typedef Cfg<P, BM> C;
+    const int R = sh.Rcap;
+    if constexpr (BM == 128 && C::BNW == 128) {
+        if (sh.gemm_waves == 8)
+            return sh.gemm_stages == 2 ? run_gemm<P, BM, C::BNW, 2, 4, 2, EPI>(a, R, N, 1, st, tm, name)
+                                       : run_gemm<P, BM, C::BNW, 2, 4, 3, EPI>(a, R, N, 1, st, tm, name);
+    }
+    return sh.gemm_stages == 2 ? run_gemm<P, BM, C::BNW, C::WM, C::WN, 2, EPI>(a, R, N, 1, st, tm, name)
+                               : run_gemm<P, BM, C::BNW, C::WM, C::WN, 3, EPI>(a, R, N, 1, st, tm, name);
+}
+
 // L1b: dG = DZ1cat W1cat (models summed along K)
 template <typename P, int BM>
 static hipError_t mlp_l1_bwd(const Shape& sh, const DevWeights<P>& wt, Work<P>& w,
@@ -848,10 +865,7 @@ static hipError_t mlp_l1_bwd(const Shape& sh, const DevWeights<P>& wt, Work<P>& 
     a.B = wt.W1T; a.ldb = M * H1; a.b_s = (long)Dp * M * H1; a.b_z = 0;
     a.C = w.dG; a.ldc = Dp; a.c_z = 0;
     a.K = M * H1;
-    if (Dp % C::BNW == 0)
-        return sh.gemm_stages == 2
-                   ? run_gemm<P, BM, C::BNW, C::WM, C::WN, 2, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd")
-                   : run_gemm<P, BM, C::BNW, C::WM, C::WN, 3, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
+    if (Dp % C::BNW == 0) return run_l1<P, BM, EPI_ACC>(a, sh, Dp, st, tm, "mlp_l1_bwd");
     return run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
 }
 
@@ -881,9 +895,7 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     a.C = w.H1; a.ldc = M * H1; a.c_z = 0;
     a.K = Dp;
     if ((M * H1) % C::BNW == 0)
-        e = sh.gemm_stages == 2
-                ? run_gemm<P, BM, C::BNW, C::WM, C::WN, 2, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd")
-                : run_gemm<P, BM, C::BNW, C::WM, C::WN, 3, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd");
+        e = run_l1<P, BM, EPI_CELU>(a, sh, M * H1, st, tm, "mlp_l1_fwd");
     else
         e = run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd");
     if (e) return e;

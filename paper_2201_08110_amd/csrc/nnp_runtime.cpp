@@ -108,7 +108,7 @@ struct nnp_handle {
     std::vector<GraphEntry> graphs;
 
     // tunable knobs as set by the caller (0 = automatic)
-    int32_t knob[NNP_N_KNOBS] = {0, 0, 0, 0};
+    int32_t knob[NNP_N_KNOBS] = {0, 0, 0, 0, 0};
 
     // timing
     bool timing = false;
@@ -356,6 +356,7 @@ int32_t knob_value(const nnp_handle* h, int k) {
     case NNP_KNOB_GEMM_STAGES: return v ? v : 2;
     case NNP_KNOB_CELL_MIN: return v ? v : 128;
     case NNP_KNOB_TAIL_TILE: return v ? v : 1;
+    case NNP_KNOB_GEMM_WAVES: return v ? v : 4;
     }
     return 0;
 }
@@ -366,6 +367,7 @@ void apply_knobs(nnp_handle* h) {
     h->shape.gemm_stages = knob_value(h, NNP_KNOB_GEMM_STAGES);
     h->shape.cell_min = knob_value(h, NNP_KNOB_CELL_MIN);
     h->shape.tail_tile = knob_value(h, NNP_KNOB_TAIL_TILE);
+    h->shape.gemm_waves = knob_value(h, NNP_KNOB_GEMM_WAVES);
     for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     h->graphs.clear();
 }
@@ -525,7 +527,8 @@ const char* prec_name(int p) { return p == NNP_PREC_FP64 ? "fp64" : p == NNP_PRE
 const char* knob_name(int k) {
     return k == NNP_KNOB_MLP_PATH ? "mlp_path"
          : k == NNP_KNOB_GEMM_STAGES ? "gemm_stages"
-         : k == NNP_KNOB_CELL_MIN ? "cell_min" : "tail_tile";
+         : k == NNP_KNOB_CELL_MIN ? "cell_min"
+         : k == NNP_KNOB_TAIL_TILE ? "tail_tile" : "gemm_waves";
 }
 
 std::string tune_key(const nnp_handle* h) {
@@ -613,6 +616,8 @@ nnp_status autotune(nnp_handle* h, const nnp_batch* b, const typename P::T* x, i
             cand = {2, 3};
         } else if (k == NNP_KNOB_TAIL_TILE) {
             if (knob_value(h, NNP_KNOB_MLP_PATH) == 1 && h->shape.row_tile == 128) cand = {1, 2, 3};
+        } else if (k == NNP_KNOB_GEMM_WAVES) {
+            if (h->shape.row_tile == 128 && h->precision != NNP_PREC_FP64) cand = {4, 8};
         } else {
             for (int c : {32, 64, 128, 256})
                 if (c < h->max_apm) cand.push_back(c);
@@ -942,6 +947,8 @@ nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value) {
         ok = ok || value == 2 || value == 3;
     } else if (knob == NNP_KNOB_TAIL_TILE) {
         ok = ok || (value >= 1 && value <= 3);
+    } else if (knob == NNP_KNOB_GEMM_WAVES) {
+        ok = ok || value == 4 || value == 8;
     } else {
         ok = ok || (value >= 16 && value <= kMaxAtomsPerMol);
     }
@@ -986,10 +993,11 @@ nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, i
             rc = autotune<PrecBF16>(h, b, (const float*)coords, reps, timings);
         if (rc) return rc;
     }
-    char vals[200];
+    char vals[240];
     std::snprintf(vals, sizeof(vals),
-                  "\"mlp_path\": %d, \"gemm_stages\": %d, \"cell_min\": %d, \"tail_tile\": %d",
-                  knob_value(h, 0), knob_value(h, 1), knob_value(h, 2), knob_value(h, 3));
+                  "\"mlp_path\": %d, \"gemm_stages\": %d, \"cell_min\": %d, \"tail_tile\": %d, "
+                  "\"gemm_waves\": %d",
+                  knob_value(h, 0), knob_value(h, 1), knob_value(h, 2), knob_value(h, 3), knob_value(h, 4));
     if (!hit && cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(NNP_E_INVALID, std::string("cannot append to tune cache ") + cache_path);

@@ -99,7 +99,8 @@ def test_knob_ids_match_header():
     hdr = open(os.path.join(ROOT, "include", "nnp.h")).read()
     ids = dict((k, int(v)) for k, v in re.findall(r"\bNNP_KNOB_([A-Z_]+)\s*=\s*(\d+)", hdr))
     assert ids == {"MLP_PATH": nnp.KNOB_MLP_PATH, "GEMM_STAGES": nnp.KNOB_GEMM_STAGES,
-                   "CELL_MIN": nnp.KNOB_CELL_MIN, "TAIL_TILE": nnp.KNOB_TAIL_TILE}
+                   "CELL_MIN": nnp.KNOB_CELL_MIN, "TAIL_TILE": nnp.KNOB_TAIL_TILE,
+                   "GEMM_WAVES": nnp.KNOB_GEMM_WAVES}
     assert set(nnp.KNOBS.values()) == set(ids.values())
 
 

@@ -19,6 +19,7 @@ SIZES = [70, 1, 33, 150]
 VARIANTS = [dict(mlp_path=m, gemm_stages=g, cell_min=c, tail_tile=1)
             for m, g, c in itertools.product([1, 2], [2, 3], [32, 1024])]
 VARIANTS += [dict(mlp_path=1, gemm_stages=2, cell_min=128, tail_tile=t) for t in (2, 3)]
+VARIANTS += [dict(mlp_path=1, gemm_stages=g, cell_min=128, tail_tile=1, gemm_waves=8) for g in (2, 3)]
 
 
 def _batch():
