@@ -80,6 +80,27 @@ __host__ __device__ inline void decode_pair(int p, int n, int& j, int& k) {
     k = p - (jj * (2 * n - jj - 1)) / 2 + jj + 1;
 }
 
+// The same pairs in rotation order: pair p = (a, a + d mod n), diagonal d
+// taking n pairs each for d < n/2 (and n/2 pairs at d = n/2 when n is even).
+// Consecutive p give distinct j and distinct k, so lanes that scatter into
+// per-atom accumulators hit different addresses.
+__device__ inline void decode_pair_rot(int p, int n, int& j, int& k) {
+    const int full = n * ((n - 1) >> 1);
+    int d, a;
+    if (p < full) {
+        d = (int)(((float)p + 0.5f) * __builtin_amdgcn_rcpf((float)n));
+        a = p - d * n;
+        if (a < 0) { --d; a += n; }
+        if (a >= n) { ++d; a -= n; }
+        d += 1;
+    } else {
+        d = n >> 1;
+        a = p - full;
+    }
+    j = a;
+    k = a + d >= n ? a + d - n : a + d;
+}
+
 // ==========================================================================
 // Element bucketing (three kernels): per-block element counts and molecule
 // checks; one small scan of the block counts into padded bucket starts; a
@@ -1170,11 +1191,11 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
                 fi2 += dEdr * u2;
             }
         }
-        // angular: lane per neighbour pair
+        // angular: lane per neighbour pair, pairs in rotation order
         const int npair = nang * (nang - 1) / 2;
         for (int p = lane; p < npair; p += 64) {
             int j, k;
-            decode_pair(p, nang, j, k);
+            decode_pair_rot(p, nang, j, k);
             const T* ej = nb + kNbStride * j;
             const T* ek = nb + kNbStride * k;
             const T rj = ej[3], rk = ek[3];
