@@ -91,6 +91,15 @@ typedef struct nnp_handle nnp_handle;
  * weights (host, FP64): [model][element][layer] { W (out x in, row-major), b (out) }.
  * This build supports n_shf_r = 16, n_shf_a * n_shf_z = 32, n_layers = 4 with
  * hidden widths that are multiples of 32 (E_UNSUPPORTED otherwise).
+ *
+ * Element networks of their own sizes (the ANI-2x element networks differ):
+ * species_widths [S][n_layers+1] gives element s's widths (first D, last 1,
+ * hidden 1..4096, any value); `widths` is then ignored.  The packed weights and
+ * parameter gradients follow those widths, so the (model, element) blocks have
+ * different lengths.  Internally every element network is zero-padded to the
+ * widest one (rounded up to a multiple of 32): zero weights and biases give
+ * z = 0, CELU(0) = 0 and no contribution downstream, so the padding changes no
+ * result.
  */
 typedef struct {
     int32_t n_species;            /* S, 1..NNP_MAX_SPECIES                                */
@@ -106,6 +115,7 @@ typedef struct {
     int32_t n_models;             /* M >= 1 */
     int32_t n_layers;             /* affine layers per network (4) */
     const int32_t* widths;        /* host [n_layers+1]; widths[0] = D, widths[n_layers] = 1 */
+    const int32_t* species_widths;/* host [S][n_layers+1] per-element widths, or NULL        */
     double celu_alpha;
     const double* weights;        /* host, FP64, packed as above */
     const double* sae;            /* host [S] or NULL (zeros) */

@@ -40,7 +40,7 @@ class _AEV(C.Structure):
 class _Net(C.Structure):
     _fields_ = [("n_models", C.c_int32), ("n_species", C.c_int32), ("n_layers", C.c_int32),
                 ("widths", C.POINTER(C.c_int32)), ("celu_alpha", C.c_double),
-                ("weights", C.POINTER(C.c_double))]
+                ("weights", C.POINTER(C.c_double)), ("species_widths", C.POINTER(C.c_int32))]
 
 
 _lib = None
@@ -108,15 +108,26 @@ def _aev_struct(hp: dict) -> _Keep:
     return _Keep(s, sr, sa, sz)
 
 
+def species_widths(hp: dict) -> list:
+    """Layer widths of every element's networks: hp["species_widths"] (one
+    list per element) when given, else hp["widths"] for all."""
+    sw = hp.get("species_widths")
+    return [list(x) for x in sw] if sw is not None else [list(hp["widths"])] * hp["n_species"]
+
+
 def _net_struct(hp: dict, weights: np.ndarray, n_models: int) -> _Keep:
     w = np.ascontiguousarray(weights, dtype=np.float64)
     wd = np.ascontiguousarray(hp["widths"], dtype=np.int32)
-    s = _Net(n_models, hp["n_species"], len(wd) - 1, _ip(wd), hp["celu_alpha"], _dp(w))
-    expect = n_models * hp["n_species"] * sum(int(wd[l + 1]) * int(wd[l]) + int(wd[l + 1])
-                                              for l in range(len(wd) - 1))
+    per = species_widths(hp)
+    if len(per) != hp["n_species"] or any(len(x) != len(wd) for x in per):
+        raise ValueError("species_widths needs one list of len(widths) per element")
+    swd = np.ascontiguousarray(per, dtype=np.int32).reshape(-1)
+    s = _Net(n_models, hp["n_species"], len(wd) - 1, _ip(wd), hp["celu_alpha"], _dp(w),
+             _ip(swd) if hp.get("species_widths") is not None else None)
+    expect = n_models * sum(sum(x[l + 1] * x[l] + x[l + 1] for l in range(len(x) - 1)) for x in per)
     if w.size != expect:
         raise ValueError(f"weights have {w.size} values, expected {expect}")
-    return _Keep(s, w, wd)
+    return _Keep(s, w, wd, swd)
 
 
 def _mol(species, coords):

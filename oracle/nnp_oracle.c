@@ -39,7 +39,9 @@
  *   energy    E_mol = u * ( (1/M) sum_m sum_i e_{m,i} + sum_i SAE[s_i] )
  *
  * Weights are one flat FP64 array, ordered [model][element][layer] and, per
- * layer, W (out x in, row-major) followed by b (out).
+ * layer, W (out x in, row-major) followed by b (out).  Every element may have
+ * networks of its own widths (the ANI-2x element networks differ in size);
+ * then the (model, element) blocks have different lengths.
  */
 #include <math.h>
 #include <stdint.h>
@@ -69,6 +71,7 @@ typedef struct {
     const int32_t* widths;    /* [L+1]; widths[0] = AEV dimension, widths[L] = 1 */
     double celu_alpha;
     const double* weights;    /* packed, see the file header */
+    const int32_t* species_widths;   /* [S][L+1] per-element widths, or NULL (all `widths`) */
 } orc_net_t;
 
 /* ------------------------------------------------------------------------ */
@@ -80,22 +83,46 @@ int32_t orc_aev_dim(const orc_aev_t* p)
     return S * p->n_shf_r + (S * (S + 1) / 2) * p->n_shf_a * p->n_shf_z;
 }
 
+/* the layer widths of element s's networks */
+static const int32_t* widths_of(const orc_net_t* n, int s)
+{
+    return n->species_widths ? n->species_widths + (int64_t)s * (n->n_layers + 1) : n->widths;
+}
+
+/* parameters of one network of element s */
+static int64_t net_size_of(const orc_net_t* n, int s)
+{
+    const int32_t* w = widths_of(n, s);
+    int64_t sz = 0;
+    for (int l = 0; l < n->n_layers; ++l)
+        sz += (int64_t)w[l + 1] * w[l] + w[l + 1];
+    return sz;
+}
+
+/* parameters of one model (all its element networks) */
 int64_t orc_net_size(const orc_net_t* n)
 {
     int64_t sz = 0;
-    for (int l = 0; l < n->n_layers; ++l)
-        sz += (int64_t)n->widths[l + 1] * n->widths[l] + n->widths[l + 1];
+    for (int s = 0; s < n->n_species; ++s) sz += net_size_of(n, s);
     return sz;
 }
 
 int64_t orc_weights_size(const orc_net_t* n)
 {
-    return (int64_t)n->n_models * n->n_species * orc_net_size(n);
+    return (int64_t)n->n_models * orc_net_size(n);
+}
+
+/* offset of network (m, s) in the packed array */
+static int64_t net_offset(const orc_net_t* n, int m, int s)
+{
+    int64_t off = (int64_t)m * orc_net_size(n);
+    for (int t = 0; t < s; ++t) off += net_size_of(n, t);
+    return off;
 }
 
 static const double* net_ptr(const orc_net_t* n, int m, int s)
 {
-    return n->weights + ((int64_t)m * n->n_species + s) * orc_net_size(n);
+    return n->weights + net_offset(n, m, s);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -363,10 +390,11 @@ static double celu(double z, double al) { return z >= 0.0 ? z : al * (exp(z / al
 static double celu_d1(double z, double al) { return z >= 0.0 ? 1.0 : exp(z / al); }
 static double celu_d2(double z, double al) { return z >= 0.0 ? 0.0 : exp(z / al) / al; }
 
-static int max_width(const orc_net_t* n)
+static int max_width(const orc_net_t* n, int s)
 {
+    const int32_t* wd = widths_of(n, s);
     int w = 0;
-    for (int l = 0; l <= n->n_layers; ++l) if (n->widths[l] > w) w = n->widths[l];
+    for (int l = 0; l <= n->n_layers; ++l) if (wd[l] > w) w = wd[l];
     return w;
 }
 
@@ -376,16 +404,17 @@ static int max_width(const orc_net_t* n)
  */
 double orc_atomic_nn(const orc_net_t* n, int32_t m, int32_t s, const double* G, double* dG)
 {
-    const int L = n->n_layers, W = max_width(n);
+    const int L = n->n_layers, W = max_width(n, s);
+    const int32_t* wd = widths_of(n, s);
     const double al = n->celu_alpha;
     double* z = (double*)calloc((size_t)L * W, sizeof(double));  /* pre-activations */
     double* a = (double*)calloc((size_t)(L + 1) * W, sizeof(double));
-    memcpy(a, G, sizeof(double) * n->widths[0]);
+    memcpy(a, G, sizeof(double) * wd[0]);
     const double* wp = net_ptr(n, m, s);
     const double* Wl[64];
     const double* bl[64];
     for (int l = 0; l < L; ++l) {
-        int nin = n->widths[l], nout = n->widths[l + 1];
+        int nin = wd[l], nout = wd[l + 1];
         Wl[l] = wp; bl[l] = wp + (int64_t)nout * nin;
         wp += (int64_t)nout * nin + nout;
         for (int o = 0; o < nout; ++o) {
@@ -402,7 +431,7 @@ double orc_atomic_nn(const orc_net_t* n, int32_t m, int32_t s, const double* G, 
         double* gp = (double*)calloc((size_t)W, sizeof(double));
         g[0] = 1.0;
         for (int l = L - 1; l >= 0; --l) {
-            int nin = n->widths[l], nout = n->widths[l + 1];
+            int nin = wd[l], nout = wd[l + 1];
             /* g holds dE/dz_l (for l = L-1 the output is linear) */
             memset(gp, 0, sizeof(double) * W);
             for (int o = 0; o < nout; ++o)
@@ -426,20 +455,21 @@ double orc_atomic_nn(const orc_net_t* n, int32_t m, int32_t s, const double* G, 
 static void atomic_nn_param_grad(const orc_net_t* n, int32_t m, int32_t s, const double* G,
                                  const double* Gdot, double alpha, double beta, double* gw)
 {
-    const int L = n->n_layers, W = max_width(n);
+    const int L = n->n_layers, W = max_width(n, s);
+    const int32_t* wd = widths_of(n, s);
     const double al = n->celu_alpha;
     double* z = (double*)calloc((size_t)L * W, sizeof(double));
     double* zd = (double*)calloc((size_t)L * W, sizeof(double));
     double* a = (double*)calloc((size_t)(L + 1) * W, sizeof(double));
     double* ad = (double*)calloc((size_t)(L + 1) * W, sizeof(double));
-    memcpy(a, G, sizeof(double) * n->widths[0]);
-    memcpy(ad, Gdot, sizeof(double) * n->widths[0]);
+    memcpy(a, G, sizeof(double) * wd[0]);
+    memcpy(ad, Gdot, sizeof(double) * wd[0]);
     const double* wp = net_ptr(n, m, s);
     const double* Wl[64];
     int64_t off[64];
     int64_t o0 = 0;
     for (int l = 0; l < L; ++l) {
-        int nin = n->widths[l], nout = n->widths[l + 1];
+        int nin = wd[l], nout = wd[l + 1];
         Wl[l] = wp + o0; off[l] = o0;
         const double* b = Wl[l] + (int64_t)nout * nin;
         o0 += (int64_t)nout * nin + nout;
@@ -468,7 +498,7 @@ static void atomic_nn_param_grad(const orc_net_t* n, int32_t m, int32_t s, const
     zb[0] = alpha;
     zdb[0] = beta;
     for (int l = L - 1; l >= 0; --l) {
-        int nin = n->widths[l], nout = n->widths[l + 1];
+        int nin = wd[l], nout = wd[l + 1];
         double* gW = gw + off[l];
         double* gb = gW + (int64_t)nout * nin;
         for (int o = 0; o < nout; ++o) {
@@ -572,7 +602,6 @@ void orc_param_grad(const orc_aev_t* p, const orc_net_t* net, double energy_scal
     const int D = orc_aev_dim(p);
     const int32_t A = mol_off[n_mols];
     const int M = net->n_models, S = net->n_species;
-    const int64_t nsz = orc_net_size(net);
     double* G = (double*)malloc(sizeof(double) * (size_t)A * D + 8);
     double* Gd = (double*)malloc(sizeof(double) * (size_t)A * D + 8);
     int32_t* mol_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)A + 8);
@@ -587,12 +616,12 @@ void orc_param_grad(const orc_aev_t* p, const orc_net_t* net, double energy_scal
                     Gd + (size_t)a0 * D);
     }
 
-    memset(gw, 0, sizeof(double) * (size_t)M * S * nsz);
+    memset(gw, 0, sizeof(double) * (size_t)orc_weights_size(net));
     /* one (model, element) network per task, atoms in order: deterministic */
 #pragma omp parallel for collapse(2) schedule(dynamic, 1)
     for (int m = 0; m < M; ++m)
         for (int s = 0; s < S; ++s) {
-            double* g = gw + ((int64_t)m * S + s) * nsz;
+            double* g = gw + net_offset(net, m, s);
             for (int i = 0; i < A; ++i) {
                 if (species[i] != s) continue;
                 double alpha = energy_scale / M * gE[mol_of[i]];

@@ -1318,7 +1318,7 @@ __global__ __launch_bounds__(256) void k_energy(int A, int B, int M, int NT, dou
                                                 const int32_t* __restrict__ row_of_atom,
                                                 const typename P::TA* __restrict__ Epart,
                                                 const typename P::TA* __restrict__ b4,
-                                                const typename P::TA* __restrict__ sae,
+                                                const double* __restrict__ sae,
                                                 double* __restrict__ E) {
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = lane_id();
@@ -1336,7 +1336,7 @@ __global__ __launch_bounds__(256) void k_energy(int A, int B, int M, int NT, dou
             for (int t = 0; t < NT; ++t) em += (double)Epart[(row * M + m) * NT + t];
             e += em;
         }
-        acc += scale * (e / M) + (double)sae[s];
+        acc += scale * (e / M) + sae[s];
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) E[b] = (a1 > a0) ? acc : 0.0;

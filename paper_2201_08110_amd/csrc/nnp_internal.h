@@ -174,7 +174,7 @@ template <typename P> struct DevWeights {
     // the fused layers 2-3 kernel's operands in fragment order (per element
     // and model: W2 [H2][H1], W3 [H3][H2], W3^T [H2][H3], W2^T [H1][H2])
     TS* W2f;  TS* W3f;  TS* W3Tf;  TS* W2Tf;
-    TA* sae;                       // [S] (already multiplied by energy_scale)
+    double* sae;                   // [S] FP64 (already multiplied by energy_scale)
 };
 
 struct Shape {
@@ -276,6 +276,8 @@ hipError_t launch_train_grads(const Shape& sh, const NetLayout& nl, Work<P>& w, 
                               typename P::TA* grad_params, hipStream_t st, const Timer& tm);
 template <typename P>
 hipError_t launch_fill(typename P::TS* p, size_t n, hipStream_t st);
+template <typename TA>
+hipError_t launch_gather(int64_t n, const int32_t* map, const TA* src, TA* dst, hipStream_t st);
 template <typename P>
 hipError_t launch_grad_coords(int A, const int32_t* mol_of_atom, const double* grad_E,
                               const typename P::T* F, typename P::T* gx, hipStream_t st);

@@ -84,6 +84,14 @@ struct nnp_handle {
     AevConst<double> cd{};
     Shape shape{};
     int64_t n_params = 0;
+    // element networks of their own widths: packed index -> index in the
+    // zero-padded uniform layout (host and device copies); gradients are
+    // formed in that layout (gpad) and gathered
+    bool het = false;
+    int64_t n_int = 0;
+    std::vector<int32_t> pmap;
+    int32_t* dmap = nullptr;
+    void* gpad = nullptr;
 
     // device memory
     std::vector<void*> allocs;
@@ -196,6 +204,12 @@ template <typename P> nnp_status upload_weights(nnp_handle* h, DevWeights<P>& dw
                                                 const double* w, bool allocate) {
     typedef typename P::TS TS;
     typedef typename P::TA TA;
+    std::vector<double> padded;
+    if (h->het) {   // into the zero-padded uniform layout
+        padded.assign((size_t)h->n_int, 0.0);
+        for (size_t i = 0; i < h->pmap.size(); ++i) padded[h->pmap[i]] = w[i];
+        w = padded.data();
+    }
     const Shape& sh = h->shape;
     const int S = h->S, M = h->M, D = h->D, Dp = sh.Dp;
     const int o1 = h->widths[1], o2 = h->widths[2], o3 = h->widths[3];
@@ -204,7 +218,8 @@ template <typename P> nnp_status upload_weights(nnp_handle* h, DevWeights<P>& dw
     std::vector<TS> W2((size_t)S * M * H2 * H1, to_store<TS>(0.0)), W2T(W2.size(), to_store<TS>(0.0));
     std::vector<TS> W3((size_t)S * M * H3 * H2, to_store<TS>(0.0)), W3T(W3.size(), to_store<TS>(0.0));
     std::vector<TA> b1((size_t)S * M * H1, 0), b2((size_t)S * M * H2, 0), b3((size_t)S * M * H3, 0);
-    std::vector<TA> w4((size_t)S * M * H3, 0), b4((size_t)S * M, 0), sae(S, 0);
+    std::vector<TA> w4((size_t)S * M * H3, 0), b4((size_t)S * M, 0);
+    std::vector<double> sae(S, 0.0);   // summed in FP64: self-energies dwarf the network part
     const size_t net = (size_t)o1 * D + o1 + (size_t)o2 * o1 + o2 + (size_t)o3 * o2 + o3 + o3 + 1;
     for (int m = 0; m < M; ++m)
         for (int s = 0; s < S; ++s) {
@@ -241,7 +256,7 @@ template <typename P> nnp_status upload_weights(nnp_handle* h, DevWeights<P>& dw
             p += o3;
             b4[sm] = (TA)p[0];
         }
-    for (int s = 0; s < S; ++s) sae[s] = (TA)(h->energy_scale * (h->sae.empty() ? 0.0 : h->sae[s]));
+    for (int s = 0; s < S; ++s) sae[s] = h->energy_scale * (h->sae.empty() ? 0.0 : h->sae[s]);
     // fragment-order copies of the per-model matrices (the fused kernel's
     // weight operands), one [N][K] matrix per element and model
     auto fragments = [&](const std::vector<TS>& src, int N, int K) {
@@ -465,6 +480,10 @@ template <typename P> nnp_status alloc_train(nnp_handle* h) {
     TALLOC(ZDB3, sizeof(TS) * R * M * sh.H3);
     TALLOC(TMP, sizeof(TS) * R * M * std::max(sh.H1, sh.H2));
 #undef TALLOC
+    if (h->het) {
+        h->gpad = h->dalloc(sizeof(typename P::TA) * (size_t)h->n_int, e);
+        if (e != hipSuccess) return fail(NNP_E_NOMEM, "training workspace (padded gradients)");
+    }
     h->train_F = h->dalloc(sizeof(T) * 3 * (size_t)std::max(h->max_atoms, 1), e);
     if (e != hipSuccess) return fail(NNP_E_NOMEM, "training workspace (forces)");
     h->train_E = (double*)h->dalloc(sizeof(double) * (size_t)h->max_mols, e);
@@ -516,7 +535,13 @@ nnp_status run_backward(nnp_handle* h, const nnp_batch* b, const typename P::T* 
     HIP_TRY(launch_train_mlp<P>(sh, wt, w, tw, w.mol_of_atom, gE, has_gF, st, tm));
     HIP_TRY(launch_train_rev3<P>(sh, wt, w, tw, w.mol_of_atom, gE, has_gF, st, tm));
     HIP_TRY(launch_train_mlp_rev<P>(sh, wt, w, tw, st, tm));
-    HIP_TRY(launch_train_grads<P>(sh, h->nl, w, tw, w.mol_of_atom, gE, has_gF, gp, st, tm));
+    if (h->het) {
+        typedef typename P::TA TA;
+        HIP_TRY(launch_train_grads<P>(sh, h->nl, w, tw, w.mol_of_atom, gE, has_gF, (TA*)h->gpad, st, tm));
+        HIP_TRY(launch_gather<TA>(h->n_params, h->dmap, (const TA*)h->gpad, gp, st));
+    } else {
+        HIP_TRY(launch_train_grads<P>(sh, h->nl, w, tw, w.mol_of_atom, gE, has_gF, gp, st, tm));
+    }
     return NNP_OK;
 }
 
@@ -665,7 +690,7 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     if (!p) return fail(NNP_E_INVALID, "null params");
     if (p->n_species < 1 || p->n_species > NNP_MAX_SPECIES)
         return fail(NNP_E_INVALID, "n_species must be in 1..8");
-    if (!p->shf_r || !p->shf_a || !p->shf_z || !p->weights || !p->widths)
+    if (!p->shf_r || !p->shf_a || !p->shf_z || !p->weights || (!p->widths && !p->species_widths))
         return fail(NNP_E_INVALID, "null shift, width or weight array");
     if (p->n_shf_r != kNR || p->n_shf_a * p->n_shf_z != kNAZ || (p->n_shf_z != 4 && p->n_shf_z != 8))
         return fail(NNP_E_UNSUPPORTED, "this build supports 16 radial shifts and 8x4 or 4x8 angular shifts");
@@ -680,11 +705,25 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     if (p->n_layers != 4) return fail(NNP_E_UNSUPPORTED, "this build supports 4 affine layers");
     const int S = p->n_species;
     const int D = S * p->n_shf_r + (S * (S + 1) / 2) * p->n_shf_a * p->n_shf_z;
-    if (p->widths[0] != D) return fail(NNP_E_INVALID, "widths[0] must equal the AEV dimension");
-    if (p->widths[4] != 1) return fail(NNP_E_INVALID, "the last width must be 1");
+    // element network widths sw[s][l]; the uniform layout wi[l] every element
+    // network is padded to (the widest, rounded up to a multiple of 32)
+    std::vector<int> sw((size_t)S * 5), wi(5, 0);
+    for (int s = 0; s < S; ++s)
+        for (int l = 0; l < 5; ++l) sw[s * 5 + l] = p->species_widths ? p->species_widths[s * 5 + l] : p->widths[l];
+    for (int s = 0; s < S; ++s) {
+        const int* ws = &sw[s * 5];
+        if (ws[0] != D) return fail(NNP_E_INVALID, "widths[0] must equal the AEV dimension");
+        if (ws[4] != 1) return fail(NNP_E_INVALID, "the last width must be 1");
+        for (int l = 1; l < 4; ++l) {
+            if (ws[l] < 1 || ws[l] > 4096) return fail(NNP_E_UNSUPPORTED, "hidden widths must be in 1..4096");
+            if (!p->species_widths && ws[l] % 32)
+                return fail(NNP_E_UNSUPPORTED, "hidden widths must be multiples of 32 up to 4096");
+        }
+    }
+    wi[0] = D;
+    wi[4] = 1;
     for (int l = 1; l < 4; ++l)
-        if (p->widths[l] < 1 || p->widths[l] > 4096 || p->widths[l] % 32)
-            return fail(NNP_E_UNSUPPORTED, "hidden widths must be multiples of 32 up to 4096");
+        for (int s = 0; s < S; ++s) wi[l] = std::max(wi[l], pad_to(sw[s * 5 + l], 32));
     if (p->precision < NNP_PREC_FP64 || p->precision > NNP_PREC_BF16_MLP)
         return fail(NNP_E_INVALID, "unknown precision");
     if (p->max_atoms < 1 || p->max_mols < 1 || p->max_atoms_per_mol < 1)
@@ -705,7 +744,8 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     h->D = D;
     h->M = p->n_models;
     h->L = p->n_layers;
-    h->widths.assign(p->widths, p->widths + 5);
+    h->widths = wi;
+    h->het = p->species_widths != nullptr;
     h->precision = p->precision;
     h->device = p->device;
     h->max_atoms = p->max_atoms;
@@ -714,15 +754,41 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     h->energy_scale = p->energy_scale;
     h->celu_alpha = p->celu_alpha;
     if (p->sae) h->sae.assign(p->sae, p->sae + S);
-    int64_t net = 0;
-    for (int l = 0; l < 4; ++l) net += (int64_t)p->widths[l + 1] * p->widths[l] + p->widths[l + 1];
-    h->n_params = net * S * h->M;
+    auto net_of = [](const int* w) {
+        int64_t n = 0;
+        for (int l = 0; l < 4; ++l) n += (int64_t)w[l + 1] * w[l] + w[l + 1];
+        return n;
+    };
+    const int64_t net_int = net_of(wi.data());
+    h->n_int = net_int * S * h->M;
+    h->n_params = 0;
+    for (int s = 0; s < S; ++s) h->n_params += net_of(&sw[s * 5]) * h->M;
+    if (h->het) {
+        if (h->n_int >= ((int64_t)1 << 31)) {
+            delete h;
+            return fail(NNP_E_UNSUPPORTED, "padded parameter count above 2^31");
+        }
+        // packed index -> padded index, layer by layer: W row-major, then b
+        h->pmap.reserve((size_t)h->n_params);
+        for (int m = 0; m < h->M; ++m)
+            for (int s = 0; s < S; ++s) {
+                const int* ws = &sw[s * 5];
+                int64_t base = ((int64_t)m * S + s) * net_int;
+                for (int l = 0; l < 4; ++l) {
+                    for (int n = 0; n < ws[l + 1]; ++n)
+                        for (int k = 0; k < ws[l]; ++k) h->pmap.push_back((int32_t)(base + (int64_t)n * wi[l] + k));
+                    for (int n = 0; n < ws[l + 1]; ++n)
+                        h->pmap.push_back((int32_t)(base + (int64_t)wi[l + 1] * wi[l] + n));
+                    base += (int64_t)wi[l + 1] * wi[l] + wi[l + 1];
+                }
+            }
+    }
     {
         NetLayout& nl = h->nl;
         nl.D = D;
-        nl.o1 = p->widths[1];
-        nl.o2 = p->widths[2];
-        nl.o3 = p->widths[3];
+        nl.o1 = wi[1];
+        nl.o2 = wi[2];
+        nl.o3 = wi[3];
         nl.offW1 = 0;
         nl.offb1 = (long)nl.o1 * D;
         nl.offW2 = nl.offb1 + nl.o1;
@@ -739,9 +805,9 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     sh.M = h->M;
     sh.D = D;
     sh.Dp = pad_to(D, 64);
-    sh.H1 = pad_to(p->widths[1], 64);
-    sh.H2 = pad_to(p->widths[2], 64);
-    sh.H3 = pad_to(p->widths[3], 64);
+    sh.H1 = pad_to(wi[1], 64);
+    sh.H2 = pad_to(wi[2], 64);
+    sh.H3 = pad_to(wi[3], 64);
     sh.row_tile = (p->max_atoms <= 256 || p->precision == NNP_PREC_FP64) ? 16 : 128;
     sh.Rcap = pad_to(p->max_atoms + S * (sh.row_tile - 1), sh.row_tile);
     sh.cap_nbr = std::max(1, std::min(h->max_apm - 1, kMaxNeighbours));
@@ -762,6 +828,13 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     nnp_status rc = e == hipSuccess ? NNP_OK : fail(NNP_E_NOMEM, "flag allocation failed");
     if (rc == NNP_OK && hipMemset(h->flag, 0, sizeof(int32_t)) != hipSuccess)
         rc = fail(NNP_E_DEVICE, "hipMemset failed");
+    if (rc == NNP_OK && h->het) {
+        h->dmap = (int32_t*)h->dalloc(sizeof(int32_t) * h->pmap.size(), e);
+        if (e != hipSuccess)
+            rc = fail(NNP_E_NOMEM, "parameter map allocation failed");
+        else if (hipMemcpy(h->dmap, h->pmap.data(), sizeof(int32_t) * h->pmap.size(), hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(NNP_E_DEVICE, "parameter map upload failed");
+    }
     if (rc == NNP_OK) {
         if (p->precision == NNP_PREC_FP64) {
             rc = upload_weights<PrecF64>(h, h->w64, p->weights, true);

@@ -308,6 +308,24 @@ hipError_t launch_grad_coords(int A, const int32_t* mol_of_atom, const double* g
     return hipGetLastError();
 }
 
+// parameter gradients of element networks narrower than the padded layout:
+// dst[i] = src[map[i]] (the padded entries are dropped)
+template <typename TA>
+__global__ void k_gather(int64_t n, const int32_t* __restrict__ map, const TA* __restrict__ src,
+                         TA* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[map[i]];
+}
+
+template <typename TA>
+hipError_t launch_gather(int64_t n, const int32_t* map, const TA* src, TA* dst, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather<TA>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, map, src, dst);
+    return hipGetLastError();
+}
+template hipError_t launch_gather<float>(int64_t, const int32_t*, const float*, float*, hipStream_t);
+template hipError_t launch_gather<double>(int64_t, const int32_t*, const double*, double*, hipStream_t);
+
 #define NNP_TRAIN_INST(P)                                                                       \
     template hipError_t launch_train_rev3<P>(const Shape&, const DevWeights<P>&, Work<P>&,     \
                                              TrainWork<P>&, const int32_t*, const double*,     \

@@ -37,6 +37,7 @@ class ModelParams(C.Structure):
         ("shf_r", C.POINTER(C.c_double)), ("shf_a", C.POINTER(C.c_double)),
         ("shf_z", C.POINTER(C.c_double)),
         ("n_models", C.c_int32), ("n_layers", C.c_int32), ("widths", C.POINTER(C.c_int32)),
+        ("species_widths", C.POINTER(C.c_int32)),
         ("celu_alpha", C.c_double), ("weights", C.POINTER(C.c_double)),
         ("sae", C.POINTER(C.c_double)), ("energy_scale", C.c_double),
         ("precision", C.c_int32), ("max_atoms", C.c_int32), ("max_mols", C.c_int32),
@@ -153,6 +154,10 @@ class NNP:
         p.n_models = n_models
         p.n_layers = len(wd) - 1
         p.widths = wd.ctypes.data_as(C.POINTER(C.c_int32))
+        if hp.get("species_widths") is not None:
+            sw = np.ascontiguousarray(hp["species_widths"], dtype=np.int32).reshape(-1)
+            self._keep.append(sw)
+            p.species_widths = sw.ctypes.data_as(C.POINTER(C.c_int32))
         p.celu_alpha = hp["celu_alpha"]
         p.weights = darr(weights)
         p.sae = darr(sae) if sae is not None else None

@@ -66,6 +66,48 @@ def ani2x_hparams() -> dict:
     )
 
 
+def ani2x_element_widths(hp: dict) -> list:
+    """Per-element layer widths of the ANI-2x element networks (H, C, N, O,
+    F, S, Cl): larger networks for the more frequent elements."""
+    D = aev_dim(hp)
+    hidden = {0: (256, 192, 160), 1: (224, 192, 160), 2: (192, 160, 128), 3: (192, 160, 128),
+              4: (160, 128, 96), 5: (160, 128, 96), 6: (160, 128, 96)}
+    return [[D, *hidden[s], 1] for s in range(hp["n_species"])]
+
+
+def ani2x_heterogeneous_hparams() -> dict:
+    """ANI-2x featuriser with element networks of their own widths; `widths`
+    keeps the largest width of every layer."""
+    hp = ani2x_hparams()
+    hp["species_widths"] = ani2x_element_widths(hp)
+    hp["widths"] = [max(w[l] for w in hp["species_widths"]) for l in range(5)]
+    return hp
+
+
+def ani1x_hparams() -> dict:
+    """ANI-1x-shaped featuriser over H, C, N, O (384-dim AEV): 16 radial
+    shifts on 0.9..5.2 A, 4 angular-distance shifts on 0.9..3.5 A, 8 angle
+    shifts, eta_r 16, eta_a 8, zeta 32, and element networks
+    384-160-128-96-1 (H), 384-144-112-96-1 (C), 384-128-112-96-1 (N, O)."""
+    hp = dict(
+        n_species=4,
+        rcr=5.2, rca=3.5,
+        eta_r=16.0, eta_a=8.0, zeta=32.0,
+        shf_r=[0.9 + k * (5.2 - 0.9) / 16.0 for k in range(16)],
+        shf_a=[0.9 + a * (3.5 - 0.9) / 4.0 for a in range(4)],
+        shf_z=[(2 * z + 1) * math.pi / 16.0 for z in range(8)],
+        angle_scale=0.95,
+        radial_pref=0.25,
+        celu_alpha=0.1,
+        energy_scale=HARTREE_TO_KCALMOL,
+    )
+    D = aev_dim(hp)
+    hp["species_widths"] = [[D, 160, 128, 96, 1], [D, 144, 112, 96, 1], [D, 128, 112, 96, 1],
+                            [D, 128, 112, 96, 1]]
+    hp["widths"] = [max(w[l] for w in hp["species_widths"]) for l in range(5)]
+    return hp
+
+
 def aev_dim(hp: dict) -> int:
     s = hp["n_species"]
     return s * len(hp["shf_r"]) + (s * (s + 1) // 2) * len(hp["shf_a"]) * len(hp["shf_z"])
@@ -126,15 +168,20 @@ def xavier_weights(n_models: int, widths, n_species: int = 7, seed: int = W_SEED
 
     W ~ U(+-sqrt(6/(fan_in+fan_out))), b ~ U(+-1/sqrt(fan_in)); model m draws
     from SeedSequence(seed).spawn(m+1)[m] so that model m is the same for any
-    ensemble size.
+    ensemble size.  `widths` is one list of layer widths for every element, or
+    one list per element (networks of different sizes per element).
     """
+    per = [list(w) for w in widths] if isinstance(widths[0], (list, tuple)) else [list(widths)] * n_species
+    if len(per) != n_species:
+        raise ValueError("one list of widths per element")
     children = np.random.SeedSequence(seed).spawn(max(n_models, 8))
     chunks = []
     for m in range(n_models):
         rng = np.random.Generator(np.random.PCG64(children[m]))
-        for _s in range(n_species):
-            for l in range(len(widths) - 1):
-                fin, fout = widths[l], widths[l + 1]
+        for s in range(n_species):
+            wd = per[s]
+            for l in range(len(wd) - 1):
+                fin, fout = wd[l], wd[l + 1]
                 bw = math.sqrt(6.0 / (fin + fout))
                 chunks.append(rng.uniform(-bw, bw, size=fout * fin))
                 bb = 1.0 / math.sqrt(fin)

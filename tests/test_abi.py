@@ -66,6 +66,22 @@ def test_create_rejects_bad_params(hp, over, code):
     assert len(lib.nnp_last_error()) > 0
 
 
+@pytest.mark.parametrize("change,code", [((0, 0, 1000), 1), ((2, 4, 2), 1), ((3, 1, 0), 6),
+                                         ((6, 2, 5000), 6)])
+def test_create_rejects_bad_element_widths(hp, change, code):
+    """species_widths: first width must be D, last 1, hidden 1..4096."""
+    nnp, lib = _lib()
+    sw = np.array([[1008, 256, 192, 160, 1]] * 7, dtype=np.int32)
+    s, l, v = change
+    sw[s, l] = v
+    w = np.zeros(synth.net_size(hp["widths"]) * 7)
+    p, keep = _params(nnp, hp, w, species_widths=sw.ctypes.data_as(C.POINTER(C.c_int32)))
+    keep.append(sw)
+    h = C.c_void_p(123)
+    assert lib.nnp_create(C.byref(p), C.byref(h)) == code
+    assert h.value is None
+
+
 def test_null_arguments():
     nnp, lib = _lib()
     h = C.c_void_p()

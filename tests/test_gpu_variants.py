@@ -1,0 +1,165 @@
+"""Model variants through the C ABI against the FP64 oracle: element networks
+of their own widths (ANI-2x sizes; per-layer and fused network paths), the
+ANI-1x-shaped featuriser (4 elements, 384-dim AEV, 8 angle shifts), nonzero
+self-energies and single-network mode.
+
+Bars as in the main parity tests: FP64 1e-10 relative on E and on forces
+(of max |F|); FP32 |dE|/atom <= 1e-4 kcal/mol and force RMSE <= 1e-3;
+BF16 networks |dE|/atom <= 2 kcal/mol and force RMSE <= 1e-2 RMS(F);
+parameter gradients 1e-10 (FP64) / 1e-4 (FP32) relative in norm.
+"""
+import numpy as np
+import pytest
+
+from paper_2201_08110_amd import synth
+from tests.gpu_util import errors, make_handle, oracle_inputs, to_device, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+ANI1X_RATIO = (30, 20, 5, 5)
+
+
+def _model(which):
+    if which == "ani2x_elements":
+        return synth.ani2x_heterogeneous_hparams(), synth.LIGAND_RATIO
+    return synth.ani1x_hparams(), ANI1X_RATIO
+
+
+def _weights(hp, M, seed):
+    return synth.xavier_weights(M, hp.get("species_widths", hp["widths"]), n_species=hp["n_species"],
+                                seed=seed)
+
+
+def _eval(torch, hp, w, M, prec, b, sae=None, **kw):
+    h = make_handle(hp, w, M, prec, b, sae=sae, **kw)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    x, sp, off = to_device(torch, b, dt)
+    E, F = h.energy_forces(x, sp, off)
+    torch.cuda.synchronize()
+    assert h.device_status() == 0
+    return E.cpu().numpy(), F.double().cpu().numpy()
+
+
+def _oracle(orc, hp, w, M, prec, b, sae=None):
+    xo, wo = oracle_inputs(b, w, prec)
+    return orc.energy_forces(hp, wo, M, b.species, xo, b.mol_offsets, sae=sae)
+
+
+@pytest.mark.parametrize("which", ["ani2x_elements", "ani1x"])
+def test_fp64_energy_forces(orc, which):
+    torch = torch_cuda()
+    hp, ratio = _model(which)
+    M = 2
+    w = _weights(hp, M, 51)
+    b = synth.random_batch(61, [24, 9, 1, 40], ratio=ratio)
+    E, F = _eval(torch, hp, w, M, "fp64", b)
+    Eo, Fo = _oracle(orc, hp, w, M, "fp64", b)
+    print(which, "fp64 dE", np.abs(E - Eo).max(), "max dF", np.abs(F - Fo).max())
+    np.testing.assert_allclose(E, Eo, rtol=1e-10)
+    np.testing.assert_allclose(F, Fo, rtol=1e-9, atol=1e-10 * np.abs(Fo).max())
+
+
+@pytest.mark.parametrize("which", ["ani2x_elements", "ani1x"])
+def test_fp32_ensemble_batch(orc, which):
+    """8 models; 300 atoms per molecule take the cell-list path; 600 atoms
+    in all make the handle batch (128-row element buckets)."""
+    torch = torch_cuda()
+    hp, ratio = _model(which)
+    M = 8
+    w = _weights(hp, M, 52)
+    b = synth.random_batch(62, [64, 300, 17, 0, 219], ratio=ratio)
+    E, F = _eval(torch, hp, w, M, "fp32", b)
+    Eo, Fo = _oracle(orc, hp, w, M, "fp32", b)
+    dE, rmse = errors(E, F, Eo, Fo, b.mol_offsets)
+    print(which, "fp32 |dE|/atom", dE, "RMSE", rmse)
+    assert dE.max() <= 1e-4 and rmse.max() <= 1e-3
+
+
+def test_bf16_element_networks_fused(orc):
+    """ANI-2x element sizes pad to 256-192-192: the fused layers 2-3 kernel."""
+    torch = torch_cuda()
+    hp, _ = _model("ani2x_elements")
+    M = 8
+    w = _weights(hp, M, 53)
+    b = synth.config_batch(5, n_mols=16)
+    from paper_2201_08110_amd.nnp import NNP
+    h = NNP(hp, w, M, "bf16", max_atoms=b.n_atoms, max_mols=b.n_mols, max_atoms_per_mol=48)
+    assert h.get_knob("mlp_path") == 1
+    x, sp, off = to_device(torch, b, torch.float32)
+    E, F = h.energy_forces(x, sp, off)
+    torch.cuda.synchronize()
+    assert h.device_status() == 0
+    Eo, Fo = _oracle(orc, hp, w, M, "bf16", b)
+    dE, rmse = errors(E.cpu().numpy(), F.double().cpu().numpy(), Eo, Fo, b.mol_offsets)
+    frms = np.sqrt(np.mean(Fo ** 2))
+    print("bf16 elements: |dE|/atom max", dE.max(), "RMSE max", rmse.max(), "RMS(F)", frms)
+    assert dE.max() <= 2.0 and rmse.max() <= 1e-2 * frms
+
+
+@pytest.mark.parametrize("which,prec", [("ani2x_elements", "fp64"), ("ani1x", "fp64"),
+                                        ("ani2x_elements", "fp32")])
+def test_param_grad_element_networks(orc, which, prec):
+    torch = torch_cuda()
+    hp, ratio = _model(which)
+    M = 2
+    w = _weights(hp, M, 54)
+    b = synth.random_batch(63, [8, 13, 10], ratio=ratio)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    h = make_handle(hp, w, M, prec, b)
+    assert h.num_params == w.size
+    x, sp, off = to_device(torch, b, dt)
+    rng = np.random.default_rng(3)
+    gE, gF = rng.normal(size=b.n_mols) * 1e-2, rng.normal(size=(b.n_atoms, 3)) * 1e-2
+    gp, _ = h.backward(x, sp, off, torch.tensor(gE, dtype=torch.float64, device="cuda"),
+                       torch.tensor(gF, dtype=dt, device="cuda"))
+    torch.cuda.synchronize()
+    assert h.device_status() == 0
+    xo, wo = oracle_inputs(b, w, prec)
+    gFo = gF if prec == "fp64" else synth.round_to_fp32(gF)
+    go = orc.param_grad(hp, wo, M, b.species, xo, b.mol_offsets, gE, gFo)
+    g = gp.double().cpu().numpy()
+    err = np.linalg.norm(g - go) / np.linalg.norm(go)
+    print(which, prec, "param grad rel err", err)
+    assert err < (1e-10 if prec == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_nonzero_self_energies(orc, hp, prec):
+    torch = torch_cuda()
+    M = 2
+    w = synth.xavier_weights(M, hp["widths"], seed=55)
+    sae = np.array([-0.60, -38.04, -54.68, -75.16, -99.80, -398.1, -460.1])   # Hartree per element
+    b = synth.random_batch(64, [12, 30, 5])
+    E, F = _eval(torch, hp, w, M, prec, b, sae=sae)
+    Eo, Fo = _oracle(orc, hp, w, M, prec, b, sae=sae)
+    E0, _ = _eval(torch, hp, w, M, prec, b)
+    if prec == "fp64":
+        np.testing.assert_allclose(E, Eo, rtol=1e-12)
+    else:
+        # the energies carry ~1e5 kcal/mol of self-energy: FP64 sums, so
+        # the per-atom error bar of the network part still applies
+        dE, rmse = errors(E, F, Eo, Fo, b.mol_offsets)
+        assert dE.max() <= 1e-4 and rmse.max() <= 1e-3
+    shift = np.array([hp["energy_scale"] * sae[b.species[a:c]].sum()
+                      for a, c in zip(b.mol_offsets[:-1], b.mol_offsets[1:])])
+    np.testing.assert_allclose(E - E0, shift, rtol=1e-9)
+    # forces do not depend on the self-energies (atomic adds leave rounding-level
+    # differences between evaluations)
+    F0 = _eval(torch, hp, w, M, prec, b)[1]
+    np.testing.assert_allclose(F, F0, rtol=0, atol=(1e-12 if prec == "fp64" else 1e-5) * np.abs(F0).max())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_single_network_mode(orc, hp, prec):
+    """One network per element (M = 1) on the replica layout."""
+    torch = torch_cuda()
+    w = synth.xavier_weights(1, hp["widths"], seed=56)
+    b = synth.config_batch(5, n_mols=8)
+    E, F = _eval(torch, hp, w, 1, prec, b, max_atoms=b.n_atoms, max_apm=48)
+    Eo, Fo = _oracle(orc, hp, w, 1, prec, b)
+    dE, rmse = errors(E, F, Eo, Fo, b.mol_offsets)
+    print("M=1", prec, "|dE|/atom", dE.max(), "RMSE", rmse.max())
+    if prec == "fp32":
+        assert dE.max() <= 1e-4 and rmse.max() <= 1e-3
+    else:
+        assert dE.max() <= 2.0 and rmse.max() <= 1e-2 * np.sqrt(np.mean(Fo ** 2))
