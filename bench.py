@@ -297,6 +297,25 @@ def main():
                 hf.close()
         out["batched_forms"] = forms
 
+    # ---- model variants on the replica layout: ANI-2x element networks of
+    # their own widths, and the ANI-1x-shaped model (4 elements, 384-dim AEV)
+    if not args.no_forms:
+        variants = {}
+        hp_el = synth.ani2x_heterogeneous_hparams()
+        hp_1x = synth.ani1x_hparams()
+        b1x = synth.replica_batch(args.replicas, 48, (30, 20, 5, 5))
+        for name, hpv, bv, prec in (("ani2x_element_widths_bf16", hp_el, b5, "bf16"),
+                                    ("ani1x_bf16", hp_1x, b1x, "bf16"),
+                                    ("ani1x_fp32", hp_1x, b1x, "fp32")):
+            wv = synth.xavier_weights(M, hpv["species_widths"], n_species=hpv["n_species"])
+            hv = nnp.NNP(hpv, wv, M, prec, max_atoms=bv.n_atoms, max_mols=bv.n_mols, max_atoms_per_mol=48)
+            secv, _, _, _, _ = run_form(torch, hv, bv, 20, 3, timing=False)
+            variants[name] = {"atom_evals_per_s": bv.n_atoms / secv, "ms_per_eval": secv * 1e3,
+                              "atoms": int(bv.n_atoms),
+                              "widths": [list(x) for x in hpv["species_widths"]]}
+            hv.close()
+        out["model_variants"] = variants
+
     # ---- NNP-MM coupling (Eq. 4): the 64-atom ligand in 47,648 MM atoms --
     if not args.no_coupling:
         out["coupling"] = coupling_form(torch, nnp, synth, args)

@@ -262,6 +262,18 @@ def config_batch(cfg: int, n_mols: int | None = None) -> Batch:
     raise ValueError(f"unknown workload {cfg}")
 
 
+def replica_batch(n_mols: int, n_atoms: int = 48, ratio=LIGAND_RATIO, seed: int = BASE_SEED + 50,
+                  sigma: float = 0.05) -> Batch:
+    """n_mols jittered replicas (Gaussian sigma in A) of one seeded molecule of
+    n_atoms atoms with the given element ratio (workload 5 for other models)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    counts = rounded_counts(n_atoms, ratio)
+    base, sp = random_molecule(g, counts, n_atoms ** (1.0 / 3.0) * 2.2)
+    mols = [(base + g.normal(0.0, sigma, size=base.shape), sp) for _ in range(n_mols)]
+    c, s, o = _pack(mols)
+    return Batch(f"{n_mols} replicas of a {n_atoms}-atom molecule", c, s, o, 8, "bf16")
+
+
 def random_batch(seed: int, sizes, box_scale: float = 2.2, ratio=LIGAND_RATIO) -> Batch:
     """Free-form seeded batch (tests): molecules of the given atom counts."""
     g = np.random.Generator(np.random.PCG64(seed))
