@@ -222,10 +222,11 @@ int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t
  *                             kernel per row tile and model (hidden widths
  *                             256-192-{160..192} only),
  *                         2 = one GEMM per layer and direction.
- *                         auto: 1 when supported and the handle batches
- *                         (max_atoms > 256, not FP64), else 2.
- *   NNP_KNOB_GEMM_STAGES  LDS pipeline depth of the layer-1 GEMMs: 2 or 3
- *                         (auto 2: two workgroups fit a compute unit).
+ *                         auto: 1 when supported, else 2.
+ *   NNP_KNOB_GEMM_STAGES  LDS pipeline depth of the layer-1 GEMMs on handles
+ *                         with 128-row buckets: 2 or 3 (auto 2: two
+ *                         workgroups fit a compute unit); 16-row buckets
+ *                         (small batches, FP64) always take 6.
  *   NNP_KNOB_CELL_MIN     molecules with more atoms than this build their
  *                         neighbour lists through cutoff cells, smaller ones
  *                         scan all atoms: 16..1024 (auto 128).
@@ -237,6 +238,12 @@ int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t
  *                         rows on 4 waves, 2 = half that (at least 16) on 4
  *                         waves, 3 = the full tile on 8 waves (2 x 4); 3 is
  *                         taken as 1 for FP64 (auto 1).
+ *   NNP_KNOB_ATOM_CHUNK   central atoms per workgroup of the featuriser and
+ *                         force kernels (4 waves): 4, 8 or 16.  Fewer atoms
+ *                         per workgroup spread a small batch over more
+ *                         compute units; more share the staging of their
+ *                         molecule.  auto: 16 when the capacity gives at
+ *                         least 1024 workgroups at 16, else 4.
  *
  * Setting a knob drops the handle's captured graphs.  Invalid knob ids or
  * values return NNP_E_INVALID (a fused path on unsupported widths returns
@@ -247,7 +254,8 @@ enum {
     NNP_KNOB_CELL_MIN = 2,
     NNP_KNOB_TAIL_TILE = 3,
     NNP_KNOB_GEMM_WAVES = 4,
-    NNP_N_KNOBS = 5
+    NNP_KNOB_ATOM_CHUNK = 5,
+    NNP_N_KNOBS = 6
 };
 nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value);
 nnp_status nnp_get_knob(nnp_handle* h, int32_t knob, int32_t* value);

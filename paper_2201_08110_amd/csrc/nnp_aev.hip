@@ -248,6 +248,88 @@ __global__ __launch_bounds__(1024) void k_bucket_scatter(int A, int S, const int
     }
 }
 
+// The three steps in one workgroup, for batches of at most kPrepBlock atoms
+// and molecules (one launch instead of three on small batches); same results.
+__global__ __launch_bounds__(1024) void k_bucket_one(int A, int B, int S, int max_apm, int row_tile,
+                                                     int Rcap, const int32_t* __restrict__ mol_off,
+                                                     const int32_t* __restrict__ species,
+                                                     int32_t* __restrict__ mol_of_atom,
+                                                     int32_t* __restrict__ row_of_atom,
+                                                     int32_t* __restrict__ atom_of_row,
+                                                     int32_t* __restrict__ tile_species,
+                                                     BucketInfo* __restrict__ info,
+                                                     int32_t* __restrict__ flag) {
+    __shared__ int wcnt[kPrepBlock / 64][kMaxSpecies];
+    __shared__ int tot[kMaxSpecies];
+    __shared__ int base[kMaxSpecies + 1];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    if (tid == 0 && (mol_off[0] != 0 || mol_off[B] != A)) atomicOr(flag, FLAG_CAPACITY);
+    if (tid < B) {
+        const int a0 = mol_off[tid], a1 = mol_off[tid + 1];
+        if (a0 < 0 || a1 < a0 || a1 > A || a1 - a0 > max_apm) atomicOr(flag, FLAG_CAPACITY);
+    }
+    const int a = tid;
+    int s = -1;
+    if (a < A) {
+        int lo = 0, hi = B;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (mol_off[mid] <= a) lo = mid;
+            else hi = mid;
+        }
+        mol_of_atom[a] = lo;
+        s = species[a];
+        if (s < 0 || s >= S) {
+            atomicOr(flag, FLAG_SPECIES);
+            s = 0;
+        }
+    }
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int mypre = 0;
+    for (int q = 0; q < S; ++q) {
+        const unsigned long long m = __ballot(s == q);
+        if (lane == 0) wcnt[wave][q] = __popcll(m);
+        if (s == q) mypre = __popcll(m & lt);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        base[0] = 0;
+        for (int q = 0; q < S; ++q) {
+            int c = 0;
+            for (int w = 0; w < kPrepBlock / 64; ++w) c += wcnt[w][q];
+            tot[q] = c;
+            base[q + 1] = base[q] + ((c + row_tile - 1) / row_tile) * row_tile;
+            info->count[q] = c;
+        }
+        for (int q = 0; q <= S; ++q) info->off[q] = base[q];
+        int rows = base[S];
+        if (rows > Rcap) {
+            atomicOr(flag, FLAG_CAPACITY);
+            rows = 0;
+        }
+        info->rows = rows;
+    }
+    __syncthreads();
+    const int rows = base[S] <= Rcap ? base[S] : 0;
+    for (int t = tid; t < Rcap / row_tile; t += blockDim.x) {
+        const int r = t * row_tile;
+        int sp = -1;
+        if (r < rows)
+            for (int q = 0; q < S; ++q)
+                if (base[q] <= r && r < base[q + 1]) sp = q;
+        tile_species[t] = sp;
+    }
+    for (int q = 0; q < S; ++q)
+        for (int r = base[q] + tot[q] + tid; r < base[q + 1] && r < rows; r += blockDim.x) atom_of_row[r] = -1;
+    if (s >= 0 && rows > 0) {
+        int pre = 0;
+        for (int w = 0; w < wave; ++w) pre += wcnt[w][s];
+        const int row = base[s] + pre + mypre;
+        row_of_atom[a] = row;
+        atom_of_row[row] = a;
+    }
+}
+
 template <typename P>
 hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* species,
                        Work<P>& w, hipStream_t st, const Timer& tm) {
@@ -255,6 +337,13 @@ hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* s
     int32_t* blk_cnt = w.blk;
     int32_t* blk_base = w.blk + (size_t)nblk * kMaxSpecies;
     tm.b("prep", st);
+    if (nblk <= 1) {
+        hipLaunchKernelGGL(k_bucket_one, dim3(1), dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S, sh.max_apm,
+                           sh.row_tile, sh.Rcap, mol_off, species, w.mol_of_atom, w.row_of_atom,
+                           w.atom_of_row, w.tile_species, w.info, w.flag);
+        tm.e("prep", st);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_bucket_count, dim3(nblk), dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S,
                        sh.max_apm, mol_off, species, w.mol_of_atom, blk_cnt, w.flag);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(256), 0, st, nblk, sh.S, sh.row_tile, sh.Rcap,
@@ -289,7 +378,7 @@ template <typename X> inline size_t lds_bytes(size_t n) { return (sizeof(X) * n 
 // central atom's cell are tested), so the scan emits sorted lists, which are
 // assembled in LDS and written out coalesced.  Also zeroes the forces.
 constexpr int kNbrChunk = 64;  // central atoms per neighbour-list workgroup
-constexpr int kChunk = 16;     // central atoms per AEV / force workgroup
+constexpr int kChunk = 16;     // most central atoms per AEV / force workgroup (the knob picks 4..16)
 constexpr int kWaves = 4;
 constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
 
@@ -307,7 +396,7 @@ __device__ inline T wave_max(T v) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, int cell_min, int cap,
+__global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, int cell_min, int skip_small, int cap,
                                                    T rcr, T rca2,
                                                    T rcr2, const int32_t* __restrict__ mol_off,
                                                    const int32_t* __restrict__ species,
@@ -319,6 +408,7 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
     const int b = blockIdx.x;
     const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
     if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
+    if (skip_small && n <= cell_min) return;   // listed by k_nbr_pairs
     const int i0 = blockIdx.y * kNbrChunk;
     if (i0 >= n) return;
     const int lane = lane_id();
@@ -327,6 +417,8 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
     T* sx = lb.take<T>(4 * (size_t)max_apm);            // staged atoms: x y z
     int* sid = lb.take<int>(max_apm);                   // local index of the k-th staged atom
     uint16_t* lst = lb.take<uint16_t>((size_t)kNbrChunk * cap);
+    T* tx = lb.take<T>(3 * (size_t)max_apm);            // the molecule's x y z, input order
+    int* tsp = lb.take<int>(max_apm);                   // and elements
     int* kstart = nullptr;                              // [nkeys+1] bucket starts (cells)
     int* kcur = nullptr;                                // [nkeys]   scatter cursors
     int* akey = nullptr;                                // [max_apm] key of every atom
@@ -342,23 +434,26 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
     // of cutoff cells with edge >= rcr, so a central atom scans <= 27 cells.
     int nc0 = 1, nc1 = 1, nc2 = 1;
     T lo0 = 0, lo1 = 0, lo2 = 0, ih0 = 0, ih1 = 0, ih2 = 0;
+    // one coalesced pass over the molecule's inputs: every later pass reads LDS
+    for (int t = lane; t < 3 * n; t += 64) tx[t] = x[3 * (size_t)a0 + t];
+    for (int j = lane; j < n; j += 64) {
+        const int s = species[a0 + j];
+        tsp[j] = (s < 0 || s >= S) ? 0 : s;
+    }
+    wave_sync();
     if (!cells) {
         int base = 0;
         for (int q = 0; q < S; ++q) {
             for (int j0 = 0; j0 < n; j0 += 64) {
                 const int j = j0 + lane;
-                int s = -1;
-                if (j < n) {
-                    s = species[a0 + j];
-                    s = (s < 0 || s >= S) ? 0 : s;
-                }
+                const int s = j < n ? tsp[j] : -1;
                 const unsigned long long m = __ballot(s == q);
                 if (s == q) {
                     const int pos = base + __popcll(m & lt);
                     sid[pos] = j;
-                    sx[4 * pos + 0] = x[3 * ((size_t)a0 + j) + 0];
-                    sx[4 * pos + 1] = x[3 * ((size_t)a0 + j) + 1];
-                    sx[4 * pos + 2] = x[3 * ((size_t)a0 + j) + 2];
+                    sx[4 * pos + 0] = tx[3 * j + 0];
+                    sx[4 * pos + 1] = tx[3 * j + 1];
+                    sx[4 * pos + 2] = tx[3 * j + 2];
                 }
                 base += __popcll(m);
             }
@@ -366,7 +461,7 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
     } else {
         T mn0 = T(1e30), mn1 = T(1e30), mn2 = T(1e30), mx0 = T(-1e30), mx1 = T(-1e30), mx2 = T(-1e30);
         for (int j = lane; j < n; j += 64) {
-            const T* p = x + 3 * ((size_t)a0 + j);
+            const T* p = tx + 3 * j;
             mn0 = fmin(mn0, p[0]); mx0 = fmax(mx0, p[0]);
             mn1 = fmin(mn1, p[1]); mx1 = fmax(mx1, p[1]);
             mn2 = fmin(mn2, p[2]); mx2 = fmax(mx2, p[2]);
@@ -383,9 +478,9 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
         for (int k = lane; k <= nkeys; k += 64) kstart[k] = 0;
         wave_sync();
         for (int j = lane; j < n; j += 64) {
-            int s = species[a0 + j];
+            int s = tsp[j];
             s = (s < 0 || s >= S) ? 0 : s;
-            const T* p = x + 3 * ((size_t)a0 + j);
+            const T* p = tx + 3 * j;
             const int c0 = min((int)((p[0] - lo0) * ih0), nc0 - 1);
             const int c1 = min((int)((p[1] - lo1) * ih1), nc1 - 1);
             const int c2 = min((int)((p[2] - lo2) * ih2), nc2 - 1);
@@ -415,9 +510,9 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
         for (int j = lane; j < n; j += 64) {
             const int pos = atomicAdd(&kcur[akey[j]], 1);
             sid[pos] = j;
-            sx[4 * pos + 0] = x[3 * ((size_t)a0 + j) + 0];
-            sx[4 * pos + 1] = x[3 * ((size_t)a0 + j) + 1];
-            sx[4 * pos + 2] = x[3 * ((size_t)a0 + j) + 2];
+            sx[4 * pos + 0] = tx[3 * j + 0];
+            sx[4 * pos + 1] = tx[3 * j + 1];
+            sx[4 * pos + 2] = tx[3 * j + 2];
         }
     }
     wave_sync();
@@ -449,8 +544,31 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
         }                                                                                      \
     }
     if (!cells) {
+        // eight candidates' loads in flight before their tests (the tests
+        // only append to this lane's list)
         for (int pass = 0; pass < 2; ++pass) {
-            for (int k = 0; k < n; ++k) NNP_TEST(k)
+            for (int k0 = 0; k0 < n; k0 += 8) {
+                int id[8];
+                T c0[8], c1[8], c2[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = min(k0 + u, n - 1);
+                    id[u] = sid[k];
+                    c0[u] = sx[4 * k];
+                    c1[u] = sx[4 * k + 1];
+                    c2[u] = sx[4 * k + 2];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const T d0 = c0[u] - xi0, d1 = c1[u] - xi1, d2 = c2[u] - xi2;
+                    const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                    if (act && k0 + u < n && id[u] != il &&
+                        (pass == 0 ? (r2 < rca2) : (r2 >= rca2 && r2 < rcr2))) {
+                        if (cnt < cap) my[cnt] = (uint16_t)id[u];
+                        ++cnt;
+                    }
+                }
+            }
             if (pass == 0) nang = cnt;
         }
     } else {
@@ -486,16 +604,123 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
     for (int e = lane; e < na * cap; e += 64) dst[e] = lst[e];
 }
 
+// Neighbour lists of molecules of at most cell_min atoms, one wave per
+// central atom and one lane per candidate: the molecule is staged in element
+// order (as k_neighbours does), each 64-candidate slice is tested at once and
+// its hits are appended in order through a ballot, angular ones (r < rca) in
+// a first sweep and the rest (r < rcr) in a second.  The lists equal those of
+// the scanning kernel entry for entry; no lane walks the molecule serially.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nbr_pairs(int A, int S, int max_apm, int cell_min, int chunk,
+                                                   int cap, T rca2, T rcr2,
+                                                   const int32_t* __restrict__ mol_off,
+                                                   const int32_t* __restrict__ species,
+                                                   const T* __restrict__ x, T* __restrict__ F,
+                                                   uint16_t* __restrict__ nbr,
+                                                   int32_t* __restrict__ nbr_cnt,
+                                                   int32_t* __restrict__ flag) {
+    extern __shared__ __align__(16) char smem[];
+    const int b = blockIdx.x;
+    const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
+    if (n <= 0 || n > max_apm || n > cell_min || a0 < 0 || a0 + n > A) return;
+    const int i0 = blockIdx.y * chunk;
+    if (i0 >= n) return;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
+    LdsBump lb(smem);
+    T* sx = lb.take<T>(4 * (size_t)max_apm);   // staged atoms x y z (element order)
+    int* sid = lb.take<int>(max_apm);          // input index of the k-th staged atom
+    T* tx = lb.take<T>(3 * (size_t)max_apm);   // input order
+    int* tsp = lb.take<int>(max_apm);
+    for (int t = tid; t < 3 * n; t += blockDim.x) tx[t] = x[3 * (size_t)a0 + t];
+    for (int j = tid; j < n; j += blockDim.x) {
+        const int s = species[a0 + j];
+        tsp[j] = (s < 0 || s >= S) ? 0 : s;
+    }
+    __syncthreads();
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (wave == 0) {   // stable counting order by element
+        int base = 0;
+        for (int q = 0; q < S; ++q)
+            for (int j0 = 0; j0 < n; j0 += 64) {
+                const int j = j0 + lane;
+                const int s = j < n ? tsp[j] : -1;
+                const unsigned long long m = __ballot(s == q);
+                if (s == q) {
+                    const int pos = base + __popcll(m & lt);
+                    sid[pos] = j;
+                    sx[4 * pos + 0] = tx[3 * j + 0];
+                    sx[4 * pos + 1] = tx[3 * j + 1];
+                    sx[4 * pos + 2] = tx[3 * j + 2];
+                }
+                base += __popcll(m);
+            }
+    }
+    __syncthreads();
+    const int nc = min(chunk, n - i0);
+    for (int ic = wave; ic < nc; ic += nw) {
+        const int il = i0 + ic;
+        const T xi0 = tx[3 * il], xi1 = tx[3 * il + 1], xi2 = tx[3 * il + 2];
+        if (F && lane < 3) F[3 * ((size_t)a0 + il) + lane] = T(0);
+        uint16_t* out = nbr + ((size_t)a0 + il) * cap;
+        int cnt = 0, nang = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int k0 = 0; k0 < n; k0 += 64) {
+                const int k = k0 + lane;
+                bool hit = false;
+                int j = 0;
+                if (k < n) {
+                    j = sid[k];
+                    const T d0 = sx[4 * k] - xi0, d1 = sx[4 * k + 1] - xi1, d2 = sx[4 * k + 2] - xi2;
+                    const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                    hit = j != il && (pass == 0 ? (r2 < rca2) : (r2 >= rca2 && r2 < rcr2));
+                }
+                const unsigned long long m = __ballot(hit);
+                const int pos = cnt + __popcll(m & lt);
+                if (hit && pos < cap) out[pos] = (uint16_t)j;
+                cnt += __popcll(m);
+            }
+            if (pass == 0) nang = cnt;
+        }
+        if (lane == 0) {
+            int nall = cnt;
+            if (nall > cap) {
+                atomicOr(flag, FLAG_CAPACITY);
+                nall = cap;
+                nang = nang > cap ? cap : nang;
+            }
+            nbr_cnt[(size_t)a0 + il] = nang | (nall << 16);
+        }
+    }
+}
+
 template <typename P>
 hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
                              const int32_t* mol_off, const int32_t* species,
                              const typename P::T* x, typename P::T* F, Work<P>& w, hipStream_t st,
                              const Timer& tm) {
     typedef typename P::T T;
+    // molecules up to cell_min atoms: one wave per central atom
+    {
+        const int small = std::min(sh.max_apm, sh.cell_min);
+        dim3 grid(sh.B, (small + sh.chunk - 1) / sh.chunk);
+        const size_t lds = lds_bytes<T>(4 * (size_t)sh.max_apm) + lds_bytes<int>(sh.max_apm) +
+                           lds_bytes<T>(3 * (size_t)sh.max_apm) + lds_bytes<int>(sh.max_apm);
+        if (lds > kMaxLds) return hipErrorInvalidValue;
+        hipError_t e = ensure_lds((const void*)k_nbr_pairs<T>, lds);
+        if (e != hipSuccess) return e;
+        tm.b("neighbours", st);
+        hipLaunchKernelGGL(k_nbr_pairs<T>, grid, dim3(256), lds, st, sh.A, sh.S, sh.max_apm, sh.cell_min,
+                           sh.chunk, sh.cap_nbr, c.rca2, c.rcr2, mol_off, species, x, F, w.nbr,
+                           w.nbr_cnt, w.flag);
+        tm.e("neighbours", st);
+        if ((e = hipGetLastError()) != hipSuccess || sh.max_apm <= sh.cell_min) return e;
+    }
+    // larger molecules: cutoff cells, one lane per central atom
     dim3 grid(sh.B, (sh.max_apm + kNbrChunk - 1) / kNbrChunk);
     const int nkeys = kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim;
     size_t lds = lds_bytes<T>(4 * (size_t)sh.max_apm) + lds_bytes<int>(sh.max_apm) +
-                 lds_bytes<uint16_t>((size_t)kNbrChunk * sh.cap_nbr);
+                 lds_bytes<uint16_t>((size_t)kNbrChunk * sh.cap_nbr) +
+                 lds_bytes<T>(3 * (size_t)sh.max_apm) + lds_bytes<int>(sh.max_apm);
     if (sh.max_apm > sh.cell_min)
         lds += lds_bytes<int>(nkeys + 1) + lds_bytes<int>(nkeys) + lds_bytes<int>(sh.max_apm);
     if (lds > kMaxLds) return hipErrorInvalidValue;
@@ -503,7 +728,7 @@ hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
     if (e != hipSuccess) return e;
     tm.b("neighbours", st);
     hipLaunchKernelGGL(k_neighbours<T>, grid, dim3(64), lds, st, sh.A, sh.S, sh.max_apm,
-                       sh.cell_min, sh.cap_nbr, c.rcr, c.rca2, c.rcr2, mol_off, species, x, F, w.nbr,
+                       sh.cell_min, 1, sh.cap_nbr, c.rcr, c.rca2, c.rcr2, mol_off, species, x, F, w.nbr,
                        w.nbr_cnt, w.flag);
     tm.e("neighbours", st);
     return hipGetLastError();
@@ -723,7 +948,7 @@ __device__ inline void pair_of(const AtomLists<T>& al, int NB, int S, int p, int
 // 16-byte stores.
 template <typename P, int NZ>
 __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
-                                             int cap, const int32_t* __restrict__ mol_off,
+                                             int chunk, int cap, const int32_t* __restrict__ mol_off,
                                              const int32_t* __restrict__ species,
                                              const typename P::T* __restrict__ x,
                                              const uint16_t* __restrict__ nbr,
@@ -739,9 +964,9 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
     const int b = blockIdx.x;
     const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
     if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
-    const int i0 = blockIdx.y * kChunk;
+    const int i0 = blockIdx.y * chunk;
     if (i0 >= n) return;
-    const int nc = min(kChunk, n - i0);
+    const int nc = min(chunk, n - i0);
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
     const int S = c.S, RL = kNR * S, NB = S * (S + 1) / 2;
 
@@ -778,15 +1003,31 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
             const int g = lane >> 4, k = lane & 15;
             const T sk = c.shf_r[k];
             for (int s = g; s < S; s += 4) {
-                T acc = T(0);
+                // two accumulators, loads of four neighbours in flight
+                T acc0 = T(0), acc1 = T(0);
                 for (int run = 0; run < 2; ++run) {
                     const int t1 = run ? al.roff[s + 1] : al.aoff[s + 1];
-                    for (int t = run ? al.roff[s] : al.aoff[s]; t < t1; ++t) {
+                    int t = run ? al.roff[s] : al.aoff[s];
+                    for (; t + 4 <= t1; t += 4) {
+                        T r[4], f[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            r[u] = nb[kNbStride * (t + u) + 3];
+                            f[u] = nb[kNbStride * (t + u) + 4];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; u += 2) {
+                            const T d0 = r[u] - sk, d1 = r[u + 1] - sk;
+                            acc0 += m_exp(-c.eta_r * d0 * d0) * f[u];
+                            acc1 += m_exp(-c.eta_r * d1 * d1) * f[u + 1];
+                        }
+                    }
+                    for (; t < t1; ++t) {
                         const T d = nb[kNbStride * t + 3] - sk;
-                        acc += m_exp(-c.eta_r * d * d) * nb[kNbStride * t + 4];
+                        acc0 += m_exp(-c.eta_r * d * d) * nb[kNbStride * t + 4];
                     }
                 }
-                row[kNR * s + k] = c.radial_pref * acc;
+                row[kNR * s + k] = c.radial_pref * (acc0 + acc1);
             }
         }
 
@@ -822,11 +1063,25 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
             for (int bl = 0; bl < NB; ++bl) {
                 const int s0 = max(al.bst[bl], p0), e0 = min(al.bst[bl + 1], p0 + nbat);
                 if (s0 >= e0) continue;
-                T acc = T(0);
-                for (int p = s0 + h; p < e0; p += 2) {
+                // two accumulators, four pairs' factors in flight
+                T acc = T(0), acc1 = T(0);
+                int p = s0 + h;
+                for (; p + 6 < e0; p += 8) {
+                    T fa[4], fz[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const T* f = pf + PF * (p + 2 * u - p0);
+                        fa[u] = f[qa];
+                        fz[u] = f[NA + qz];
+                    }
+                    acc += fa[0] * fz[0] + fa[2] * fz[2];
+                    acc1 += fa[1] * fz[1] + fa[3] * fz[3];
+                }
+                for (; p < e0; p += 2) {
                     const T* f = pf + PF * (p - p0);
                     acc += f[qa] * f[NA + qz];
                 }
+                acc += acc1;
                 acc += __shfl_xor(acc, 32);
                 if (h == 0) row[RL + kNAZ * bl + q] += acc;
             }
@@ -859,7 +1114,7 @@ hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const i
                       const int32_t* species, const typename P::T* x, Work<P>& w,
                       typename P::T* aev_out, hipStream_t st, const Timer& tm) {
     typedef typename P::T T;
-    dim3 grid(sh.B, (sh.max_apm + kChunk - 1) / kChunk);
+    dim3 grid(sh.B, (sh.max_apm + sh.chunk - 1) / sh.chunk);
     int nw = kWaves;
     size_t lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw);
     while (lds > kMaxLds && nw > 1) lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw /= 2);
@@ -868,7 +1123,7 @@ hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const i
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("aev", st);
-    hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.cap_nbr,
+    hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.chunk, sh.cap_nbr,
                        mol_off, species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.G, aev_out);
     tm.e("aev", st);
     return hipGetLastError();
@@ -885,7 +1140,7 @@ hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const i
 // their rates along v.
 template <typename P, int NZ>
 __global__ __launch_bounds__(256) void k_aev_jvp(AevConst<typename P::T> c, int A, int max_apm,
-                                                 int cap, const int32_t* __restrict__ mol_off,
+                                                 int chunk, int cap, const int32_t* __restrict__ mol_off,
                                                  const int32_t* __restrict__ species,
                                                  const typename P::T* __restrict__ x,
                                                  const typename P::T* __restrict__ v,
@@ -902,9 +1157,9 @@ __global__ __launch_bounds__(256) void k_aev_jvp(AevConst<typename P::T> c, int 
     const int b = blockIdx.x;
     const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
     if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
-    const int i0 = blockIdx.y * kChunk;
+    const int i0 = blockIdx.y * chunk;
     if (i0 >= n) return;
-    const int nc = min(kChunk, n - i0);
+    const int nc = min(chunk, n - i0);
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
     const int S = c.S, RL = kNR * S;
 
@@ -1050,7 +1305,7 @@ hipError_t launch_aev_jvp(const Shape& sh, const AevConst<typename P::T>& c,
                           const typename P::T* x, const typename P::T* v, Work<P>& w,
                           typename P::TS* Gd, hipStream_t st, const Timer& tm) {
     typedef typename P::T T;
-    dim3 grid(sh.B, (sh.max_apm + kChunk - 1) / kChunk);
+    dim3 grid(sh.B, (sh.max_apm + sh.chunk - 1) / sh.chunk);
     int nw = kWaves;
     size_t lds = jvp_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw);
     while (lds > kMaxLds && nw > 1) lds = jvp_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw /= 2);
@@ -1059,7 +1314,7 @@ hipError_t launch_aev_jvp(const Shape& sh, const AevConst<typename P::T>& c,
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("aev_jvp", st);
-    hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.cap_nbr,
+    hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.chunk, sh.cap_nbr,
                        mol_off, species, x, v, w.nbr, w.nbr_cnt, w.row_of_atom, Gd);
     tm.e("aev_jvp", st);
     return hipGetLastError();
@@ -1091,7 +1346,7 @@ __device__ inline void st4(double* p, const double v[4]) {
 
 template <typename P, int NZ>
 __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A, int max_apm,
-                                                int cap, const int32_t* __restrict__ mol_off,
+                                                int chunk, int cap, const int32_t* __restrict__ mol_off,
                                                 const int32_t* __restrict__ species,
                                                 const typename P::T* __restrict__ x,
                                                 const uint16_t* __restrict__ nbr,
@@ -1106,9 +1361,9 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
     const int b = blockIdx.x;
     const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
     if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
-    const int i0 = blockIdx.y * kChunk;
+    const int i0 = blockIdx.y * chunk;
     if (i0 >= n) return;
-    const int nc = min(kChunk, n - i0);
+    const int nc = min(chunk, n - i0);
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
     const int S = c.S, RL = kNR * S, NB = S * (S + 1) / 2;
     const int GL = RL + kBlkPad * NB;
@@ -1293,7 +1548,7 @@ hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
                          Work<P>& w, typename P::T* F, hipStream_t st, const Timer& tm) {
     typedef typename P::T T;
     if (c.Dp > 2 * 16 * 64) return hipErrorInvalidValue;
-    dim3 grid(sh.B, (sh.max_apm + kChunk - 1) / kChunk);
+    dim3 grid(sh.B, (sh.max_apm + sh.chunk - 1) / sh.chunk);
     int nw = kWaves;
     size_t lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw);
     while (lds > kMaxLds && nw > 1) lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw /= 2);
@@ -1302,7 +1557,7 @@ hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("forces", st);
-    hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.cap_nbr,
+    hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.chunk, sh.cap_nbr,
                        mol_off, species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.dG, F);
     tm.e("forces", st);
     return hipGetLastError();

@@ -192,6 +192,7 @@ struct Shape {
     int gemm_waves;                    // waves per workgroup of the layer-1 GEMMs (4 or 8)
     int cell_min;                      // molecules above this many atoms use cutoff cells
     int tail_tile;                     // fused kernel tile variant (1, 2 or 3)
+    int chunk;                         // central atoms per featuriser / force workgroup (4, 8, 16)
 };
 
 // kernel timing hook (runtime-side); launchers call these around launches

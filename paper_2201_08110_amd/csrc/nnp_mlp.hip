@@ -850,6 +850,9 @@ static hipError_t run_l1(GemmArgs<P> a, const Shape& sh, int N, hipStream_t st, 
             return sh.gemm_stages == 2 ? run_gemm<P, BM, C::BNW, 2, 4, 2, EPI>(a, R, N, 1, st, tm, name)
                                        : run_gemm<P, BM, C::BNW, 2, 4, 3, EPI>(a, R, N, 1, st, tm, name);
     }
+    // 16-row tiles (small batches) stream the weights through a deeper pipeline:
+    // few workgroups, so each keeps more loads in flight
+    if constexpr (BM == 16) return run_gemm<P, BM, C::BNW, C::WM, C::WN, 6, EPI>(a, R, N, 1, st, tm, name);
     return sh.gemm_stages == 2 ? run_gemm<P, BM, C::BNW, C::WM, C::WN, 2, EPI>(a, R, N, 1, st, tm, name)
                                : run_gemm<P, BM, C::BNW, C::WM, C::WN, 3, EPI>(a, R, N, 1, st, tm, name);
 }

@@ -116,7 +116,7 @@ struct nnp_handle {
     std::vector<GraphEntry> graphs;
 
     // tunable knobs as set by the caller (0 = automatic)
-    int32_t knob[NNP_N_KNOBS] = {0, 0, 0, 0, 0};
+    int32_t knob[NNP_N_KNOBS] = {0, 0, 0, 0, 0, 0};
 
     // timing
     bool timing = false;
@@ -367,11 +367,14 @@ int32_t knob_value(const nnp_handle* h, int k) {
     switch (k) {
     case NNP_KNOB_MLP_PATH:
         if (v) return v;
-        return (mlp_fused_supported(sh.H1, sh.H2, sh.H3) && sh.row_tile == 128) ? 1 : 2;
+        return mlp_fused_supported(sh.H1, sh.H2, sh.H3) ? 1 : 2;
     case NNP_KNOB_GEMM_STAGES: return v ? v : 2;
     case NNP_KNOB_CELL_MIN: return v ? v : 128;
     case NNP_KNOB_TAIL_TILE: return v ? v : 1;
     case NNP_KNOB_GEMM_WAVES: return v ? v : 4;
+    case NNP_KNOB_ATOM_CHUNK:
+        if (v) return v;
+        return (int64_t)h->max_mols * ((h->max_apm + 15) / 16) >= 1024 ? 16 : 4;
     }
     return 0;
 }
@@ -383,6 +386,7 @@ void apply_knobs(nnp_handle* h) {
     h->shape.cell_min = knob_value(h, NNP_KNOB_CELL_MIN);
     h->shape.tail_tile = knob_value(h, NNP_KNOB_TAIL_TILE);
     h->shape.gemm_waves = knob_value(h, NNP_KNOB_GEMM_WAVES);
+    h->shape.chunk = knob_value(h, NNP_KNOB_ATOM_CHUNK);
     for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     h->graphs.clear();
 }
@@ -553,7 +557,8 @@ const char* knob_name(int k) {
     return k == NNP_KNOB_MLP_PATH ? "mlp_path"
          : k == NNP_KNOB_GEMM_STAGES ? "gemm_stages"
          : k == NNP_KNOB_CELL_MIN ? "cell_min"
-         : k == NNP_KNOB_TAIL_TILE ? "tail_tile" : "gemm_waves";
+         : k == NNP_KNOB_TAIL_TILE ? "tail_tile"
+         : k == NNP_KNOB_GEMM_WAVES ? "gemm_waves" : "atom_chunk";
 }
 
 std::string tune_key(const nnp_handle* h) {
@@ -643,6 +648,8 @@ nnp_status autotune(nnp_handle* h, const nnp_batch* b, const typename P::T* x, i
             if (knob_value(h, NNP_KNOB_MLP_PATH) == 1 && h->shape.row_tile == 128) cand = {1, 2, 3};
         } else if (k == NNP_KNOB_GEMM_WAVES) {
             if (h->shape.row_tile == 128 && h->precision != NNP_PREC_FP64) cand = {4, 8};
+        } else if (k == NNP_KNOB_ATOM_CHUNK) {
+            cand = {4, 8, 16};
         } else {
             for (int c : {32, 64, 128, 256})
                 if (c < h->max_apm) cand.push_back(c);
@@ -1022,6 +1029,8 @@ nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value) {
         ok = ok || (value >= 1 && value <= 3);
     } else if (knob == NNP_KNOB_GEMM_WAVES) {
         ok = ok || value == 4 || value == 8;
+    } else if (knob == NNP_KNOB_ATOM_CHUNK) {
+        ok = ok || value == 4 || value == 8 || value == 16;
     } else {
         ok = ok || (value >= 16 && value <= kMaxAtomsPerMol);
     }
@@ -1066,15 +1075,13 @@ nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, i
             rc = autotune<PrecBF16>(h, b, (const float*)coords, reps, timings);
         if (rc) return rc;
     }
-    char vals[240];
-    std::snprintf(vals, sizeof(vals),
-                  "\"mlp_path\": %d, \"gemm_stages\": %d, \"cell_min\": %d, \"tail_tile\": %d, "
-                  "\"gemm_waves\": %d",
-                  knob_value(h, 0), knob_value(h, 1), knob_value(h, 2), knob_value(h, 3), knob_value(h, 4));
+    std::string vals;
+    for (int k = 0; k < NNP_N_KNOBS; ++k)
+        vals += std::string(k ? ", " : "") + "\"" + knob_name(k) + "\": " + std::to_string(knob_value(h, k));
     if (!hit && cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(NNP_E_INVALID, std::string("cannot append to tune cache ") + cache_path);
-        std::fprintf(f, "{\"key\": \"%s\", %s}\n", key.c_str(), vals);
+        std::fprintf(f, "{\"key\": \"%s\", %s}\n", key.c_str(), vals.c_str());
         std::fclose(f);
     }
     if (report && report_cap > 0) {

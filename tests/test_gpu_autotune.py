@@ -20,6 +20,8 @@ VARIANTS = [dict(mlp_path=m, gemm_stages=g, cell_min=c, tail_tile=1)
             for m, g, c in itertools.product([1, 2], [2, 3], [32, 1024])]
 VARIANTS += [dict(mlp_path=1, gemm_stages=2, cell_min=128, tail_tile=t) for t in (2, 3)]
 VARIANTS += [dict(mlp_path=1, gemm_stages=g, cell_min=128, tail_tile=1, gemm_waves=8) for g in (2, 3)]
+VARIANTS += [dict(mlp_path=2, gemm_stages=2, cell_min=c, tail_tile=1, gemm_waves=4, atom_chunk=a)
+             for a, c in ((16, 32), (8, 1024), (4, 128))]
 
 
 def _batch():

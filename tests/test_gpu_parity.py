@@ -100,7 +100,8 @@ def test_batch_equals_single_molecules(hp):
         np.testing.assert_allclose(F[a0:a1], Fk, rtol=1e-10, atol=1e-10)
 
 
-def test_bf16_mlp_replicas(orc, hp):
+@pytest.mark.parametrize("n_mols", [16, 40])
+def test_bf16_mlp_replicas(orc, hp, n_mols):
     """BF16 network GEMMs (FP32 accumulate), FP32 AEV and forces, 16 replicas.
 
     Bound: operands are rounded to bf16 (relative 2^-9 each); with K-term dot
@@ -110,7 +111,7 @@ def test_bf16_mlp_replicas(orc, hp):
     asserts |dE|/atom <= 2 kcal/mol and force RMSE <= 1e-2 * RMS(F).
     """
     torch = torch_cuda()
-    b = synth.config_batch(5, n_mols=16)
+    b = synth.config_batch(5, n_mols=n_mols)   # 768 atoms: one bucketing block; 1920: three
     w = synth.xavier_weights(8, hp["widths"])
     _, E, F = _run(torch, hp, w, 8, "bf16", b)
     Eo, Fo = _oracle(orc, hp, w, 8, "bf16", b)

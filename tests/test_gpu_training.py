@@ -23,13 +23,15 @@ def _relerr(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("with_force_term", [False, True])
-def test_param_grad_fp64_matches_oracle(orc, hp, with_force_term):
+@pytest.mark.parametrize("with_force_term,chunk", [(False, 0), (True, 0), (True, 16)])
+def test_param_grad_fp64_matches_oracle(orc, hp, with_force_term, chunk):
     torch = torch_cuda()
     b = synth.random_batch(31, [7, 12, 9])
     M = 2
     w = synth.xavier_weights(M, hp["widths"], seed=41)
     h = make_handle(hp, w, M, "fp64", b)
+    if chunk:
+        h.set_knob("atom_chunk", chunk)
     x, sp, off = to_device(torch, b, torch.float64)
     gE, gF = _cotangents(1, b.n_mols, b.n_atoms)
     if not with_force_term:
