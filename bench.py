@@ -188,6 +188,61 @@ def coupling_form(torch, nnp, synth, args):
     return res
 
 
+def overlap_form(torch, nnp, synth, hp, w, M, reps=200, n_probe=1024):
+    """The ligand's NNP/MM force step (V_NNP graph + coupling, FP32) alone,
+    an MM stand-in alone (Coulomb terms of n_probe MM atoms with the rest of
+    the environment), both on one stream, and both on two streams joined every
+    step; overlap = (t_step + t_mm - t_concurrent) / min(t_step, t_mm)."""
+    from paper_2201_08110_amd.nnpmm import NNPMMStep
+    s = synth.coupling_system()
+    lig = synth.config_batch(2)
+    f32 = torch.float32
+    dev = lambda a, dt=f32: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    x_nnp, x_mm, p_nnp, p_mm = dev(s.x_nnp), dev(s.x_mm), dev(s.par_nnp), dev(s.par_mm)
+    sp, off = dev(lig.species, torch.int32), dev(lig.mol_offsets, torch.int32)
+    model = nnp.NNP(hp, w, M, "fp32", max_atoms=len(s.x_nnp), max_mols=1, max_atoms_per_mol=len(s.x_nnp))
+    coup = nnp.Coupling(len(s.x_nnp), len(s.x_mm), synth.COULOMB_K, 0.0, "fp32")
+    probe = nnp.Coupling(n_probe, len(s.x_mm) - n_probe, synth.COULOMB_K, 0.0, "fp32")
+    step = NNPMMStep(model, coup, sp, off, p_nnp, p_mm)
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    Fn, Fm = torch.empty_like(x_nnp), torch.zeros_like(x_mm)
+    Ep = torch.zeros(1, dtype=torch.float64, device="cuda")
+    pq = s.par_mm[:n_probe].copy()
+    pq[:, 2] = 0.0   # no LJ between the unscreened MM stand-in atoms
+    xp, pp, xe, pe = dev(s.x_mm[:n_probe]), dev(pq), dev(s.x_mm[n_probe:]), dev(s.par_mm[n_probe:])
+    Fpn, Fpm = torch.zeros((n_probe, 3), dtype=f32, device="cuda"), torch.zeros_like(xe)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ev = [torch.cuda.Event() for _ in range(2)]
+
+    def run(mode):
+        for i in range(reps):
+            if mode == "conc":
+                # both start when the previous step has joined; a waits for b
+                ev[0].record(sa)
+                sb.wait_event(ev[0])
+            if mode in ("step", "seq", "conc"):
+                step(x_nnp, x_mm, E, Fn, Fm, sa)
+            if mode in ("mm", "seq"):
+                probe(xp, pp, xe, pe, out=(Ep, Fpn, Fpm), stream=sa)
+            if mode == "conc":
+                probe(xp, pp, xe, pe, out=(Ep, Fpn, Fpm), stream=sb)
+                ev[1].record(sb)
+                sa.wait_event(ev[1])
+
+    res = {"workload": f"{len(s.x_nnp)}-atom ligand NNP/MM force step (8-model FP32 NNP graph + coupling "
+                       f"with {len(s.x_mm)} MM atoms) || MM stand-in ({n_probe} x {len(s.x_mm) - n_probe} Coulomb terms)"}
+    for mode in ("step", "mm", "seq", "conc"):
+        run(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(mode)
+        torch.cuda.synchronize()
+        res[f"us_{mode}"] = (time.perf_counter() - t0) / reps * 1e6
+    res["overlap"] = (res["us_step"] + res["us_mm"] - res["us_conc"]) / min(res["us_step"], res["us_mm"])
+    model.close(); coup.close(); probe.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +332,13 @@ def main():
                              "us_per_eval": sec2g * 1e6, "us_per_eval_eager": sec2 * 1e6,
                              "launch": "one captured HIP graph per evaluation"}
         h2.close()
+        h2 = nnp.NNP(hp, w, M, "bf16", max_atoms=b2.n_atoms, max_mols=1, max_atoms_per_mol=64)
+        sec2b, _, _, _, _ = run_form(torch, h2, b2, max(args.steps, 200), args.warmup,
+                                     timing=False, graph=True)
+        out["plain_bf16"] = {"workload": "single 64-atom ligand, 8-model ensemble, BF16 networks",
+                             "value": b2.n_atoms / sec2b, "unit": "atom-evals/s",
+                             "us_per_eval": sec2b * 1e6, "launch": "one captured HIP graph per evaluation"}
+        h2.close()
 
     # ---- like-for-like batched forms: both precisions on the replica batch
     # and on the ragged batch of 512 molecules (10-120 atoms) ---------------
@@ -315,6 +377,10 @@ def main():
                               "widths": [list(x) for x in hpv["species_widths"]]}
             hv.close()
         out["model_variants"] = variants
+
+    # ---- NNP/MM step overlapped with MM work on a second stream ----------
+    if not args.no_coupling:
+        out["nnpmm_overlap"] = [overlap_form(torch, nnp, synth, hp, w, M, n_probe=n) for n in (128, 1024)]
 
     # ---- NNP-MM coupling (Eq. 4): the 64-atom ligand in 47,648 MM atoms --
     if not args.no_coupling:

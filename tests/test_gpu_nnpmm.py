@@ -1,0 +1,108 @@
+"""The NNP-region force step of NNP/MM (Methods, Eq. 1): V_NNP of the ligand
+(Eq. 2-3) plus the coupling term (Eq. 4), against the sum of the two FP64
+oracles; and the same step run concurrently with an MM stand-in on a second
+stream against a sequential run.
+
+Bars (FP32): the NNP part |dE| <= 1e-4 kcal/mol per atom and force RMSE
+<= 1e-3 (as in the main parity tests), plus the coupling part's own bars
+(|dE| <= 5e-6 sum |V_ij|, |dF| <= 1e-4 max |F|).  Concurrent and sequential
+runs: energies equal exactly (fixed-order sums), forces to 1e-5 of max |F|
+(atomic adds of per-workgroup partial forces)."""
+import numpy as np
+import pytest
+
+from paper_2201_08110_amd import synth
+from tests.gpu_util import torch_cuda
+
+pytestmark = pytest.mark.gpu
+K = synth.COULOMB_K
+
+
+def _setup(torch, hp, n_probe=256):
+    from paper_2201_08110_amd.nnp import NNP, Coupling
+    from paper_2201_08110_amd.nnpmm import NNPMMStep
+    s = synth.coupling_system()
+    lig = synth.config_batch(2)
+    w = synth.xavier_weights(8, hp["widths"])
+    dev = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    f32 = torch.float32
+    t = dict(x_nnp=dev(s.x_nnp, f32), x_mm=dev(s.x_mm, f32), par_nnp=dev(s.par_nnp, f32),
+             par_mm=dev(s.par_mm, f32), sp=dev(lig.species, torch.int32),
+             off=dev(lig.mol_offsets, torch.int32))
+    model = NNP(hp, w, 8, "fp32", max_atoms=len(s.x_nnp), max_mols=1, max_atoms_per_mol=len(s.x_nnp))
+    coup = Coupling(len(s.x_nnp), len(s.x_mm), K, 0.0, "fp32")
+    step = NNPMMStep(model, coup, t["sp"], t["off"], t["par_nnp"], t["par_mm"])
+    # MM stand-in for the concurrent stream: Coulomb terms of n_probe MM
+    # atoms with the rest of the environment (the shape of an MM nonbonded
+    # kernel's work; no self pairs, no LJ between unscreened MM atoms)
+    probe = Coupling(n_probe, len(s.x_mm) - n_probe, K, 0.0, "fp32")
+    pp = s.par_mm[:n_probe].copy()
+    pp[:, 2] = 0.0
+    t.update(xp=dev(s.x_mm[:n_probe], f32), pp=dev(pp, f32), xe=dev(s.x_mm[n_probe:], f32),
+             pe=dev(s.par_mm[n_probe:], f32))
+    return s, lig, w, t, step, probe, n_probe
+
+
+def test_step_matches_oracles(orc, hp):
+    torch = torch_cuda()
+    s, lig, w, t, step, _, _ = _setup(torch, hp)
+    st = torch.cuda.Stream()
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    Fn = torch.empty_like(t["x_nnp"])
+    Fm = torch.zeros_like(t["x_mm"])
+    for _ in range(3):   # eager call that captures, then replays
+        with torch.cuda.stream(st):
+            Fm.zero_()
+        step(t["x_nnp"], t["x_mm"], E, Fn, Fm, st)
+    st.synchronize()
+    assert step.model.device_status() == 0
+    r = synth.round_to_fp32
+    xo = r(s.x_nnp)
+    En, Fnn = orc.energy_forces(hp, r(w), 8, lig.species, xo, lig.mol_offsets)
+    Ec, Fcn, Fcm, vabs = orc.coupling(xo, r(s.par_nnp), r(s.x_mm), r(s.par_mm), K, with_abs=True)
+    dE = abs(float(E.cpu()[0]) - (En[0] + Ec))
+    print("NNP/MM step: dE", dE, "E", float(E.cpu()[0]), En[0] + Ec)
+    assert dE <= 1e-4 * len(s.x_nnp) + 5e-6 * vabs
+    F = Fn.double().cpu().numpy()
+    Fo = Fnn + Fcn
+    rmse = np.sqrt(np.mean((F - Fo) ** 2))
+    assert rmse <= 1e-3 + 1e-4 * np.abs(Fcn).max()
+    np.testing.assert_allclose(Fm.double().cpu().numpy(), Fcm, rtol=0, atol=1e-4 * np.abs(Fcm).max())
+
+
+def test_concurrent_equals_sequential(hp):
+    torch = torch_cuda()
+    s, lig, w, t, step, probe, n_probe = _setup(torch, hp)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    Fn = torch.empty_like(t["x_nnp"])
+    Fm = torch.zeros_like(t["x_mm"])
+    Ep = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Fpn = torch.zeros((n_probe, 3), dtype=torch.float32, device="cuda")
+    Fpm = torch.zeros_like(t["xe"])
+    rng = np.random.default_rng(5)
+    for it in range(5):
+        x_new = torch.tensor(synth.round_to_fp32(s.x_nnp + rng.normal(0, 0.02, s.x_nnp.shape)),
+                             dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        # concurrent: NNP/MM step on stream a, MM stand-in on stream b
+        with torch.cuda.stream(sa):
+            t["x_nnp"].copy_(x_new)
+            Fm.zero_()
+        step(t["x_nnp"], t["x_mm"], E, Fn, Fm, sa)
+        probe(t["xp"], t["pp"], t["xe"], t["pe"], out=(Ep, Fpn, Fpm), stream=sb)
+        torch.cuda.synchronize()
+        Ec, Fc, Fmc = E.clone(), Fn.clone(), Fm.clone()
+        Epc = Ep.clone()
+        # sequential, both on stream a
+        with torch.cuda.stream(sa):
+            Fm.zero_()
+        step(t["x_nnp"], t["x_mm"], E, Fn, Fm, sa)
+        probe(t["xp"], t["pp"], t["xe"], t["pe"], out=(Ep, Fpn, Fpm), stream=sa)
+        torch.cuda.synchronize()
+        assert step.model.device_status() == 0
+        assert float(Ec.cpu()[0]) == float(E.cpu()[0]), it
+        assert np.isfinite(float(Ep.cpu()[0])) and float(Epc.cpu()[0]) == float(Ep.cpu()[0]), it
+        scale = float(Fn.abs().max())
+        np.testing.assert_allclose(Fc.cpu().numpy(), Fn.cpu().numpy(), rtol=0, atol=1e-5 * scale)
+        np.testing.assert_array_equal(Fmc.cpu().numpy(), Fm.cpu().numpy())
