@@ -253,6 +253,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 form")
     ap.add_argument("--no-forms", action="store_true", help="skip the like-for-like batched forms")
     ap.add_argument("--no-coupling", action="store_true", help="skip the NNP-MM coupling form")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="skip the NNP/MM step overlapped with an MM stand-in")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one elementwise copy (negation) of this many MiB (a "
                          "reference dispatch for HBM traffic counters)")
@@ -379,7 +381,7 @@ def main():
         out["model_variants"] = variants
 
     # ---- NNP/MM step overlapped with MM work on a second stream ----------
-    if not args.no_coupling:
+    if not args.no_coupling and not args.no_overlap:
         out["nnpmm_overlap"] = [overlap_form(torch, nnp, synth, hp, w, M, n_probe=n) for n in (128, 1024)]
 
     # ---- NNP-MM coupling (Eq. 4): the 64-atom ligand in 47,648 MM atoms --
