@@ -3,6 +3,8 @@
 Only the tests, the package smoke check and the benchmark's CPU-baseline leg
 may import this.  It wraps `nnp_oracle.c` (plain C, built with gcc by
 `build()`) through ctypes and shares no code with the HIP library.
+`oracle.hessian` writes the energy once more in plain torch FP64 operations
+for Hessian-vector products (coordinate gradients of force-dependent losses).
 """
 from __future__ import annotations
 
