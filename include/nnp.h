@@ -181,8 +181,12 @@ nnp_status nnp_aev(nnp_handle* h, const nnp_batch* b, const void* coords, void* 
  *   grad_params  device, float (double for FP64 handles), packed exactly like
  *                nnp_model_params.weights: dL/dW for every model and element
  *                (overwritten);
- *   grad_coords  device, coordinate type [n_atoms][3], dL/dx, or NULL.  Only
- *                available when grad_F is NULL (E_UNSUPPORTED otherwise).
+ *   grad_coords  device, coordinate type [n_atoms][3], dL/dx, or NULL:
+ *                -gE_b F_i - (H grad_F)_i with H the Hessian of the
+ *                molecule's energy in its coordinates (F = -dE/dx, Methods,
+ *                Eq. 3); the Hessian-vector product is formed exactly (the
+ *                AEV-row tangent through the networks, and the second
+ *                derivatives of the featuriser along grad_F).
  */
 nnp_status nnp_energy_forces_backward(nnp_handle* h, const nnp_batch* b, const void* coords,
                                       const double* grad_E, const void* grad_F,

@@ -35,10 +35,6 @@ class NNPFunction(torch.autograd.Function):
         need_x, need_w = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if gE is None and gF is None:
             return None, None, None, None, None
-        if need_x and gF is not None and bool(torch.any(gF != 0)):
-            raise NotImplementedError(
-                "coordinate gradients of force-dependent losses need the Hessian-vector "
-                "product of the potential, which this build does not provide")
         gE_ = gE.detach().to(torch.float64).contiguous() if gE is not None else None
         gF_ = gF.detach().to(coords.dtype).contiguous() if gF is not None else None
         gp, gx = model.backward(coords.detach().contiguous(), species, mol_offsets, gE_, gF_,

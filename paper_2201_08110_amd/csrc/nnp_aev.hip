@@ -1564,6 +1564,292 @@ hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
 }
 
 // ==========================================================================
+// Second-order term of a Hessian-vector product.  With F = -sum_i (dG_i/dx)^T g_i
+// (the force contraction above, g the dE/dAEV rows), the derivative of the
+// energy gradient along v has two parts: the rows' own change (handled by
+// running the force contraction on the rows' tangent) and the change of
+// dG/dx itself with g held fixed.  This kernel forms the second part as the
+// tangent of the force contraction along x + t v: every geometric quantity is
+// carried as a (value, tangent) pair; the work split is k_forces'.
+template <typename T> struct Du {
+    T v, t;
+};
+template <typename T> __device__ inline Du<T> du(T v, T t = T(0)) { return Du<T>{v, t}; }
+template <typename T> __device__ inline Du<T> operator+(Du<T> a, Du<T> b) { return {a.v + b.v, a.t + b.t}; }
+template <typename T> __device__ inline Du<T> operator-(Du<T> a, Du<T> b) { return {a.v - b.v, a.t - b.t}; }
+template <typename T> __device__ inline Du<T> operator-(Du<T> a) { return {-a.v, -a.t}; }
+template <typename T> __device__ inline Du<T> operator*(Du<T> a, Du<T> b) { return {a.v * b.v, a.t * b.v + a.v * b.t}; }
+template <typename T> __device__ inline Du<T> operator*(T s, Du<T> a) { return {s * a.v, s * a.t}; }
+template <typename T> __device__ inline Du<T> operator+(Du<T> a, T s) { return {a.v + s, a.t}; }
+template <typename T> __device__ inline Du<T> d_rcp(Du<T> a) {
+    const T r = m_rcp(a.v);
+    return {r, -a.t * r * r};
+}
+template <typename T> __device__ inline Du<T> d_sqrt(Du<T> a) {
+    const T q = m_sqrt(a.v);
+    return {q, T(0.5) * a.t * m_rcp(q)};
+}
+template <typename T> __device__ inline Du<T> d_exp(Du<T> a) {
+    const T e = m_exp(a.v);
+    return {e, e * a.t};
+}
+template <typename T> __device__ inline Du<T> d_powu(Du<T> a, T p) {
+    if (!(a.v > T(0))) return {T(0), T(0)};
+    const T y = m_powu(a.v, p);
+    return {y, p * y * m_rcp(a.v) * a.t};
+}
+// fc(r) = cos(pi r / Rc)/2 + 1/2 and its derivative, both as pairs
+template <typename T> __device__ inline void d_cutoff(Du<T> r, T pi_rc, Du<T>& fc, Du<T>& dfc) {
+    const T cs = m_cos(pi_rc * r.v), sn = m_sin(pi_rc * r.v);
+    fc = {T(0.5) * cs + T(0.5), -T(0.5) * pi_rc * sn * r.t};
+    dfc = {-T(0.5) * pi_rc * sn, -T(0.5) * pi_rc * pi_rc * cs * r.t};
+}
+
+constexpr int kNbStrideT = 16;   // values dx dy dz r fc_r dfc_r fc_a dfc_a, then their tangents
+
+template <typename P, int NZ>
+__global__ __launch_bounds__(256) void k_forces_tan(AevConst<typename P::T> c, int A, int max_apm,
+                                                    int chunk, int cap,
+                                                    const int32_t* __restrict__ mol_off,
+                                                    const int32_t* __restrict__ species,
+                                                    const typename P::T* __restrict__ x,
+                                                    const typename P::T* __restrict__ vdir,
+                                                    const uint16_t* __restrict__ nbr,
+                                                    const int32_t* __restrict__ nbr_cnt,
+                                                    const int32_t* __restrict__ row_of_atom,
+                                                    const typename P::TA* __restrict__ dG,
+                                                    typename P::T* __restrict__ Tout) {
+    typedef typename P::T T;
+    typedef typename P::TA TA;
+    typedef Du<T> D;
+    constexpr int NA = kNAZ / NZ;
+    extern __shared__ __align__(16) char smem[];
+    const int b = blockIdx.x;
+    const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
+    if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
+    const int i0 = blockIdx.y * chunk;
+    if (i0 >= n) return;
+    const int nc = min(chunk, n - i0);
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
+    const int S = c.S, RL = kNR * S, NB = S * (S + 1) / 2;
+    const int GL = RL + kBlkPad * NB;
+
+    LdsBump lb(smem);
+    ChunkStage<T> cs;
+    cs.take(lb, max_apm, cap);
+    T* sv = lb.take<T>(3 * (size_t)max_apm);   // the direction v of the molecule
+    T* sF = lb.take<T>(3 * (size_t)max_apm);
+    T* nb = lb.take<T>((size_t)nw * cap * kNbStrideT) + (size_t)wave * cap * kNbStrideT;
+    int* nsp = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
+    int* nid = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
+    T* g = lb.take<T>((size_t)nw * GL) + (size_t)wave * GL;
+
+    cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, row_of_atom);
+    for (int t = tid; t < 3 * n; t += blockDim.x) {
+        sv[t] = vdir[3 * (size_t)a0 + t];
+        sF[t] = T(0);
+    }
+    __syncthreads();
+    for (int ic = wave; ic < nc; ic += nw) {
+        const int il = i0 + ic;
+        const int cnt = cs.ccnt[ic];
+        const int nang = cnt & 0xffff, nall = cnt >> 16;
+        // the atom's dE/dAEV row, laid out as in k_forces
+        {
+            const TA* src = dG + (size_t)cs.crow[ic] * c.Dp;
+            for (int e = lane; e < c.D; e += 64) {
+                const int le = e < RL ? e : RL + kBlkPad * ((e - RL) / kNAZ) + (e - RL) % kNAZ;
+                g[le] = (T)src[e];
+            }
+        }
+        // neighbours with tangents: d_j = x_j - x_i moves along v_j - v_i
+        {
+            const T xi0 = cs.sx[3 * il], xi1 = cs.sx[3 * il + 1], xi2 = cs.sx[3 * il + 2];
+            const T vi0 = sv[3 * il], vi1 = sv[3 * il + 1], vi2 = sv[3 * il + 2];
+            for (int t = lane; t < nall; t += 64) {
+                const int j = cs.clst[(size_t)ic * cap + t];
+                const T d0 = cs.sx[3 * j] - xi0, d1 = cs.sx[3 * j + 1] - xi1, d2 = cs.sx[3 * j + 2] - xi2;
+                const T t0 = sv[3 * j] - vi0, t1 = sv[3 * j + 1] - vi1, t2 = sv[3 * j + 2] - vi2;
+                const D r = d_sqrt(D{d0 * d0 + d1 * d1 + d2 * d2, T(2) * (d0 * t0 + d1 * t1 + d2 * t2)});
+                D fcr, dfcr, fca = du(T(0)), dfca = du(T(0));
+                d_cutoff(r, c.pi_rcr, fcr, dfcr);
+                if (t < nang) d_cutoff(r, c.pi_rca, fca, dfca);
+                T* e = nb + kNbStrideT * t;
+                e[0] = d0; e[1] = d1; e[2] = d2; e[3] = r.v; e[4] = fcr.v; e[5] = dfcr.v; e[6] = fca.v; e[7] = dfca.v;
+                e[8] = t0; e[9] = t1; e[10] = t2; e[11] = r.t; e[12] = fcr.t; e[13] = dfcr.t; e[14] = fca.t; e[15] = dfca.t;
+                nsp[t] = cs.ssp[j];
+                nid[t] = j;
+            }
+        }
+        wave_sync();
+        T fi0 = 0, fi1 = 0, fi2 = 0;   // tangent force on the central atom, per lane
+        // radial: lane per (neighbour, group of 4 shifts)
+        for (int it = lane; it < ((4 * nall + 63) & ~63); it += 64) {
+            const bool act = it < 4 * nall;
+            const int t = act ? (it >> 2) : 0, q = it & 3;
+            D dEdr = du(T(0));
+            const T* e = nb + kNbStrideT * t;
+            if (act) {
+                const D r{e[3], e[11]}, fc{e[4], e[12]}, dfc{e[5], e[13]};
+                const T* gg = g + kNR * nsp[t] + 4 * q;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const D d = r + (-c.shf_r[4 * q + kk]);
+                    const D ex = c.radial_pref * d_exp(-c.eta_r * (d * d));
+                    dEdr = dEdr + gg[kk] * (ex * ((T(-2) * c.eta_r) * (d * fc) + dfc));
+                }
+            }
+            dEdr.v += __shfl_xor(dEdr.v, 1);
+            dEdr.t += __shfl_xor(dEdr.t, 1);
+            dEdr.v += __shfl_xor(dEdr.v, 2);
+            dEdr.t += __shfl_xor(dEdr.t, 2);
+            if (act && q == 0) {
+                const D inv = d_rcp(D{e[3], e[11]});
+                const D f0 = dEdr * (D{e[0], e[8]} * inv), f1 = dEdr * (D{e[1], e[9]} * inv),
+                        f2 = dEdr * (D{e[2], e[10]} * inv);
+                const int j = nid[t];
+                lds_add(&sF[3 * j + 0], -f0.t);
+                lds_add(&sF[3 * j + 1], -f1.t);
+                lds_add(&sF[3 * j + 2], -f2.t);
+                fi0 += f0.t;
+                fi1 += f1.t;
+                fi2 += f2.t;
+            }
+        }
+        // angular: lane per neighbour pair
+        const int npair = nang * (nang - 1) / 2;
+        for (int p = lane; p < npair; p += 64) {
+            int j, k;
+            decode_pair_rot(p, nang, j, k);
+            const T* ej = nb + kNbStrideT * j;
+            const T* ek = nb + kNbStrideT * k;
+            const D rj{ej[3], ej[11]}, rk{ek[3], ek[11]};
+            const D ij = d_rcp(rj), ik = d_rcp(rk);
+            const D uj0 = D{ej[0], ej[8]} * ij, uj1 = D{ej[1], ej[9]} * ij, uj2 = D{ej[2], ej[10]} * ij;
+            const D uk0 = D{ek[0], ek[8]} * ik, uk1 = D{ek[1], ek[9]} * ik, uk2 = D{ek[2], ek[10]} * ik;
+            D cs_ = uj0 * uk0 + uj1 * uk1 + uj2 * uk2;
+            if (cs_.v > T(1)) cs_ = du(T(1));
+            if (cs_.v < T(-1)) cs_ = du(T(-1));
+            const D cp = c.angle_scale * cs_;
+            const D sn = d_sqrt(D{T(1), T(0)} - cp * cp);
+            const D fcj{ej[6], ej[14]}, fck{ek[6], ek[14]}, dfcj{ej[7], ej[15]}, dfck{ek[7], ek[15]};
+            const D fcc = fcj * fck;
+            const D rm = T(0.5) * (rj + rk);
+            const T* gb = g + RL + kBlkPad * pair_index(nsp[j], nsp[k], S);
+            D fz[NZ], dfz[NZ];
+            const D isn = d_rcp(sn);
+#pragma unroll
+            for (int z = 0; z < NZ; ++z) {
+                const D cz = c.cos_z[z] * cp + c.sin_z[z] * sn;
+                const D hh = T(0.5) * (cz + T(1));
+                const D hp = d_powu(hh, c.zeta - T(1));
+                fz[z] = T(2) * (hp * hh);
+                const D dcz = c.angle_scale * (du(c.cos_z[z]) - c.sin_z[z] * (cp * isn));
+                dfz[z] = c.zeta * (hp * dcz);
+            }
+            D Dc = du(T(0)), Drj = du(T(0)), Drk = du(T(0));
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const D d = rm + (-c.shf_a[a]);
+                const D fa = d_exp(-c.eta_a * (d * d));
+                const D dfa_half = -c.eta_a * (d * fa);
+                D sg = du(T(0)), sgd = du(T(0));
+#pragma unroll
+                for (int z = 0; z < NZ; ++z) {
+                    const T gv = gb[NZ * a + z];
+                    sg = sg + gv * fz[z];
+                    sgd = sgd + gv * dfz[z];
+                }
+                Dc = Dc + sgd * (fa * fcc);
+                Drj = Drj + sg * (dfa_half * fcc + fa * (dfcj * fck));
+                Drk = Drk + sg * (dfa_half * fcc + fa * (fcj * dfck));
+            }
+            const D gj0 = Drj * uj0 + Dc * ((uk0 - cs_ * uj0) * ij);
+            const D gj1 = Drj * uj1 + Dc * ((uk1 - cs_ * uj1) * ij);
+            const D gj2 = Drj * uj2 + Dc * ((uk2 - cs_ * uj2) * ij);
+            const D gk0 = Drk * uk0 + Dc * ((uj0 - cs_ * uk0) * ik);
+            const D gk1 = Drk * uk1 + Dc * ((uj1 - cs_ * uk1) * ik);
+            const D gk2 = Drk * uk2 + Dc * ((uj2 - cs_ * uk2) * ik);
+            const int jj = nid[j], kk = nid[k];
+            lds_add(&sF[3 * jj + 0], -gj0.t);
+            lds_add(&sF[3 * jj + 1], -gj1.t);
+            lds_add(&sF[3 * jj + 2], -gj2.t);
+            lds_add(&sF[3 * kk + 0], -gk0.t);
+            lds_add(&sF[3 * kk + 1], -gk1.t);
+            lds_add(&sF[3 * kk + 2], -gk2.t);
+            fi0 += gj0.t + gk0.t;
+            fi1 += gj1.t + gk1.t;
+            fi2 += gj2.t + gk2.t;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            fi0 += __shfl_xor(fi0, off);
+            fi1 += __shfl_xor(fi1, off);
+            fi2 += __shfl_xor(fi2, off);
+        }
+        if (lane == 0) {
+            lds_add(&sF[3 * il + 0], fi0);
+            lds_add(&sF[3 * il + 1], fi1);
+            lds_add(&sF[3 * il + 2], fi2);
+        }
+        wave_sync();
+    }
+    __syncthreads();
+    for (int t = tid; t < 3 * n; t += blockDim.x) {
+        T val = sF[t];
+        if (val != T(0)) gbl_add(&Tout[3 * (size_t)a0 + t], val);
+    }
+}
+
+template <typename T>
+static size_t forces_tan_lds(int max_apm, int cap, int S, int nw) {
+    const int GL = kNR * S + kBlkPad * S * (S + 1) / 2;
+    return ChunkStage<T>::bytes(max_apm, cap) + 2 * lds_bytes<T>(3 * (size_t)max_apm) +
+           lds_bytes<T>((size_t)nw * cap * kNbStrideT) + 2 * lds_bytes<int>((size_t)nw * cap) +
+           lds_bytes<T>((size_t)nw * GL);
+}
+
+template <typename P>
+hipError_t launch_forces_tan(const Shape& sh, const AevConst<typename P::T>& c,
+                             const int32_t* mol_off, const int32_t* species, const typename P::T* x,
+                             const typename P::T* v, Work<P>& w, typename P::T* Tout, hipStream_t st,
+                             const Timer& tm) {
+    typedef typename P::T T;
+    dim3 grid(sh.B, (sh.max_apm + sh.chunk - 1) / sh.chunk);
+    int nw = kWaves;
+    size_t lds = forces_tan_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw);
+    while (lds > kMaxLds && nw > 1) lds = forces_tan_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw /= 2);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    auto kern = c.nZ == 4 ? k_forces_tan<P, 4> : k_forces_tan<P, 8>;
+    hipError_t e = ensure_lds((const void*)kern, lds);
+    if (e != hipSuccess) return e;
+    tm.b("forces_tan", st);
+    hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.chunk, sh.cap_nbr,
+                       mol_off, species, x, v, w.nbr, w.nbr_cnt, w.row_of_atom, w.dG, Tout);
+    tm.e("forces_tan", st);
+    return hipGetLastError();
+}
+
+// y -= x over n values
+template <typename T>
+__global__ __launch_bounds__(256) void k_sub(size_t n, const T* __restrict__ xv, T* __restrict__ y) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] -= xv[i];
+}
+template <typename T> hipError_t launch_sub(size_t n, const T* xv, T* y, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sub<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, xv, y);
+    return hipGetLastError();
+}
+template hipError_t launch_sub<float>(size_t, const float*, float*, hipStream_t);
+template hipError_t launch_sub<double>(size_t, const double*, double*, hipStream_t);
+template hipError_t launch_forces_tan<PrecF64>(const Shape&, const AevConst<double>&, const int32_t*,
+                                               const int32_t*, const double*, const double*,
+                                               Work<PrecF64>&, double*, hipStream_t, const Timer&);
+template hipError_t launch_forces_tan<PrecF32>(const Shape&, const AevConst<float>&, const int32_t*,
+                                               const int32_t*, const float*, const float*,
+                                               Work<PrecF32>&, float*, hipStream_t, const Timer&);
+
+// ==========================================================================
 // energies: one wave per molecule, FP64 sum of the atomic energies in a fixed
 // order.  e_atom = scale * ( mean_m (sum_t Epart + b4) ) + sae_scaled.
 template <typename P>

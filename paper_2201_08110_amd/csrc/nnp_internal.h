@@ -277,6 +277,15 @@ hipError_t launch_train_grads(const Shape& sh, const NetLayout& nl, Work<P>& w, 
                               typename P::TA* grad_params, hipStream_t st, const Timer& tm);
 template <typename P>
 hipError_t launch_fill(typename P::TS* p, size_t n, hipStream_t st);
+template <typename P>
+hipError_t launch_l1_bwd(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipStream_t st,
+                         const Timer& tm);
+template <typename P>
+hipError_t launch_forces_tan(const Shape& sh, const AevConst<typename P::T>& c,
+                             const int32_t* mol_off, const int32_t* species, const typename P::T* x,
+                             const typename P::T* v, Work<P>& w, typename P::T* Tout, hipStream_t st,
+                             const Timer& tm);
+template <typename T> hipError_t launch_sub(size_t n, const T* xv, T* y, hipStream_t st);
 template <typename TA>
 hipError_t launch_gather(int64_t n, const int32_t* map, const TA* src, TA* dst, hipStream_t st);
 template <typename P>

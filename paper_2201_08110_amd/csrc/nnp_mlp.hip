@@ -1093,6 +1093,20 @@ hipError_t launch_train_mlp_rev(const Shape& sh, const DevWeights<P>& wt, Work<P
     return hipErrorInvalidValue;
 }
 
+// dG = DZ1cat W1cat alone (the AEV-row adjoint of whatever DZ1 holds)
+template <typename P>
+hipError_t launch_l1_bwd(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipStream_t st,
+                         const Timer& tm) {
+    GemmArgs<P> base{};
+    base.tile_species = w.tile_species;
+    base.row_tile = sh.row_tile;
+    base.info = w.info;
+    base.n_models = sh.M;
+    if (sh.row_tile == 128) return mlp_l1_bwd<P, 128>(sh, wt, w, base, st, tm);
+    if (sh.row_tile == 16) return mlp_l1_bwd<P, 16>(sh, wt, w, base, st, tm);
+    return hipErrorInvalidValue;
+}
+
 template <typename P>
 hipError_t launch_mlp(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipStream_t st,
                       const Timer& tm) {
@@ -1106,7 +1120,9 @@ hipError_t launch_mlp(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipS
                                             TrainWork<P>&, const int32_t*, const double*, bool, \
                                             hipStream_t, const Timer&);                          \
     template hipError_t launch_train_mlp_rev<P>(const Shape&, const DevWeights<P>&, Work<P>&,   \
-                                                TrainWork<P>&, hipStream_t, const Timer&);
+                                                TrainWork<P>&, hipStream_t, const Timer&);       \
+    template hipError_t launch_l1_bwd<P>(const Shape&, const DevWeights<P>&, Work<P>&,         \
+                                         hipStream_t, const Timer&);
 NNP_TRAIN_INST(PrecF64)
 NNP_TRAIN_INST(PrecF32)
 

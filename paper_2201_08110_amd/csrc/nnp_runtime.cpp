@@ -514,13 +514,24 @@ nnp_status run_backward(nnp_handle* h, const nnp_batch* b, const typename P::T* 
     TrainWork<P>& tw = train_of<P>(h);
     const AevConst<T>& c = const_of<T>(h);
     Timer tm = make_timer(h);
-    if (gx) {
+    const bool has_gF = gF != nullptr;
+    if (gx && !has_gF) {
         // dL/dx of an energy-only loss: -gE_b F_i from one forward evaluation
         rc = run_forward<P>(h, b, x, h->train_E, (T*)h->train_F, nullptr);
         if (rc) return rc;
         HIP_TRY(launch_grad_coords<P>(sh.A, w.mol_of_atom, gE, (const T*)h->train_F, gx, st));
     }
-    const bool has_gF = gF != nullptr;
+    if (gx && has_gF) {
+        // dL/dx = -gE F - H gF.  With K(r) = -sum_i (dG_i/dx)^T r_i the force
+        // contraction of AEV-row cotangents r: H gF = -K(rows' tangent) -
+        // (tangent of K(g) along gF at fixed rows g).  Here gx starts as that
+        // second tangent, from the forward pass's rows g = dE/dG ...
+        rc = run_forward<P>(h, b, x, h->train_E, (T*)h->train_F, nullptr);
+        if (rc) return rc;
+        HIP_TRY(launch_fill<P>(gx, 3 * (size_t)sh.A, st));
+        if (sh.A > 0)
+            HIP_TRY(launch_forces_tan<P>(sh, c, b->mol_offsets, b->species, x, gF, w, gx, st, tm));
+    }
     HIP_TRY(launch_prep<P>(sh, b->mol_offsets, b->species, w, st, tm));
     if (sh.A > 0) {
         HIP_TRY(launch_neighbours<P>(sh, c, b->mol_offsets, b->species, x, (T*)nullptr, w, st, tm));
@@ -545,6 +556,16 @@ nnp_status run_backward(nnp_handle* h, const nnp_batch* b, const typename P::T* 
         HIP_TRY(launch_gather<TA>(h->n_params, h->dmap, (const TA*)h->gpad, gp, st));
     } else {
         HIP_TRY(launch_train_grads<P>(sh, h->nl, w, tw, w.mol_of_atom, gE, has_gF, gp, st, tm));
+    }
+    if (gx && has_gF && sh.A > 0) {
+        // ... and the reverse pass above left DZ1 = the layer-1 adjoint of
+        // (u/M)(gE e - edot): its AEV-row adjoint is gE g - gdot, and
+        // K(gE g - gdot) = gE F + sum_i (dG_i/dx)^T gdot, so
+        // gx = tangent - K(gE g - gdot) = -gE F - H gF.
+        HIP_TRY(launch_l1_bwd<P>(sh, weights_of<P>(h), w, st, tm));
+        HIP_TRY(launch_fill<P>((T*)h->train_F, 3 * (size_t)sh.A, st));
+        HIP_TRY(launch_forces<P>(sh, c, b->mol_offsets, b->species, x, w, (T*)h->train_F, st, tm));
+        HIP_TRY(launch_sub<T>(3 * (size_t)sh.A, (const T*)h->train_F, gx, st));
     }
     return NNP_OK;
 }
@@ -929,9 +950,6 @@ nnp_status nnp_energy_forces_backward(nnp_handle* h, const nnp_batch* b, const v
     if (rc) return rc;
     if (!grad_params || (b->n_atoms > 0 && !coords))
         return fail(NNP_E_INVALID, "null coords or grad_params");
-    if (grad_coords && grad_F)
-        return fail(NNP_E_UNSUPPORTED,
-                    "coordinate gradients of force-dependent losses are not implemented");
     if (h->precision == NNP_PREC_BF16_MLP)
         return fail(NNP_E_UNSUPPORTED, "the training backward runs on FP32 or FP64 handles");
     DeviceGuard dg(h->device);

@@ -137,15 +137,52 @@ def test_autograd_function_and_finite_differences(hp):
         assert gx[a, c] == pytest.approx(fd, rel=1e-5, abs=1e-6)
 
 
-def test_force_loss_coordinate_gradient_is_unsupported(hp):
+@pytest.mark.parametrize("prec,which", [("fp64", "ani2x"), ("fp64", "ani1x_elements"), ("fp32", "ani2x")])
+def test_force_loss_coordinate_gradient(hp, prec, which):
+    """dL/dx = -gE F - H gF against the FP64 Hessian-vector oracle (torch,
+    pinned to the C oracle and to differences of its forces).  FP64: 1e-9
+    relative in norm; FP32: 2e-4 (second derivatives of single-precision
+    featuriser terms)."""
+    torch = torch_cuda()
+    pytest.importorskip("torch")
+    from oracle import hessian
+    if which == "ani2x":
+        h_, ratio = hp, synth.LIGAND_RATIO
+        w = synth.xavier_weights(2, hp["widths"], seed=45)
+    else:
+        h_, ratio = synth.ani1x_hparams(), (30, 20, 5, 5)
+        w = synth.xavier_weights(2, h_["species_widths"], n_species=4, seed=45)
+    b = synth.random_batch(36, [9, 14, 1, 6], box_scale=1.9, ratio=ratio)
+    h = make_handle(h_, w, 2, prec, b)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    x, sp, off = to_device(torch, b, dt)
+    gE, gF = _cotangents(4, b.n_mols, b.n_atoms)
+    _, gx = h.backward(x, sp, off, torch.tensor(gE, dtype=torch.float64, device="cuda"),
+                       torch.tensor(gF, dtype=dt, device="cuda"), want_coords=True)
+    torch.cuda.synchronize()
+    assert h.device_status() == 0
+    xo, wo = oracle_inputs(b, w, prec)
+    gFo = gF if prec == "fp64" else synth.round_to_fp32(gF)
+    go = hessian.coord_grad(h_, wo, 2, b.species, xo, b.mol_offsets, gE, gFo)
+    err = _relerr(gx.double().cpu().numpy(), go)
+    print(prec, which, "force-loss dL/dx rel err", err)
+    assert err < (1e-9 if prec == "fp64" else 2e-4)
+
+
+def test_force_loss_autograd_double_backward(hp):
+    """Through the autograd Function: d/dx of a force loss equals the C ABI's
+    coordinate gradient (FP64)."""
     torch = torch_cuda()
     from paper_2201_08110_amd.autograd import nnp_energy_forces
-    b = synth.random_batch(36, [6])
-    w = synth.xavier_weights(1, hp["widths"], seed=45)
+    b = synth.random_batch(37, [7, 5])
+    w = synth.xavier_weights(1, hp["widths"], seed=46)
     h = make_handle(hp, w, 1, "fp64", b)
     x, sp, off = to_device(torch, b, torch.float64)
     xg = x.clone().requires_grad_(True)
     params = torch.tensor(w, dtype=torch.float64)
-    _, F = nnp_energy_forces(h, xg, params, sp, off)
-    with pytest.raises(NotImplementedError):
-        (F ** 2).sum().backward()
+    E, F = nnp_energy_forces(h, xg, params, sp, off)
+    ((F ** 2).sum() + 0.3 * E.sum()).backward()
+    gE = torch.full((b.n_mols,), 0.3, dtype=torch.float64, device="cuda")
+    _, gx = h.backward(x, sp, off, gE, 2 * F.detach(), want_coords=True)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(xg.grad.cpu().numpy(), gx.cpu().numpy(), rtol=1e-12, atol=1e-12)
