@@ -243,6 +243,43 @@ def overlap_form(torch, nnp, synth, hp, w, M, reps=200, n_probe=1024):
     return res
 
 
+def training_form(torch, nnp, synth, hp, w, M, reps=20):
+    """Workload 4 (64 molecules of 30-80 atoms, 8 models, FP32): one training
+    step = energies and forces, then dL/dW of a loss of both (force term
+    included); and the same with dL/dx (the Hessian-vector product)."""
+    b = synth.config_batch(4)
+    h = nnp.NNP(hp, w, M, "fp32", max_atoms=b.n_atoms, max_mols=b.n_mols, max_atoms_per_mol=80)
+    x = torch.tensor(b.coords, dtype=torch.float32, device="cuda")
+    sp = torch.tensor(b.species, dtype=torch.int32, device="cuda")
+    off = torch.tensor(b.mol_offsets, dtype=torch.int32, device="cuda")
+    rng = np.random.default_rng(4)
+    gE = torch.tensor(rng.normal(size=b.n_mols) * 1e-2, dtype=torch.float64, device="cuda")
+    gF = torch.tensor(rng.normal(size=(b.n_atoms, 3)) * 1e-2, dtype=torch.float32, device="cuda")
+    res = {"workload": f"{b.n_mols} molecules of 30-80 atoms ({b.n_atoms} atoms), 8-model ensemble, FP32",
+           "atoms": int(b.n_atoms)}
+    for name, want_x in (("param_grad", False), ("param_and_coord_grad", True)):
+        def step():
+            h.energy_forces(x, sp, off)
+            h.backward(x, sp, off, gE, gF, want_coords=want_x)
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        res[f"ms_per_step_{name}"] = (time.perf_counter() - t0) / reps * 1e3
+    h.set_timing(True)
+    for _ in range(5):
+        h.energy_forces(x, sp, off)
+        h.backward(x, sp, off, gE, gF, want_coords=True)
+    torch.cuda.synchronize()
+    res["kernels_us"] = {k: 1e3 * ms / c for k, (c, ms) in h.kernel_times().items()}
+    h.set_timing(False)
+    h.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +416,10 @@ def main():
                               "widths": [list(x) for x in hpv["species_widths"]]}
             hv.close()
         out["model_variants"] = variants
+
+    # ---- training step (workload 4) ---------------------------------------
+    if not args.no_forms:
+        out["training"] = training_form(torch, nnp, synth, hp, w, M)
 
     # ---- NNP/MM step overlapped with MM work on a second stream ----------
     if not args.no_coupling and not args.no_overlap:
