@@ -4,10 +4,10 @@ hand-written backward that returns parameter gradients.
     E, F = nnp_energy_forces(model, coords, params, species, mol_offsets)
 
 E [B] (float64) and F [A, 3] (coordinate dtype) are differentiable with
-respect to `params` (the packed FP64 master weights, any device) for any loss
-of E and F, and with respect to `coords` for losses that depend on E only
-(F = -dE/dx, Methods, Eq. 3; the coordinate gradient of a force-dependent
-loss would need the Hessian and raises).  All arithmetic runs in the HIP
+respect to `params` (the packed FP64 master weights, any device) and to
+`coords` for any loss of E and F (F = -dE/dx, Methods, Eq. 3: a loss of the
+forces reaches the coordinates through the energy Hessian, whose products
+with dL/dF the library forms exactly).  All arithmetic runs in the HIP
 library; this module only moves tensors across the ABI.
 """
 from __future__ import annotations
