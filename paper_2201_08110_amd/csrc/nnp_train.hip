@@ -101,8 +101,13 @@ template <> struct MFW<double> {
 };
 
 constexpr int kWT = 64;   // output tile (n and k)
-constexpr int kWR = 16;   // rows per LDS slice
+constexpr int kWR = 16;   // rows per LDS slice (divides every row tile)
 
+// One workgroup: a 64 x 64 tile of one (element, model) weight gradient,
+// 2 x 2 waves of 32 x 32 (many workgroups: the reduction over a bucket's rows
+// is serial in each).  The next 16-row slice of both operands is loaded into
+// registers (16-byte vectors) while the MFMAs consume the current one from
+// LDS.  Columns past an operand's valid width read as zero.
 template <typename P>
 __global__ __launch_bounds__(256) void k_wgrad(int S, int M, const BucketInfo* __restrict__ info,
                                                const typename P::TS* __restrict__ X1,
@@ -115,9 +120,13 @@ __global__ __launch_bounds__(256) void k_wgrad(int S, int M, const BucketInfo* _
     typedef typename P::TS TS;
     typedef typename P::TA TA;
     typedef MFW<TS> mf;
-    constexpr int LD = kWT + 4;
-    __shared__ TS Xs[kWR][LD];
-    __shared__ TS Ys[kWR][LD];
+    constexpr int VEC = 16 / (int)sizeof(TS);            // elements per 16-byte load
+    constexpr int LD = kWT + VEC;                        // padded LDS row
+    constexpr int NV = kWR * kWT / VEC / 256;            // vector loads per thread and operand
+    constexpr int FM = kWT / 32, FN = kWT / 32;          // 16 x 16 MFMA tiles per wave
+    typedef typename std::conditional<sizeof(TS) == 8, double2, float4>::type TV;
+    __shared__ __align__(16) TS Xs[kWR][LD];
+    __shared__ __align__(16) TS Ys[kWR][LD];
     const int tile = blockIdx.x, sm = blockIdx.y;
     const int s = sm % S, m = sm / S;
     const int tn = tile % ntn, tk = tile / ntn;
@@ -125,51 +134,69 @@ __global__ __launch_bounds__(256) void k_wgrad(int S, int M, const BucketInfo* _
     if (n0 >= out_o || k0 >= in_o) return;
     const int r0 = info->off[s], r1 = info->off[s + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;   // 2 x 2 waves of 32 x 32
-    typename mf::Acc acc[2][2];
+    const int wm = wave >> 1, wn = wave & 1;
+    const int xv = xw, yv = yw ? yw : ldy;               // valid columns of each operand block
+    typename mf::Acc acc[FM][FN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[i][j][q] = 0;
     const int xo = m * xw + n0, yo = m * yw + k0;
+    TV xr[NV], yr[NV];
+    auto gload = [&](const TS* X, const TS* Y, int r) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int e = tid + 256 * v, rr = e / (kWT / VEC), col = (e % (kWT / VEC)) * VEC;
+            TV zx, zy;
+            zx = zy = TV{};
+            xr[v] = n0 + col < xv ? *(const TV*)(X + (size_t)(r + rr) * ldx + xo + col) : zx;
+            yr[v] = k0 + col < yv ? *(const TV*)(Y + (size_t)(r + rr) * ldy + yo + col) : zy;
+        }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int e = tid + 256 * v, rr = e / (kWT / VEC), col = (e % (kWT / VEC)) * VEC;
+            *(TV*)&Xs[rr][col] = xr[v];
+            *(TV*)&Ys[rr][col] = yr[v];
+        }
+    };
     for (int pass = 0; pass < 2; ++pass) {
         const TS* X = pass ? X2 : X1;
         const TS* Y = pass ? Y2 : Y1;
-        if (!X || !Y) continue;
+        if (!X || !Y || r0 >= r1) continue;
+        gload(X, Y, r0);
         for (int r = r0; r < r1; r += kWR) {
-            for (int e = tid; e < kWR * kWT; e += 256) {
-                const int rr = e / kWT, cc = e % kWT;
-                Xs[rr][cc] = X[(size_t)(r + rr) * ldx + xo + cc];
-                Ys[rr][cc] = Y[(size_t)(r + rr) * ldy + yo + cc];
-            }
+            lstore();
             __syncthreads();
+            if (r + kWR < r1) gload(X, Y, r + kWR);
 #pragma unroll
             for (int kk = 0; kk < kWR; kk += 4) {
                 const int kr = kk + (lane >> 4);
-                TS a[2], b[2];
+                TS a[FM], b[FN];
 #pragma unroll
-                for (int i = 0; i < 2; ++i) a[i] = Xs[kr][wm * 32 + i * 16 + (lane & 15)];
+                for (int i = 0; i < FM; ++i) a[i] = Xs[kr][wm * (kWT / 2) + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) b[j] = Ys[kr][wn * 32 + j * 16 + (lane & 15)];
+                for (int j = 0; j < FN; ++j) b[j] = Ys[kr][wn * (kWT / 2) + j * 16 + (lane & 15)];
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) acc[i][j] = mf::mma(a[i], b[j], acc[i][j]);
+                    for (int j = 0; j < FN; ++j) acc[i][j] = mf::mma(a[i], b[j], acc[i][j]);
             }
             __syncthreads();
         }
     }
     TA* out = gparam + ((long)m * S + s) * net + offW;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int n = n0 + wm * 32 + i * 16 + mf::row(lane, q);
-                const int k = k0 + wn * 32 + j * 16 + (lane & 15);
+                const int n = n0 + wm * (kWT / 2) + i * 16 + mf::row(lane, q);
+                const int k = k0 + wn * (kWT / 2) + j * 16 + (lane & 15);
                 if (n < out_o && k < in_o) out[(long)n * in_o + k] = (TA)acc[i][j][q];
             }
 }
