@@ -1059,10 +1059,14 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
                 }
             }
             wave_sync();
-            // blocks meeting this batch; lanes q and q + 32 take alternate pairs
-            for (int bl = 0; bl < NB; ++bl) {
+            // blocks meeting this batch (one ballot over the block list, then
+            // only those); lanes q and q + 32 take alternate pairs
+            const unsigned long long live =
+                __ballot(lane < NB && al.bst[lane] < al.bst[lane + 1] && al.bst[lane] < p0 + nbat &&
+                         al.bst[lane + 1] > p0);
+            for (unsigned long long mset = live; mset; mset &= mset - 1) {
+                const int bl = __builtin_ctzll(mset);
                 const int s0 = max(al.bst[bl], p0), e0 = min(al.bst[bl + 1], p0 + nbat);
-                if (s0 >= e0) continue;
                 // two accumulators, four pairs' factors in flight
                 T acc = T(0), acc1 = T(0);
                 int p = s0 + h;
