@@ -18,19 +18,19 @@ pytestmark = pytest.mark.gpu
 K = synth.COULOMB_K
 
 
-def _setup(torch, hp, n_probe=256):
+def _setup(torch, hp, n_probe=256, prec="fp32"):
     from paper_2201_08110_amd.nnp import NNP, Coupling
     from paper_2201_08110_amd.nnpmm import NNPMMStep
     s = synth.coupling_system()
     lig = synth.config_batch(2)
     w = synth.xavier_weights(8, hp["widths"])
     dev = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
-    f32 = torch.float32
+    f32 = torch.float32 if prec == "fp32" else torch.float64
     t = dict(x_nnp=dev(s.x_nnp, f32), x_mm=dev(s.x_mm, f32), par_nnp=dev(s.par_nnp, f32),
              par_mm=dev(s.par_mm, f32), sp=dev(lig.species, torch.int32),
              off=dev(lig.mol_offsets, torch.int32))
-    model = NNP(hp, w, 8, "fp32", max_atoms=len(s.x_nnp), max_mols=1, max_atoms_per_mol=len(s.x_nnp))
-    coup = Coupling(len(s.x_nnp), len(s.x_mm), K, 0.0, "fp32")
+    model = NNP(hp, w, 8, prec, max_atoms=len(s.x_nnp), max_mols=1, max_atoms_per_mol=len(s.x_nnp))
+    coup = Coupling(len(s.x_nnp), len(s.x_mm), K, 0.0, prec)
     step = NNPMMStep(model, coup, t["sp"], t["off"], t["par_nnp"], t["par_mm"])
     # MM stand-in for the concurrent stream: Coulomb terms of n_probe MM
     # atoms with the rest of the environment (the shape of an MM nonbonded
@@ -43,9 +43,10 @@ def _setup(torch, hp, n_probe=256):
     return s, lig, w, t, step, probe, n_probe
 
 
-def test_step_matches_oracles(orc, hp):
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_step_matches_oracles(orc, hp, prec):
     torch = torch_cuda()
-    s, lig, w, t, step, _, _ = _setup(torch, hp)
+    s, lig, w, t, step, _, _ = _setup(torch, hp, prec=prec)
     st = torch.cuda.Stream()
     E = torch.empty(1, dtype=torch.float64, device="cuda")
     Fn = torch.empty_like(t["x_nnp"])
@@ -56,15 +57,20 @@ def test_step_matches_oracles(orc, hp):
         step(t["x_nnp"], t["x_mm"], E, Fn, Fm, st)
     st.synchronize()
     assert step.model.device_status() == 0
-    r = synth.round_to_fp32
+    r = synth.round_to_fp32 if prec == "fp32" else (lambda a: np.asarray(a, dtype=np.float64))
     xo = r(s.x_nnp)
     En, Fnn = orc.energy_forces(hp, r(w), 8, lig.species, xo, lig.mol_offsets)
     Ec, Fcn, Fcm, vabs = orc.coupling(xo, r(s.par_nnp), r(s.x_mm), r(s.par_mm), K, with_abs=True)
     dE = abs(float(E.cpu()[0]) - (En[0] + Ec))
-    print("NNP/MM step: dE", dE, "E", float(E.cpu()[0]), En[0] + Ec)
-    assert dE <= 1e-4 * len(s.x_nnp) + 5e-6 * vabs
+    print("NNP/MM step", prec, ": dE", dE, "E", float(E.cpu()[0]), En[0] + Ec)
     F = Fn.double().cpu().numpy()
     Fo = Fnn + Fcn
+    if prec == "fp64":
+        assert dE <= 1e-10 * (abs(En[0]) + vabs)
+        np.testing.assert_allclose(F, Fo, rtol=0, atol=1e-9 * np.abs(Fo).max())
+        np.testing.assert_allclose(Fm.cpu().numpy(), Fcm, rtol=0, atol=1e-10 * np.abs(Fcm).max())
+        return
+    assert dE <= 1e-4 * len(s.x_nnp) + 5e-6 * vabs
     rmse = np.sqrt(np.mean((F - Fo) ** 2))
     assert rmse <= 1e-3 + 1e-4 * np.abs(Fcn).max()
     np.testing.assert_allclose(Fm.double().cpu().numpy(), Fcm, rtol=0, atol=1e-4 * np.abs(Fcm).max())

@@ -137,8 +137,10 @@ def test_autograd_function_and_finite_differences(hp):
         assert gx[a, c] == pytest.approx(fd, rel=1e-5, abs=1e-6)
 
 
-@pytest.mark.parametrize("prec,which", [("fp64", "ani2x"), ("fp64", "ani1x_elements"), ("fp32", "ani2x")])
-def test_force_loss_coordinate_gradient(hp, prec, which):
+@pytest.mark.parametrize("prec,which,knobs", [
+    ("fp64", "ani2x", {}), ("fp64", "ani1x_elements", {}), ("fp32", "ani2x", {}),
+    ("fp64", "ani2x", {"cell_min": 16, "atom_chunk": 16})])
+def test_force_loss_coordinate_gradient(hp, prec, which, knobs):
     """dL/dx = -gE F - H gF against the FP64 Hessian-vector oracle (torch,
     pinned to the C oracle and to differences of its forces).  FP64: 1e-9
     relative in norm; FP32: 2e-4 (second derivatives of single-precision
@@ -154,6 +156,8 @@ def test_force_loss_coordinate_gradient(hp, prec, which):
         w = synth.xavier_weights(2, h_["species_widths"], n_species=4, seed=45)
     b = synth.random_batch(36, [9, 14, 1, 6], box_scale=1.9, ratio=ratio)
     h = make_handle(h_, w, 2, prec, b)
+    for k, v in knobs.items():   # cutoff-cell neighbour lists above 16 atoms, 16-atom chunks
+        h.set_knob(k, v)
     dt = torch.float64 if prec == "fp64" else torch.float32
     x, sp, off = to_device(torch, b, dt)
     gE, gF = _cotangents(4, b.n_mols, b.n_atoms)
