@@ -396,7 +396,7 @@ __device__ inline T wave_max(T v) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, int cell_min, int skip_small, int cap,
+__global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, int cell_min, int cap,
                                                    T rcr, T rca2,
                                                    T rcr2, const int32_t* __restrict__ mol_off,
                                                    const int32_t* __restrict__ species,
@@ -408,30 +408,23 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
     const int b = blockIdx.x;
     const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
     if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
-    if (skip_small && n <= cell_min) return;   // listed by k_nbr_pairs
+    if (n <= cell_min) return;   // listed by k_nbr_pairs
     const int i0 = blockIdx.y * kNbrChunk;
     if (i0 >= n) return;
     const int lane = lane_id();
-    const bool cells = n > cell_min;   // larger molecules use cutoff cells
     LdsBump lb(smem);
     T* sx = lb.take<T>(4 * (size_t)max_apm);            // staged atoms: x y z
     int* sid = lb.take<int>(max_apm);                   // local index of the k-th staged atom
     uint16_t* lst = lb.take<uint16_t>((size_t)kNbrChunk * cap);
     T* tx = lb.take<T>(3 * (size_t)max_apm);            // the molecule's x y z, input order
     int* tsp = lb.take<int>(max_apm);                   // and elements
-    int* kstart = nullptr;                              // [nkeys+1] bucket starts (cells)
-    int* kcur = nullptr;                                // [nkeys]   scatter cursors
-    int* akey = nullptr;                                // [max_apm] key of every atom
-    if (max_apm > cell_min) {
-        kstart = lb.take<int>(kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim + 1);
-        kcur = lb.take<int>(kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim);
-        akey = lb.take<int>(max_apm);
-    }
-    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    constexpr int kKeys = kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim;
+    int* kstart = lb.take<int>(kKeys + 1);             // bucket starts
+    int* kcur = lb.take<int>(kKeys);                   // scatter cursors
+    int* akey = lb.take<int>(max_apm);                 // key of every atom
 
-    // ---- staging.  Small molecules: atoms in element order (one bucket per
-    // element).  Large molecules: atoms in (element, cell) order over a grid
-    // of cutoff cells with edge >= rcr, so a central atom scans <= 27 cells.
+    // ---- staging: atoms in (element, cell) order over a grid of cutoff
+    // cells with edge >= rcr, so a central atom scans <= 27 cells
     int nc0 = 1, nc1 = 1, nc2 = 1;
     T lo0 = 0, lo1 = 0, lo2 = 0, ih0 = 0, ih1 = 0, ih2 = 0;
     // one coalesced pass over the molecule's inputs: every later pass reads LDS
@@ -441,24 +434,7 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
         tsp[j] = (s < 0 || s >= S) ? 0 : s;
     }
     wave_sync();
-    if (!cells) {
-        int base = 0;
-        for (int q = 0; q < S; ++q) {
-            for (int j0 = 0; j0 < n; j0 += 64) {
-                const int j = j0 + lane;
-                const int s = j < n ? tsp[j] : -1;
-                const unsigned long long m = __ballot(s == q);
-                if (s == q) {
-                    const int pos = base + __popcll(m & lt);
-                    sid[pos] = j;
-                    sx[4 * pos + 0] = tx[3 * j + 0];
-                    sx[4 * pos + 1] = tx[3 * j + 1];
-                    sx[4 * pos + 2] = tx[3 * j + 2];
-                }
-                base += __popcll(m);
-            }
-        }
-    } else {
+    {
         T mn0 = T(1e30), mn1 = T(1e30), mn2 = T(1e30), mx0 = T(-1e30), mx1 = T(-1e30), mx2 = T(-1e30);
         for (int j = lane; j < n; j += 64) {
             const T* p = tx + 3 * j;
@@ -543,35 +519,7 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
             ++cnt;                                                                             \
         }                                                                                      \
     }
-    if (!cells) {
-        // eight candidates' loads in flight before their tests (the tests
-        // only append to this lane's list)
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int k0 = 0; k0 < n; k0 += 8) {
-                int id[8];
-                T c0[8], c1[8], c2[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int k = min(k0 + u, n - 1);
-                    id[u] = sid[k];
-                    c0[u] = sx[4 * k];
-                    c1[u] = sx[4 * k + 1];
-                    c2[u] = sx[4 * k + 2];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const T d0 = c0[u] - xi0, d1 = c1[u] - xi1, d2 = c2[u] - xi2;
-                    const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                    if (act && k0 + u < n && id[u] != il &&
-                        (pass == 0 ? (r2 < rca2) : (r2 >= rca2 && r2 < rcr2))) {
-                        if (cnt < cap) my[cnt] = (uint16_t)id[u];
-                        ++cnt;
-                    }
-                }
-            }
-            if (pass == 0) nang = cnt;
-        }
-    } else {
+    {
         const int ncell = nc0 * nc1 * nc2;
         const int c0 = act ? min((int)((xi0 - lo0) * ih0), nc0 - 1) : 0;
         const int c1 = act ? min((int)((xi1 - lo1) * ih1), nc1 - 1) : 0;
@@ -718,17 +666,16 @@ hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
     // larger molecules: cutoff cells, one lane per central atom
     dim3 grid(sh.B, (sh.max_apm + kNbrChunk - 1) / kNbrChunk);
     const int nkeys = kMaxSpecies * kMaxCellsPerDim * kMaxCellsPerDim * kMaxCellsPerDim;
-    size_t lds = lds_bytes<T>(4 * (size_t)sh.max_apm) + lds_bytes<int>(sh.max_apm) +
-                 lds_bytes<uint16_t>((size_t)kNbrChunk * sh.cap_nbr) +
-                 lds_bytes<T>(3 * (size_t)sh.max_apm) + lds_bytes<int>(sh.max_apm);
-    if (sh.max_apm > sh.cell_min)
-        lds += lds_bytes<int>(nkeys + 1) + lds_bytes<int>(nkeys) + lds_bytes<int>(sh.max_apm);
+    const size_t lds = lds_bytes<T>(4 * (size_t)sh.max_apm) + lds_bytes<int>(sh.max_apm) +
+                       lds_bytes<uint16_t>((size_t)kNbrChunk * sh.cap_nbr) +
+                       lds_bytes<T>(3 * (size_t)sh.max_apm) + lds_bytes<int>(sh.max_apm) +
+                       lds_bytes<int>(nkeys + 1) + lds_bytes<int>(nkeys) + lds_bytes<int>(sh.max_apm);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     hipError_t e = ensure_lds((const void*)k_neighbours<T>, lds);
     if (e != hipSuccess) return e;
     tm.b("neighbours", st);
     hipLaunchKernelGGL(k_neighbours<T>, grid, dim3(64), lds, st, sh.A, sh.S, sh.max_apm,
-                       sh.cell_min, 1, sh.cap_nbr, c.rcr, c.rca2, c.rcr2, mol_off, species, x, F, w.nbr,
+                       sh.cell_min, sh.cap_nbr, c.rcr, c.rca2, c.rcr2, mol_off, species, x, F, w.nbr,
                        w.nbr_cnt, w.flag);
     tm.e("neighbours", st);
     return hipGetLastError();
