@@ -189,7 +189,7 @@ struct Shape {
     // kernel variants in effect (resolved tunable knobs)
     int mlp_fused;                     // 1: fused layers 2-3 kernel, 0: per-layer GEMMs
     int gemm_stages;                   // LDS stages of the layer-1 GEMMs (2 or 3)
-    int gemm_waves;                    // waves per workgroup of the layer-1 GEMMs (4 or 8)
+    int gemm_waves;                    // waves per workgroup of the layer-1 forward GEMM (4 or 8)
     int cell_min;                      // molecules above this many atoms use cutoff cells
     int tail_tile;                     // fused kernel tile variant (1, 2 or 3)
     int chunk;                         // central atoms per featuriser / force workgroup (4, 8, 16)

@@ -845,7 +845,9 @@ static hipError_t run_l1(GemmArgs<P> a, const Shape& sh, int N, hipStream_t st, 
                          const char* name) {
     typedef Cfg<P, BM> C;
     const int R = sh.Rcap;
-    if constexpr (BM == 128 && C::BNW == 128) {
+    // 8 waves (2 x 4 of 64 x 32) for the forward GEMM when the knob says so;
+    // the backward GEMM measured better on 4
+    if constexpr (BM == 128 && C::BNW == 128 && EPI == EPI_CELU) {
         if (sh.gemm_waves == 8)
             return sh.gemm_stages == 2 ? run_gemm<P, BM, C::BNW, 2, 4, 2, EPI>(a, R, N, 1, st, tm, name)
                                        : run_gemm<P, BM, C::BNW, 2, 4, 3, EPI>(a, R, N, 1, st, tm, name);

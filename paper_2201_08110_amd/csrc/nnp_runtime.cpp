@@ -371,7 +371,7 @@ int32_t knob_value(const nnp_handle* h, int k) {
     case NNP_KNOB_GEMM_STAGES: return v ? v : 2;
     case NNP_KNOB_CELL_MIN: return v ? v : 128;
     case NNP_KNOB_TAIL_TILE: return v ? v : 1;
-    case NNP_KNOB_GEMM_WAVES: return v ? v : 4;
+    case NNP_KNOB_GEMM_WAVES: return v ? v : 8;
     case NNP_KNOB_ATOM_CHUNK:
         if (v) return v;
         return (int64_t)h->max_mols * ((h->max_apm + 15) / 16) >= 1024 ? 16 : 4;
