@@ -165,21 +165,39 @@ __global__ __launch_bounds__(256) void k_bucket_scan(int nblk, int S, int row_ti
     __shared__ int base[kMaxSpecies + 1];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (nblk + nt - 1) / nt, k0 = min(tid * per, nblk), k1 = min(k0 + per, nblk);
+    // per-element arrays indexed with compile-time indices only (kept in
+    // registers); elements past S stay zero
     int sum[kMaxSpecies];
+#pragma unroll
     for (int q = 0; q < kMaxSpecies; ++q) sum[q] = 0;
     for (int k = k0; k < k1; ++k)
-        for (int q = 0; q < S; ++q) sum[q] += blk_cnt[k * kMaxSpecies + q];
-    for (int q = 0; q < S; ++q) part[tid][q] = sum[q];
-    __syncthreads();
-    if (tid < S) {   // exclusive scan over the threads' ranges, per element
-        int run = 0;
-        for (int t = 0; t < nt; ++t) {
-            const int v = part[t][tid];
-            part[t][tid] = run;
-            run += v;
+#pragma unroll
+        for (int q = 0; q < kMaxSpecies; ++q)
+            if (q < S) sum[q] += blk_cnt[k * kMaxSpecies + q];
+    // exclusive scan over the threads' ranges, per element: in-wave shuffles,
+    // then the totals of the preceding waves
+    __shared__ int wtot[4][kMaxSpecies];
+    const int lane = lane_id(), wave = tid >> 6;
+    int incl[kMaxSpecies];
+#pragma unroll
+    for (int q = 0; q < kMaxSpecies; ++q) incl[q] = sum[q];
+    for (int o = 1; o < 64; o <<= 1)
+#pragma unroll
+        for (int q = 0; q < kMaxSpecies; ++q) {
+            const int v = __shfl_up(incl[q], o);
+            if (lane >= o) incl[q] += v;
         }
-        tot[tid] = run;
+    if (lane == 63)
+#pragma unroll
+        for (int q = 0; q < kMaxSpecies; ++q) wtot[wave][q] = incl[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kMaxSpecies; ++q) {
+        int off = 0;
+        for (int w = 0; w < wave; ++w) off += wtot[w][q];
+        if (q < S) part[tid][q] = off + incl[q] - sum[q];
     }
+    if (tid < S) tot[tid] = wtot[0][tid] + wtot[1][tid] + wtot[2][tid] + wtot[3][tid];
     __syncthreads();
     if (tid == 0) {
         base[0] = 0;
