@@ -7,7 +7,7 @@
 // eps_ij = sqrt(eps_i eps_j) and an optional plain cutoff.  Forces act on both
 // sides.  Both force sums are formed without atomics and in a fixed order:
 //
-//   MM side       one thread per MM atom, the NNP atoms staged in LDS:
+//   MM side       four lanes per MM atom, the NNP atoms staged in LDS:
 //                 F_j and a per-block energy partial;
 //   NNP side      one thread per NNP atom for one chunk of MM atoms staged
 //                 in LDS: per-chunk partial F_i;
@@ -33,8 +33,8 @@ template <> __device__ inline double c_rsqrt<double>(double x) { return 1.0 / sq
 // energy of the pair and (dV/dr)/r
 template <typename T>
 __device__ inline void couple_pair(T k, T r2, T qq, T sig, T se, T& v, T& dvr) {
-    const T ri2 = T(1) / r2;
     const T ri = c_rsqrt(r2);
+    const T ri2 = ri * ri;
     const T coul = k * qq * ri;
     const T s2 = sig * sig * ri2;
     const T s6 = s2 * s2 * s2, s12 = s6 * s6;
@@ -53,9 +53,13 @@ __device__ inline void load_atom(const T* __restrict__ x, const T* __restrict__ 
     out[5] = sqrt(par[3 * (size_t)i + 2]);
 }
 
-// MM side: one thread per MM atom j, the NNP atoms in LDS (s, [6][n_nnp]);
-// F_j and the block's energy partial.  Two accumulator sets over alternate
-// NNP atoms keep two independent dependency chains in flight.
+// MM side: four lanes per MM atom j, each over every fourth NNP atom (staged
+// in LDS, s = [6][n_nnp]), combined by a fixed two-step shuffle tree; F_j and
+// the block's energy partial.
+constexpr int kMmLanes = 4;
+constexpr int kMmPerBlock = kMmBlock / kMmLanes;   // MM atoms per workgroup
+static_assert(kMmPerBlock == kCoupleMmPerBlock, "energy partials sized by the handle");
+
 template <typename T>
 __device__ inline void couple_mm_side(int blk, int n_nnp, const T* __restrict__ x_nnp,
                                       const T* __restrict__ par_nnp, int n_mm, const T* __restrict__ x_mm,
@@ -68,48 +72,41 @@ __device__ inline void couple_mm_side(int blk, int n_nnp, const T* __restrict__ 
         for (int v = 0; v < kCoupleVals; ++v) s[v * n_nnp + i] = a[v];
     }
     __syncthreads();
-    const int j = blk * blockDim.x + threadIdx.x;
+    const int j = blk * kMmPerBlock + (int)(threadIdx.x / kMmLanes), sub = threadIdx.x % kMmLanes;
+    const bool act = j < n_mm;
+    T f0 = 0, f1 = 0, f2 = 0;
     double e = 0.0;
-    if (j < n_mm) {
+    if (act) {
         T b[kCoupleVals];
         load_atom(x_mm, par_mm, j, b);
-        T f[2][3] = {{0, 0, 0}, {0, 0, 0}};
-        double eh[2] = {0.0, 0.0};
-        int i = 0;
-        for (; i + 1 < n_nnp; i += 2) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int ii = i + u;
-                const T d0 = b[0] - s[ii], d1 = b[1] - s[n_nnp + ii], d2 = b[2] - s[2 * n_nnp + ii];
-                const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                if (rc2 > T(0) && r2 >= rc2) continue;
-                T v, dvr;
-                couple_pair(k, r2, s[3 * n_nnp + ii] * b[3], s[4 * n_nnp + ii] + b[4],
-                            s[5 * n_nnp + ii] * b[5], v, dvr);
-                eh[u] += (double)v;
-                f[u][0] -= dvr * d0;
-                f[u][1] -= dvr * d1;
-                f[u][2] -= dvr * d2;
-            }
-        }
-        if (i < n_nnp) {
+        for (int i = sub; i < n_nnp; i += kMmLanes) {
             const T d0 = b[0] - s[i], d1 = b[1] - s[n_nnp + i], d2 = b[2] - s[2 * n_nnp + i];
             const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            if (!(rc2 > T(0) && r2 >= rc2)) {
-                T v, dvr;
-                couple_pair(k, r2, s[3 * n_nnp + i] * b[3], s[4 * n_nnp + i] + b[4], s[5 * n_nnp + i] * b[5],
-                            v, dvr);
-                eh[0] += (double)v;
-                f[0][0] -= dvr * d0;
-                f[0][1] -= dvr * d1;
-                f[0][2] -= dvr * d2;
-            }
+            if (rc2 > T(0) && r2 >= rc2) continue;
+            T v, dvr;
+            couple_pair(k, r2, s[3 * n_nnp + i] * b[3], s[4 * n_nnp + i] + b[4], s[5 * n_nnp + i] * b[5], v,
+                        dvr);
+            e += (double)v;
+            f0 -= dvr * d0;
+            f1 -= dvr * d1;
+            f2 -= dvr * d2;
         }
-        e = eh[0] + eh[1];
-        T* F = F_mm + 3 * (size_t)j;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) F[c] = (accumulate ? F[c] : T(0)) + (f[0][c] + f[1][c]);
     }
+    // the four lanes of one MM atom are adjacent
+#pragma unroll
+    for (int o = 1; o < kMmLanes; o <<= 1) {
+        f0 += __shfl_xor(f0, o);
+        f1 += __shfl_xor(f1, o);
+        f2 += __shfl_xor(f2, o);
+        e += __shfl_xor(e, o);
+    }
+    if (act && sub == 0) {
+        T* F = F_mm + 3 * (size_t)j;
+        F[0] = (accumulate ? F[0] : T(0)) + f0;
+        F[1] = (accumulate ? F[1] : T(0)) + f1;
+        F[2] = (accumulate ? F[2] : T(0)) + f2;
+    }
+    if (sub != 0) e = 0.0;
     for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
     __syncthreads();
@@ -211,7 +208,7 @@ hipError_t launch_coupling(const CouplingShape& cs, int n_nnp, const T* x_nnp, c
                            int n_mm, const T* x_mm, const T* par_mm, double* E, T* F_nnp, T* F_mm,
                            double* e_part, T* f_part, bool accumulate, hipStream_t st) {
     const T k = (T)cs.coulomb_k, rc2 = (T)(cs.cutoff > 0 ? cs.cutoff * cs.cutoff : 0.0);
-    const int n_eblk = n_mm > 0 ? (n_mm + kMmBlock - 1) / kMmBlock : 0;
+    const int n_eblk = n_mm > 0 ? (n_mm + kMmPerBlock - 1) / kMmPerBlock : 0;
     const int n_chunks = n_mm > 0 ? (n_mm + cs.chunk - 1) / cs.chunk : 0;
     if (n_eblk > 0) {
         const int n_groups = n_nnp > 0 ? (n_nnp + 63) / 64 : 0, n_cg = (n_chunks + 3) / 4;

@@ -221,6 +221,10 @@ inline hipError_t ensure_lds(const void* kern, size_t bytes) {
 }
 
 // NNP-MM coupling (fixed at creation of a coupling handle)
+// MM atoms per MM-side coupling workgroup (four lanes each): the size of the
+// per-workgroup energy partials the handle allocates
+constexpr int kCoupleMmPerBlock = 64;
+
 struct CouplingShape {
     double coulomb_k;   // 1 / (4 pi eps0) in the caller's units
     double cutoff;      // 0: every pair

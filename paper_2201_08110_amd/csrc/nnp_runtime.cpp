@@ -1147,11 +1147,11 @@ nnp_status nnp_coupling_create(int32_t precision, int32_t max_nnp, int32_t max_m
     c->cs.cutoff = cutoff;
     c->cs.max_nnp = max_nnp;
     c->cs.max_mm = max_mm;
-    // MM atoms per NNP-side wave: 64, widened (up to 512, the LDS limit of
-    // four FP64 chunks) so that at most 1024 chunks exist where possible
-    c->cs.chunk = 64 * std::min(8, std::max(1, (max_mm + 64 * 1024 - 1) / (64 * 1024)));
+    // MM atoms per NNP-side wave: 16, widened (up to 512, the LDS limit of
+    // four FP64 chunks) by 16 per 64k MM atoms so the partials stay bounded
+    c->cs.chunk = 16 * std::min(32, std::max(1, (max_mm + 64 * 1024 - 1) / (64 * 1024)));
     const size_t tsz = precision == NNP_PREC_FP64 ? sizeof(double) : sizeof(float);
-    const size_t n_eblk = (size_t)(max_mm + 255) / 256;
+    const size_t n_eblk = (size_t)(max_mm + kCoupleMmPerBlock - 1) / kCoupleMmPerBlock;
     const size_t n_chunks = (size_t)(max_mm + c->cs.chunk - 1) / c->cs.chunk;
     hipError_t e = hipMalloc(&c->e_part, sizeof(double) * n_eblk);
     if (e == hipSuccess) e = hipMalloc(&c->f_part, tsz * 3 * n_chunks * (size_t)max_nnp);
