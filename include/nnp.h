@@ -243,6 +243,14 @@ int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t
  *                         rows on 4 waves, 2 = half that (at least 16) on 4
  *                         waves, 3 = the full tile on 8 waves (2 x 4); 3 is
  *                         taken as 1 for FP64 (auto 1).
+ *   NNP_KNOB_L1_PATH      layer-1 GEMMs of BF16 handles with 128-row
+ *                         buckets: 1 = both operands staged through LDS
+ *                         (the GEMM_STAGES / GEMM_WAVES knobs apply),
+ *                         2 = activation rows through LDS and the weights
+ *                         loaded into registers from a fragment-ordered copy
+ *                         (128 x 256 tiles; needs M*H1 and the padded AEV
+ *                         length to be multiples of 256).  auto: 2 when
+ *                         supported, else 1.
  *   NNP_KNOB_ATOM_CHUNK   central atoms per workgroup of the featuriser and
  *                         force kernels (4 waves): 4, 8 or 16.  Fewer atoms
  *                         per workgroup spread a small batch over more
@@ -260,7 +268,8 @@ enum {
     NNP_KNOB_TAIL_TILE = 3,
     NNP_KNOB_GEMM_WAVES = 4,
     NNP_KNOB_ATOM_CHUNK = 5,
-    NNP_N_KNOBS = 6
+    NNP_KNOB_L1_PATH = 6,
+    NNP_N_KNOBS = 7
 };
 nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value);
 nnp_status nnp_get_knob(nnp_handle* h, int32_t knob, int32_t* value);

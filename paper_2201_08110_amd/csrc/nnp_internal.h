@@ -174,6 +174,9 @@ template <typename P> struct DevWeights {
     // the fused layers 2-3 kernel's operands in fragment order (per element
     // and model: W2 [H2][H1], W3 [H3][H2], W3^T [H2][H3], W2^T [H1][H2])
     TS* W2f;  TS* W3f;  TS* W3Tf;  TS* W2Tf;
+    // the layer-1 GEMMs' weight operands in fragment order (BF16 only, per
+    // element: W1cat [M*H1][Dp] and W1cat^T [Dp][M*H1]; null otherwise)
+    TS* W1f;  TS* W1Tf;
     double* sae;                   // [S] FP64 (already multiplied by energy_scale)
 };
 
@@ -190,6 +193,7 @@ struct Shape {
     int mlp_fused;                     // 1: fused layers 2-3 kernel, 0: per-layer GEMMs
     int gemm_stages;                   // LDS stages of the layer-1 GEMMs (2 or 3)
     int gemm_waves;                    // waves per workgroup of the layer-1 forward GEMM (4 or 8)
+    int l1_path;                       // layer-1 GEMMs: 1 = both operands through LDS, 2 = weights in registers
     int cell_min;                      // molecules above this many atoms use cutoff cells
     int tail_tile;                     // fused kernel tile variant (1, 2 or 3)
     int chunk;                         // central atoms per featuriser / force workgroup (4, 8, 16)

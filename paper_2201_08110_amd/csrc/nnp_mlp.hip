@@ -190,6 +190,11 @@ template <int N> __device__ inline void vm_wait_barrier() {
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
     asm volatile("s_barrier" ::: "memory");
 }
+// s_waitcnt vmcnt(N) alone (expcnt and lgkmcnt left at their maxima)
+template <int N> __device__ inline void vm_wait() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
 
 // One workgroup of 4 waves computes a BM x BN tile of C = A B^T (A [rows][K],
 // B [N][K], both K-contiguous).  K streams through S LDS stages of 128-byte
@@ -492,6 +497,214 @@ static hipError_t run_gemm(GemmArgs<P> a, int Rcap, int N, int nz, hipStream_t s
     if (e != hipSuccess) return e;
     tm.b(name, st);
     hipLaunchKernelGGL(kern, dim3(T), dim3(64 * WM * WN), lds, st, a);
+    tm.e(name, st);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Layer-1 GEMMs in BF16 with the weight operand in registers.  On gfx950 the
+// LDS returns about 64 bytes per clock per CU to ds_read_b128, which caps a
+// kernel that reads both operands' fragments from LDS with 64 x 64 wave tiles
+// near half the MFMA peak.  Here only the activation rows go through LDS
+// (direct global->LDS loads, two stages, as in k_gemm); each wave loads its
+// weight fragments straight into registers from a fragment-ordered copy of
+// the weights (frag_index layout: one 1 KiB contiguous load per fragment),
+// one k-step ahead.  A workgroup of 4 waves owns a 128 x 256 tile, each wave
+// 128 rows x 64 columns, so LDS serves 64 FLOP per byte read and no weight
+// fragment is loaded twice in a workgroup.
+//
+// Every k-step issues the same loads (4 fragment loads; the second step of a
+// slice also 4 direct row loads), so fixed wait counts hold: a fragment is
+// waited for with 8 younger loads in flight, the row slice needed next with
+// 12 (S - 2) + 8.  With S = 3 the prologue issues one row slice twice (same
+// data to the same LDS), which makes the first slice's count exact too.  Past
+// the end the last slice and the last fragments are loaded again (L2 hits).
+// The LDS fragment reads of the next k-step are interleaved with the MFMAs
+// of the current one.
+constexpr int kRbBM = 128, kRbBN = 256, kRbWN = 4;
+
+template <int S, int EPI>
+__global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
+    typedef bf16_t TS;
+    typedef float TA;
+    typedef MF<TS> mf;
+    typedef typename mf::Acc Acc;
+    typedef typename mf::Frag Frag;
+    typedef Slice<TS> L;
+    constexpr int BM = kRbBM, BN = kRbBN, BK = L::BK;   // BK = 64 (two 32-deep k-steps)
+    constexpr int WTN = BN / kRbWN, FM = BM / 16, FN = WTN / 16;
+    constexpr int NQ = BM / 8 / kRbWN;                   // direct row loads per wave per slice
+    static_assert(BK == 2 * mf::KM && NQ == 4 && FN == 4, "tile");
+    static_assert(S == 2 || S == 3, "stages");
+    extern __shared__ __align__(16) char smem_raw[];
+    TS* const stage0 = (TS*)smem_raw;                    // S stages of BM rows
+
+    // tile schedule as in k_gemm (XCD-contiguous ranges, kGroupM row tiles)
+    const int T = g.nm * g.nn;
+    const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
+    const int q8 = T >> 3, r8 = T & 7;
+    const int lin = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+    const int grp = lin / (kGroupM * g.nn), inside = lin % (kGroupM * g.nn);
+    const int gsz = min(kGroupM, g.nm - grp * kGroupM);
+    const int tile_n = inside / gsz, tile_m = grp * kGroupM + inside % gsz;
+
+    const int rows = g.info->rows;
+    if (tile_m * BM >= rows) return;
+    const int s = g.tile_species[(tile_m * BM) / g.row_tile];
+    if (s < 0) return;
+    const int lane = threadIdx.x & 63, wn = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+    const TS* A = g.A + (size_t)tile_m * BM * g.lda;
+    const int KQ = g.K / mf::KM;                         // k-steps along K
+    // this wave's fragment column f (16 columns each) starts at fragment
+    // (tile_n * BN / 16 + wn * FN + f, k-step 0)
+    const TS* Bw = g.B + (size_t)s * g.b_s + ((size_t)(tile_n * (BN / 16) + wn * FN) * KQ * 64 + lane) * 8;
+
+    const int ld_row = lane >> 3, ld_chunk = (lane & 7) ^ (lane >> 3);
+    auto issue_rows = [&](int src, int st_) {
+        TS* d = stage0 + (size_t)st_ * BM * BK;
+        const int k0 = src * BK + ld_chunk * L::VE;
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int q = wn + kRbWN * u;
+            __builtin_amdgcn_global_load_lds(NNP_GPTR(A + (size_t)(q * 8 + ld_row) * g.lda + k0),
+                                             NNP_LPTR(d + q * 8 * BK), 16, 0, 0);
+        }
+    };
+    // Fragment loads are issued as inline global_load_dwordx4: the compiler's
+    // wait insertion does not follow loads whose registers are carried around
+    // the loop and waits for every load in flight before the first k-step of
+    // each slice.  Each use below is preceded by an explicit vm_wait that
+    // leaves exactly the loads issued after it in flight, and a scheduling
+    // barrier keeps the MFMAs behind that wait.
+    Frag fb[2][FN];
+    auto load_frags = [&](Frag(&b)[FN], int step) {
+#pragma unroll
+        for (int f = 0; f < FN; ++f)
+            asm volatile("global_load_dwordx4 %0, %1, off"
+                         : "=v"(b[f])
+                         : "v"(Bw + ((size_t)f * KQ + step) * 64 * 8));
+    };
+    Frag fa[2][FM];
+    auto read_rows = [&](Frag(&a)[FM], const TS* st_, int kk) {
+        const int kf = kk + (lane >> 4) * mf::KL;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i] = *(const Frag*)(&st_[L::at(i * 16 + (lane & 15), kf)]);
+    };
+    Acc acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+    auto mma = [&](const Frag(&a)[FM], const Frag(&b)[FN]) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int i = 0; i < FM; ++i) acc[i][j] = mf::mma(b[j], a[i], acc[i][j]);
+    };
+    auto stage = [&](int kt) { return stage0 + (size_t)(S == 2 ? kt & 1 : kt % S) * BM * BK; };
+    // MFMAs of one k-step with the next k-step's fragment reads spread
+    // among them (4 MFMAs, 1 read)
+    auto mma_reads = [&](const Frag(&a)[FM], const Frag(&b)[FN], Frag(&nxt)[FM], const TS* st_, int kk) {
+        read_rows(nxt, st_, kk);
+        mma(a, b);
+#pragma unroll
+        for (int q = 0; q < FM; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);   // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
+        }
+    };
+
+    const int nk = g.K / BK, last = 2 * nk - 1;
+#pragma unroll
+    for (int p = 0; p < S - 1; ++p) issue_rows(min(p, nk - 1), p);
+    load_frags(fb[0], 0);
+    if (S == 3) issue_rows(min(1, nk - 1), 1);          // count padding (same rows again)
+    vm_wait_barrier<S == 2 ? 4 : 12>();                  // rows of slice 0 landed
+    issue_rows(min(S - 1, nk - 1), S - 1);
+    __builtin_amdgcn_s_waitcnt(0xc07f);                  // lgkmcnt(0): kernel arguments
+    read_rows(fa[0], stage(0), 0);
+    for (int kt = 0; kt < nk - 1; ++kt) {
+        // k-step 2 kt
+        load_frags(fb[1], 2 * kt + 1);
+        vm_wait<8>();                                    // fragments of this step
+        __builtin_amdgcn_sched_barrier(0);
+        mma_reads(fa[0], fb[0], fa[1], stage(kt), mf::KM);
+        __builtin_amdgcn_sched_barrier(0);
+        // k-step 2 kt + 1
+        load_frags(fb[0], min(2 * kt + 2, last));
+        vm_wait_barrier<12 * (S - 2) + 8>();             // rows of slice kt+1 landed, stage of kt free
+        issue_rows(min(kt + S, nk - 1), S == 2 ? kt & 1 : kt % S);
+        vm_wait<8>();
+        __builtin_amdgcn_sched_barrier(0);
+        mma_reads(fa[1], fb[1], fa[0], stage(kt + 1), 0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    {
+        load_frags(fb[1], last);
+        vm_wait<8>();
+        __builtin_amdgcn_sched_barrier(0);
+        mma_reads(fa[0], fb[0], fa[1], stage(nk - 1), mf::KM);
+        __builtin_amdgcn_sched_barrier(0);
+        vm_wait_barrier<0>();                            // everything landed; no load still writes LDS
+        __builtin_amdgcn_sched_barrier(0);
+        mma(fa[1], fb[1]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // ---- epilogue: acc[i][j][r] of lane l is C[row i*16 + l%16][col j*16 + 4 (l/16) + r]
+    const int row0 = tile_m * BM + (lane & 15);
+    const int col0 = tile_n * BN + wn * WTN + mf::col0(lane);
+    if (EPI == EPI_CELU) {
+        TS* C = (TS*)g.C;
+        const TA* bias = g.bias + (size_t)s * g.bias_s;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = col0 + j * 16;
+            TA bb[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bb[r] = bias[col + r];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                TA v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = celu(acc[i][j][r] + bb[r], g.alpha, g.inv_alpha);
+                Quad<TS, 1>::st(C + (size_t)(row0 + i * 16) * g.ldc + col, v);
+            }
+        }
+    } else {   // EPI_ACC
+        TA* C = (TA*)g.C;
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                TA v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = acc[i][j][r];
+                Quad<TA, 1>::st(C + (size_t)(row0 + i * 16) * g.ldc + col0 + j * 16, v);
+            }
+    }
+}
+
+static bool l1rb_fits(int Rcap, int N, int K) {
+    return Rcap % kRbBM == 0 && N % kRbBN == 0 && K % Slice<bf16_t>::BK == 0 && K > 0;
+}
+
+template <int EPI>
+static hipError_t run_l1rb(GemmArgs<PrecBF16> a, int Rcap, int N, int stages, hipStream_t st,
+                           const Timer& tm, const char* name) {
+    if (!l1rb_fits(Rcap, N, a.K) || a.B == nullptr || (stages != 2 && stages != 3)) return hipErrorInvalidValue;
+    a.nm = Rcap / kRbBM;
+    a.nn = N / kRbBN;
+    a.nz = 1;
+    const size_t lds = (size_t)stages * kRbBM * 128;
+    auto kern = stages == 2 ? k_l1rb<2, EPI> : k_l1rb<3, EPI>;
+    hipError_t e = ensure_lds((const void*)kern, lds);
+    if (e != hipSuccess) return e;
+    tm.b(name, st);
+    hipLaunchKernelGGL(kern, dim3(a.nm * a.nn), dim3(64 * kRbWN), lds, st, a);
     tm.e(name, st);
     return hipGetLastError();
 }
@@ -870,6 +1083,12 @@ static hipError_t mlp_l1_bwd(const Shape& sh, const DevWeights<P>& wt, Work<P>& 
     a.B = wt.W1T; a.ldb = M * H1; a.b_s = (long)Dp * M * H1; a.b_z = 0;
     a.C = w.dG; a.ldc = Dp; a.c_z = 0;
     a.K = M * H1;
+    if constexpr (std::is_same<P, PrecBF16>::value && BM == kRbBM) {
+        if (sh.l1_path == 2) {
+            a.B = wt.W1Tf;
+            return run_l1rb<EPI_ACC>(a, R, Dp, sh.gemm_stages, st, tm, "mlp_l1_bwd");
+        }
+    }
     if (Dp % C::BNW == 0) return run_l1<P, BM, EPI_ACC>(a, sh, Dp, st, tm, "mlp_l1_bwd");
     return run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_ACC>(a, R, Dp, 1, st, tm, "mlp_l1_bwd");
 }
@@ -899,7 +1118,17 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     a.bias = wt.b1; a.bias_s = (long)M * H1; a.bias_z = 0;
     a.C = w.H1; a.ldc = M * H1; a.c_z = 0;
     a.K = Dp;
-    if ((M * H1) % C::BNW == 0)
+    bool l1_done = false;
+    if constexpr (std::is_same<P, PrecBF16>::value && BM == kRbBM) {
+        if (sh.l1_path == 2) {
+            a.B = wt.W1f;
+            e = run_l1rb<EPI_CELU>(a, R, M * H1, sh.gemm_stages, st, tm, "mlp_l1_fwd");
+            l1_done = true;
+        }
+    }
+    if (l1_done)
+        ;
+    else if ((M * H1) % C::BNW == 0)
         e = run_l1<P, BM, EPI_CELU>(a, sh, M * H1, st, tm, "mlp_l1_fwd");
     else
         e = run_gemm<P, BM, C::BNN, C::WM, C::WN, C::S, EPI_CELU>(a, R, M * H1, 1, st, tm, "mlp_l1_fwd");

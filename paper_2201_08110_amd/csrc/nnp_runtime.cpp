@@ -116,7 +116,7 @@ struct nnp_handle {
     std::vector<GraphEntry> graphs;
 
     // tunable knobs as set by the caller (0 = automatic)
-    int32_t knob[NNP_N_KNOBS] = {0, 0, 0, 0, 0, 0};
+    int32_t knob[NNP_N_KNOBS] = {0, 0, 0, 0, 0, 0, 0};
 
     // timing
     bool timing = false;
@@ -269,6 +269,20 @@ template <typename P> nnp_status upload_weights(nnp_handle* h, DevWeights<P>& dw
     };
     const std::vector<TS> W2f = fragments(W2, H2, H1), W3f = fragments(W3, H3, H2);
     const std::vector<TS> W3Tf = fragments(W3T, H2, H3), W2Tf = fragments(W2T, H1, H2);
+    // the layer-1 weights in fragment order for the register-operand GEMMs
+    // (BF16): one [M*H1][Dp] matrix and its transpose per element
+    std::vector<TS> W1f, W1Tf;
+    if (std::is_same<TS, bf16_t>::value) {
+        const int N1 = M * H1;
+        W1f.resize(W1.size());
+        W1Tf.resize(W1T.size());
+        for (size_t e = 0; e < (size_t)S; ++e)
+            for (int n = 0; n < N1; ++n)
+                for (int k = 0; k < Dp; ++k) {
+                    W1f[e * N1 * Dp + frag_index<TS>(n, k, Dp)] = W1[(e * N1 + n) * Dp + k];
+                    W1Tf[e * N1 * Dp + frag_index<TS>(k, n, N1)] = W1[(e * N1 + n) * Dp + k];
+                }
+    }
     hipError_t e = hipSuccess;
     auto put = [&](auto*& dst, const auto& src) -> bool {
         size_t bytes = src.size() * sizeof(src[0]);
@@ -282,7 +296,8 @@ template <typename P> nnp_status upload_weights(nnp_handle* h, DevWeights<P>& dw
     if (!put(dw.W1, W1) || !put(dw.W1T, W1T) || !put(dw.b1, b1) || !put(dw.W2, W2) ||
         !put(dw.W2T, W2T) || !put(dw.b2, b2) || !put(dw.W3, W3) || !put(dw.W3T, W3T) ||
         !put(dw.b3, b3) || !put(dw.w4, w4) || !put(dw.b4, b4) || !put(dw.sae, sae) ||
-        !put(dw.W2f, W2f) || !put(dw.W3f, W3f) || !put(dw.W3Tf, W3Tf) || !put(dw.W2Tf, W2Tf))
+        !put(dw.W2f, W2f) || !put(dw.W3f, W3f) || !put(dw.W3Tf, W3Tf) || !put(dw.W2Tf, W2Tf) ||
+        (!W1f.empty() && (!put(dw.W1f, W1f) || !put(dw.W1Tf, W1Tf))))
         return fail(e == hipErrorOutOfMemory ? NNP_E_NOMEM : NNP_E_DEVICE,
                     std::string("weight upload: ") + hipGetErrorString(e));
     return NNP_OK;
@@ -360,6 +375,14 @@ template <typename T> const AevConst<T>& const_of(nnp_handle* h);
 template <> const AevConst<float>& const_of<float>(nnp_handle* h) { return h->cf; }
 template <> const AevConst<double>& const_of<double>(nnp_handle* h) { return h->cd; }
 
+// the register-operand layer-1 GEMMs: BF16, 128-row buckets, both GEMMs'
+// N (M*H1 forward, the padded AEV length backward) in 256-column tiles
+bool l1_regs_supported(const nnp_handle* h) {
+    const Shape& sh = h->shape;
+    return h->precision == NNP_PREC_BF16_MLP && sh.row_tile == 128 && (sh.M * sh.H1) % 256 == 0 &&
+           sh.Dp % 256 == 0;
+}
+
 // value in effect of a knob (automatic choices resolved)
 int32_t knob_value(const nnp_handle* h, int k) {
     const Shape& sh = h->shape;
@@ -375,6 +398,9 @@ int32_t knob_value(const nnp_handle* h, int k) {
     case NNP_KNOB_ATOM_CHUNK:
         if (v) return v;
         return (int64_t)h->max_mols * ((h->max_apm + 15) / 16) >= 1024 ? 16 : 4;
+    case NNP_KNOB_L1_PATH:
+        if (v) return v;
+        return l1_regs_supported(h) ? 2 : 1;
     }
     return 0;
 }
@@ -387,6 +413,7 @@ void apply_knobs(nnp_handle* h) {
     h->shape.tail_tile = knob_value(h, NNP_KNOB_TAIL_TILE);
     h->shape.gemm_waves = knob_value(h, NNP_KNOB_GEMM_WAVES);
     h->shape.chunk = knob_value(h, NNP_KNOB_ATOM_CHUNK);
+    h->shape.l1_path = knob_value(h, NNP_KNOB_L1_PATH);
     for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     h->graphs.clear();
 }
@@ -579,7 +606,8 @@ const char* knob_name(int k) {
          : k == NNP_KNOB_GEMM_STAGES ? "gemm_stages"
          : k == NNP_KNOB_CELL_MIN ? "cell_min"
          : k == NNP_KNOB_TAIL_TILE ? "tail_tile"
-         : k == NNP_KNOB_GEMM_WAVES ? "gemm_waves" : "atom_chunk";
+         : k == NNP_KNOB_GEMM_WAVES ? "gemm_waves"
+         : k == NNP_KNOB_ATOM_CHUNK ? "atom_chunk" : "l1_path";
 }
 
 std::string tune_key(const nnp_handle* h) {
@@ -671,6 +699,8 @@ nnp_status autotune(nnp_handle* h, const nnp_batch* b, const typename P::T* x, i
             if (h->shape.row_tile == 128 && h->precision != NNP_PREC_FP64) cand = {4, 8};
         } else if (k == NNP_KNOB_ATOM_CHUNK) {
             cand = {4, 8, 16};
+        } else if (k == NNP_KNOB_L1_PATH) {
+            if (l1_regs_supported(h)) cand = {1, 2};
         } else {
             for (int c : {32, 64, 128, 256})
                 if (c < h->max_apm) cand.push_back(c);
@@ -1049,6 +1079,10 @@ nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value) {
         ok = ok || value == 4 || value == 8;
     } else if (knob == NNP_KNOB_ATOM_CHUNK) {
         ok = ok || value == 4 || value == 8 || value == 16;
+    } else if (knob == NNP_KNOB_L1_PATH) {
+        if (value == 2 && !l1_regs_supported(h))
+            return fail(NNP_E_UNSUPPORTED, "register-operand layer-1 GEMMs need BF16 and 128-row buckets");
+        ok = ok || value == 1 || value == 2;
     } else {
         ok = ok || (value >= 16 && value <= kMaxAtomsPerMol);
     }

@@ -62,9 +62,11 @@ EXPORTS = ("nnp_create", "nnp_destroy", "nnp_energy_forces", "nnp_energy_forces_
 FLAG_ACCUMULATE = 2
 
 #: tunable knobs (include/nnp.h)
-KNOB_MLP_PATH, KNOB_GEMM_STAGES, KNOB_CELL_MIN, KNOB_TAIL_TILE, KNOB_GEMM_WAVES, KNOB_ATOM_CHUNK = range(6)
+(KNOB_MLP_PATH, KNOB_GEMM_STAGES, KNOB_CELL_MIN, KNOB_TAIL_TILE, KNOB_GEMM_WAVES, KNOB_ATOM_CHUNK,
+ KNOB_L1_PATH) = range(7)
 KNOBS = {"mlp_path": KNOB_MLP_PATH, "gemm_stages": KNOB_GEMM_STAGES, "cell_min": KNOB_CELL_MIN,
-         "tail_tile": KNOB_TAIL_TILE, "gemm_waves": KNOB_GEMM_WAVES, "atom_chunk": KNOB_ATOM_CHUNK}
+         "tail_tile": KNOB_TAIL_TILE, "gemm_waves": KNOB_GEMM_WAVES, "atom_chunk": KNOB_ATOM_CHUNK,
+         "l1_path": KNOB_L1_PATH}
 
 
 def load_library(path: str = LIB_PATH):

@@ -113,10 +113,11 @@ def test_null_arguments():
 def test_knob_ids_match_header():
     nnp, _ = _lib()
     hdr = open(os.path.join(ROOT, "include", "nnp.h")).read()
-    ids = dict((k, int(v)) for k, v in re.findall(r"\bNNP_KNOB_([A-Z_]+)\s*=\s*(\d+)", hdr))
+    ids = dict((k, int(v)) for k, v in re.findall(r"\bNNP_KNOB_([A-Z0-9_]+)\s*=\s*(\d+)", hdr))
     assert ids == {"MLP_PATH": nnp.KNOB_MLP_PATH, "GEMM_STAGES": nnp.KNOB_GEMM_STAGES,
                    "CELL_MIN": nnp.KNOB_CELL_MIN, "TAIL_TILE": nnp.KNOB_TAIL_TILE,
-                   "GEMM_WAVES": nnp.KNOB_GEMM_WAVES, "ATOM_CHUNK": nnp.KNOB_ATOM_CHUNK}
+                   "GEMM_WAVES": nnp.KNOB_GEMM_WAVES, "ATOM_CHUNK": nnp.KNOB_ATOM_CHUNK,
+                   "L1_PATH": nnp.KNOB_L1_PATH}
     assert set(nnp.KNOBS.values()) == set(ids.values())
 
 

@@ -121,3 +121,37 @@ def test_autotune_choice_and_cache(orc, hp, tmp_path):
     torch.cuda.synchronize()
     dE, rmse = errors(E.cpu().numpy(), F.double().cpu().numpy(), Eo, Fo, b.mol_offsets)
     assert dE.max() <= 1e-4 and rmse.max() <= 1e-3
+
+
+def test_bf16_layer1_paths(orc, hp):
+    """Layer-1 GEMMs with both operands staged through LDS (path 1) and with
+    the weights in registers (path 2, 2 and 3 LDS stages) on a ragged batch of
+    several element buckets: each against the FP64 oracle at the BF16 bar, and
+    against each other (same BF16 operands, FP32 sums in another order)."""
+    torch = torch_cuda()
+    b = synth.random_batch(72, [64, 300, 17, 219, 150])
+    M = 8
+    w = synth.xavier_weights(M, hp["widths"], seed=48)
+    h = make_handle(hp, w, M, "bf16", b, max_atoms=1024)
+    assert h.get_knob("l1_path") == 2
+    x, sp, off = to_device(torch, b, torch.float32)
+    xo, wo = oracle_inputs(b, w, "bf16")
+    Eo, Fo = orc.energy_forces(hp, wo, M, b.species, xo, b.mol_offsets)
+    frms = np.sqrt(np.mean(Fo ** 2))
+    out = {}
+    for path, stages in ((1, 2), (2, 2), (2, 3)):
+        h.set_knob("l1_path", path)
+        h.set_knob("gemm_stages", stages)
+        E, F = h.energy_forces(x, sp, off)
+        torch.cuda.synchronize()
+        assert h.device_status() == 0
+        E, F = E.cpu().numpy(), F.double().cpu().numpy()
+        dE, rmse = errors(E, F, Eo, Fo, b.mol_offsets)
+        print("bf16 l1_path", path, "stages", stages, "|dE|/atom", dE.max(), "RMSE", rmse.max(), "RMS(F)", frms)
+        assert dE.max() <= 2.0 and rmse.max() <= 1e-2 * frms
+        out[(path, stages)] = (E, F)
+    n_at = np.diff(b.mol_offsets)
+    for key in ((2, 2), (2, 3)):
+        dE = np.abs(out[key][0] - out[(1, 2)][0]) / np.maximum(n_at, 1)
+        assert dE.max() <= 0.05, key
+        assert np.sqrt(np.mean((out[key][1] - out[(1, 2)][1]) ** 2)) <= 5e-3 * frms, key
