@@ -905,8 +905,9 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
     const int wn = wave & 3, m0 = (wave >> 2) * (BM / TW);   // column quarter, first row
     const size_t sz = (size_t)s * g.M + z;
 
-    // H1 tile -> LDS (sliced), direct loads: per K slice BM/8 loads of 8 rows
-    {
+    // H1 tile -> LDS (sliced), direct loads: per K slice BM/8 loads of 8 rows.
+    // Loaded again into the same region for the last phase's CELU'(H1).
+    auto load_h1_tile = [&]() {
         const TS* src0 = g.H1 + (size_t)row0 * g.ldh + (size_t)z * H1;
         const int lr = lane >> 3, lc = (lane & 7) ^ (lane >> 3);
         constexpr int NQ = (H1 / L::BK) * (BM / 8);
@@ -920,6 +921,9 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
                 __builtin_amdgcn_global_load_lds(NNP_GPTR(src), NNP_LPTR(Us + (t * BM + rq * 8) * L::BK), 16, 0, 0);
             }
         }
+    };
+    {
+        load_h1_tile();
         // the layer parameters the epilogues read, staged beside the tile
         for (int t = tid; t < H2 + 2 * H3; t += NT) {
             const TA v = t < H2 ? g.b2[sz * H2 + t]
@@ -1026,16 +1030,18 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
         constexpr int FN = H1 / 64;
         Acc acc[FM][FN];
         const int n0 = wn * (H1 / 4);
-        const TS* Hr = g.H1 + (size_t)row0 * g.ldh + (size_t)z * H1;
         TS* Out = g.DZ1 + (size_t)row0 * g.ldh + (size_t)z * H1;
-        // CELU'(H1) operands of the epilogue, fetched ahead of the product
+        // CELU'(H1) operands of the epilogue: the H1 tile again, into the
+        // region DZ3 held (every wave is past its last read of DZ3), in
+        // flight during the product; whole 128-byte rows per load
+        load_h1_tile();
+        tail_product<TS, BM, FM, FN, H2>(acc, Hs, m0, g.W2Tf + sz * H1 * H2, n0 / 16, lane);
+        vm_wait_barrier<0>();   // H1 tile landed (all waves' parts)
         TA hh[FM][FN][4];
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
-                Quad<TS, ST>::ld(Hr + (size_t)(m0 + i * 16 + rl) * g.ldh + n0 + j * 16 + cl, hh[i][j]);
-        tail_product<TS, BM, FM, FN, H2>(acc, Hs, m0, g.W2Tf + sz * H1 * H2, n0 / 16, lane);
+            for (int i = 0; i < FM; ++i) LdsQuad<TS, ST>::ld(Us, BM, m0 + i * 16 + rl, n0 + j * 16 + cl, hh[i][j]);
         if constexpr (std::is_same<TS, bf16_t>::value && FN == 4) {
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
