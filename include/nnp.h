@@ -235,9 +235,10 @@ int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t
  *                         neighbour lists through cutoff cells, smaller ones
  *                         scan all atoms: 16..1024 (auto 128).
  *   NNP_KNOB_GEMM_WAVES   waves per workgroup of the layer-1 forward GEMM
- *                         on handles with 128-row buckets: 4 (2 x 2 waves
- *                         of 64 x 64) or 8 (2 x 4 waves of 64 x 32) (auto 8;
- *                         the backward GEMM always runs 4).
+ *                         of layer-1 path 1 on handles with 128-row buckets:
+ *                         4 (2 x 2 waves of 64 x 64) or 8 (2 x 4 waves of
+ *                         64 x 32) (auto 8; the backward GEMM always runs 4;
+ *                         path 2 always runs 4 waves of 128 x 64).
  *   NNP_KNOB_TAIL_TILE    row tile of the fused layers 2-3 kernel (handles
  *                         with 128-row buckets): 1 = 128 / (operand bytes)
  *                         rows on 4 waves, 2 = half that (at least 16) on 4

@@ -703,7 +703,13 @@ hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
 // Shared set-up of the AEV and force kernels: the molecule's coordinates and
 // elements, and the chunk's neighbour counts, bucket rows and neighbour lists,
 // all staged in LDS once per workgroup.
-constexpr int kNbStride = 8;   // dx dy dz r fc_r dfc_r fc_a dfc_a
+// Per-neighbour LDS record: dx dy dz r fc_r dfc_r fc_a dfc_a, padded to an
+// odd number of words so that lanes reading the same field of consecutive
+// records hit distinct banks (a stride of 8 words put every fourth record on
+// the same bank).  The featuriser's LDS stays within a quarter of the CU's
+// 160 KB on the headline shape (four workgroups per CU): odd strides for its
+// pair-factor records too would cross that line.
+constexpr int kNbStride = 9;
 
 template <typename T> struct ChunkStage {
     T* sx;            // [max_apm*3]
@@ -1574,7 +1580,7 @@ template <typename T> __device__ inline void d_cutoff(Du<T> r, T pi_rc, Du<T>& f
     dfc = {-T(0.5) * pi_rc * sn, -T(0.5) * pi_rc * pi_rc * cs * r.t};
 }
 
-constexpr int kNbStrideT = 16;   // values dx dy dz r fc_r dfc_r fc_a dfc_a, then their tangents
+constexpr int kNbStrideT = 17;   // values dx dy dz r fc_r dfc_r fc_a dfc_a, then their tangents (odd stride: banks)
 
 template <typename P, int NZ>
 __global__ __launch_bounds__(256) void k_forces_tan(AevConst<typename P::T> c, int A, int max_apm,

@@ -169,24 +169,30 @@ template <> struct Quad<bf16_t, 1> {
 // p points at (row l%16, column 8 (l/16)) of the strip.  Fewer, wider write
 // requests make these stores markedly cheaper on gfx950.
 __device__ inline void st_strip_bf16(bf16_t* p, const uint32_t (&pk)[4][2], int lane) {
-    const int q = lane >> 4, hi = q >> 1;
-    const int srcA = ((lane & 15) + 32 * (q & 1)) * 4, srcB = srcA + 64;   // byte lane addresses
+    const int q = lane >> 4, hi = q >> 1, odd = q & 1;
+    // sources: lanes (l%16) + 32 (q%2) and 16 past it.  Odd q pulls them in
+    // the other order, so the 32 lanes of each ds_bpermute read 32 distinct
+    // banks (lane (l%16) + 32 and lane l%16 would share one).
+    const int srcA = ((lane & 15) + 32 * odd) * 4, srcB = srcA + 64;   // byte lane addresses
+    const int s1 = odd ? srcB : srcA, s2 = odd ? srcA : srcB;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {   // columns 32 h + 8 q ..: piece 2 h + q/2 of lanes 2(q%2), 2(q%2)+1
         const int jl = 2 * h, jh = 2 * h + 1;
+        uint32_t a0 = __builtin_amdgcn_ds_bpermute(s1, (int)pk[jl][0]);
+        uint32_t a1 = __builtin_amdgcn_ds_bpermute(s1, (int)pk[jh][0]);
+        uint32_t b0 = __builtin_amdgcn_ds_bpermute(s1, (int)pk[jl][1]);
+        uint32_t b1 = __builtin_amdgcn_ds_bpermute(s1, (int)pk[jh][1]);
+        const uint32_t f0 = hi ? a1 : a0, f1 = hi ? b1 : b0;   // from s1
+        a0 = __builtin_amdgcn_ds_bpermute(s2, (int)pk[jl][0]);
+        a1 = __builtin_amdgcn_ds_bpermute(s2, (int)pk[jh][0]);
+        b0 = __builtin_amdgcn_ds_bpermute(s2, (int)pk[jl][1]);
+        b1 = __builtin_amdgcn_ds_bpermute(s2, (int)pk[jh][1]);
+        const uint32_t g0 = hi ? a1 : a0, g1 = hi ? b1 : b0;   // from s2
         uint4 o;
-        uint32_t a0 = __builtin_amdgcn_ds_bpermute(srcA, (int)pk[jl][0]);
-        uint32_t a1 = __builtin_amdgcn_ds_bpermute(srcA, (int)pk[jh][0]);
-        uint32_t b0 = __builtin_amdgcn_ds_bpermute(srcA, (int)pk[jl][1]);
-        uint32_t b1 = __builtin_amdgcn_ds_bpermute(srcA, (int)pk[jh][1]);
-        o.x = hi ? a1 : a0;
-        o.y = hi ? b1 : b0;
-        a0 = __builtin_amdgcn_ds_bpermute(srcB, (int)pk[jl][0]);
-        a1 = __builtin_amdgcn_ds_bpermute(srcB, (int)pk[jh][0]);
-        b0 = __builtin_amdgcn_ds_bpermute(srcB, (int)pk[jl][1]);
-        b1 = __builtin_amdgcn_ds_bpermute(srcB, (int)pk[jh][1]);
-        o.z = hi ? a1 : a0;
-        o.w = hi ? b1 : b0;
+        o.x = odd ? g0 : f0;   // columns +0..3 come from srcA
+        o.y = odd ? g1 : f1;
+        o.z = odd ? f0 : g0;   // columns +4..7 from srcB
+        o.w = odd ? f1 : g1;
         *(uint4*)(p + 32 * h) = o;
     }
 }
