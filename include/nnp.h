@@ -214,6 +214,13 @@ nnp_status nnp_get_device_status(nnp_handle* h, int32_t* code);
  * nnp_set_timing.  Returns the number of distinct kernels (-1 on a null
  * handle); names/counts/total_ms may be NULL to query the count. */
 nnp_status nnp_set_timing(nnp_handle* h, int32_t enable);
+/* Restrict the timing above to launches of the kernel called `name` (the
+ * names nnp_kernel_times reports, e.g. "mlp_tail"); NULL or "" times every
+ * launch again.  Each event record between kernels costs microseconds of GPU
+ * time, so timing one kernel perturbs an evaluation least.  Clears the totals
+ * like nnp_set_timing; the setting persists across nnp_set_timing calls.
+ * NNP_E_INVALID on a null handle. */
+nnp_status nnp_set_timing_only(nnp_handle* h, const char* name);
 int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t* counts,
                          double* total_ms);
 

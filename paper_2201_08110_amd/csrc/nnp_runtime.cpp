@@ -120,6 +120,7 @@ struct nnp_handle {
 
     // timing
     bool timing = false;
+    std::string timing_only;           // time only launches of this name (empty: all)
     std::vector<EventPair> pending;
     std::vector<hipEvent_t> free_events;
     std::map<std::string, std::pair<int64_t, double>> totals;
@@ -146,12 +147,14 @@ namespace {
 
 void tm_begin(void* ctx, const char* name, hipStream_t s) {
     nnp_handle* h = (nnp_handle*)ctx;
+    if (!h->timing_only.empty() && h->timing_only != name) return;
     EventPair p{name, h->ev(), h->ev()};
     (void)hipEventRecord(p.a, s);
     h->pending.push_back(p);
 }
 void tm_end(void* ctx, const char* name, hipStream_t s) {
     nnp_handle* h = (nnp_handle*)ctx;
+    if (!h->timing_only.empty() && h->timing_only != name) return;
     for (auto it = h->pending.rbegin(); it != h->pending.rend(); ++it)
         if (it->name == name) {
             (void)hipEventRecord(it->b, s);
@@ -1028,6 +1031,14 @@ nnp_status nnp_set_timing(nnp_handle* h, int32_t enable) {
     h->pending.clear();
     h->totals.clear();
     h->timing = enable != 0;
+    return NNP_OK;
+}
+
+nnp_status nnp_set_timing_only(nnp_handle* h, const char* name) {
+    if (!h) return fail(NNP_E_INVALID, "null handle");
+    const nnp_status rc = nnp_set_timing(h, h->timing ? 1 : 0);   // clears the totals
+    if (rc != NNP_OK) return rc;
+    h->timing_only = name ? name : "";
     return NNP_OK;
 }
 

@@ -55,7 +55,8 @@ _lib = None
 #: every symbol include/nnp.h declares
 EXPORTS = ("nnp_create", "nnp_destroy", "nnp_energy_forces", "nnp_energy_forces_f64", "nnp_aev",
            "nnp_energy_forces_backward", "nnp_set_weights", "nnp_num_params", "nnp_aev_dim",
-           "nnp_get_device_status", "nnp_set_timing", "nnp_kernel_times", "nnp_last_error",
+           "nnp_get_device_status", "nnp_set_timing", "nnp_set_timing_only", "nnp_kernel_times",
+           "nnp_last_error",
            "nnp_set_knob", "nnp_get_knob", "nnp_autotune",
            "nnp_coupling_create", "nnp_coupling_destroy", "nnp_coupling_eval")
 
@@ -101,6 +102,8 @@ def load_library(path: str = LIB_PATH):
     lib.nnp_get_device_status.restype = i32
     lib.nnp_set_timing.argtypes = [vp, i32]
     lib.nnp_set_timing.restype = i32
+    lib.nnp_set_timing_only.argtypes = [vp, C.c_char_p]
+    lib.nnp_set_timing_only.restype = i32
     lib.nnp_kernel_times.argtypes = [vp, i32, P(C.c_char_p), P(i64), P(d)]
     lib.nnp_kernel_times.restype = i32
     lib.nnp_last_error.argtypes = []
@@ -293,7 +296,10 @@ class NNP:
         _check(self.lib.nnp_get_device_status(self.h, C.byref(code)))
         return int(code.value)
 
-    def set_timing(self, on: bool):
+    def set_timing(self, on: bool, only: str | None = None):
+        """Per-kernel event timing on or off; `only` restricts it to one
+        kernel name (None: every kernel)."""
+        _check(self.lib.nnp_set_timing_only(self.h, only.encode() if only else None))
         _check(self.lib.nnp_set_timing(self.h, 1 if on else 0))
 
     def set_knob(self, name: str, value: int):

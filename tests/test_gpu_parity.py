@@ -190,3 +190,30 @@ def test_large_molecules_cell_lists(orc, hp, prec, sizes):
         dE, rmse = errors(E, F, Eo, Fo, b.mol_offsets)
         print("cells fp32 |dE|/atom", dE, "RMSE", rmse)
         assert dE.max() <= 1e-4 and rmse.max() <= 1e-3
+
+
+def test_kernel_timing_filters(hp):
+    """Per-kernel event timing: every launch, then one named kernel only; the
+    results are unchanged by timing and the filter reports only its kernel."""
+    torch = torch_cuda()
+    b = synth.config_batch(5, n_mols=16)
+    w = synth.xavier_weights(8, hp["widths"])
+    h = make_handle(hp, w, 8, "bf16", b, max_atoms=1024)
+    x, sp, off = to_device(torch, b, torch.float32)
+    E0, F0 = h.energy_forces(x, sp, off)
+    h.set_timing(True)
+    for _ in range(3):
+        E1, F1 = h.energy_forces(x, sp, off)
+    kt = h.kernel_times()
+    assert {"aev", "forces", "mlp_l1_fwd", "mlp_tail", "mlp_l1_bwd"} <= set(kt)
+    assert all(c == 3 and ms > 0 for c, ms in kt.values())
+    h.set_timing(True, only="mlp_tail")
+    for _ in range(2):
+        E2, F2 = h.energy_forces(x, sp, off)
+    kt2 = h.kernel_times()
+    assert set(kt2) == {"mlp_tail"} and kt2["mlp_tail"][0] == 2
+    h.set_timing(False)
+    torch.cuda.synchronize()
+    assert h.device_status() == 0
+    np.testing.assert_array_equal(E1.cpu().numpy(), E0.cpu().numpy())
+    np.testing.assert_array_equal(E2.cpu().numpy(), E0.cpu().numpy())
