@@ -217,3 +217,39 @@ def test_kernel_timing_filters(hp):
     assert h.device_status() == 0
     np.testing.assert_array_equal(E1.cpu().numpy(), E0.cpu().numpy())
     np.testing.assert_array_equal(E2.cpu().numpy(), E0.cpu().numpy())
+
+
+def test_full_size_replicas_sampled(orc, hp):
+    """The benchmark's configuration: 1024 replicas of the 48-atom ligand
+    (49,152 atoms), 8 models, BF16 networks, the handle sized as the
+    benchmark sizes it.  Six molecules (first, last, four seeded) against the
+    FP64 oracle at the BF16 bars of test_bf16_mlp_replicas; over all 1024
+    molecules, each molecule's forces sum to zero (every pair term acts on
+    its two atoms with opposite signs), to FP32 rounding."""
+    torch = torch_cuda()
+    from paper_2201_08110_amd.nnp import NNP
+    b = synth.config_batch(5, n_mols=1024)
+    w = synth.xavier_weights(8, hp["widths"])
+    h = NNP(hp, w, 8, "bf16", max_atoms=b.n_atoms, max_mols=b.n_mols, max_atoms_per_mol=48)
+    assert h.get_knob("l1_path") == 2 and h.get_knob("mlp_path") == 1
+    x, sp, off = to_device(torch, b, torch.float32)
+    E, F = h.energy_forces(x, sp, off)
+    torch.cuda.synchronize()
+    assert h.device_status() == 0
+    E, F = E.cpu().numpy(), F.double().cpu().numpy()
+    assert np.all(np.isfinite(E)) and np.all(np.isfinite(F))
+    o = np.asarray(b.mol_offsets)
+    assert np.all(np.diff(o) == 48)
+    net = np.add.reduceat(F, o[:-1], axis=0)
+    print("full size: max |net force| / max |F|", np.abs(net).max() / np.abs(F).max())
+    assert np.abs(net).max() <= 1e-4 * np.abs(F).max()
+    rng = np.random.default_rng(11)
+    pick = sorted({0, b.n_mols - 1, *rng.choice(np.arange(1, b.n_mols - 1), 4, replace=False).tolist()})
+    rows = np.concatenate([np.arange(o[m], o[m + 1]) for m in pick])
+    sub_off = np.arange(len(pick) + 1, dtype=np.int64) * 48
+    Eo, Fo = orc.energy_forces(hp, synth.round_to_fp32(w), 8, np.asarray(b.species)[rows],
+                               synth.round_to_fp32(np.asarray(b.coords)[rows]), sub_off)
+    dE, rmse = errors(E[pick], F[rows], Eo, Fo, sub_off)
+    frms = np.sqrt(np.mean(Fo ** 2))
+    print("full size, sampled", pick, "|dE|/atom max", dE.max(), "RMSE max", rmse.max(), "RMS(F)", frms)
+    assert dE.max() <= 2.0 and rmse.max() <= 1e-2 * frms
