@@ -46,7 +46,8 @@ typedef int32_t nnp_status;
 
 #define NNP_OK              0
 #define NNP_E_INVALID       1   /* null pointer, size out of range, bad hyper-parameter      */
-#define NNP_E_SPECIES       2   /* element index outside the table (device flag)              */
+#define NNP_E_SPECIES       2   /* element (index or atomic number) outside the handle's table:
+                                   at creation (bad table) or from the device flag            */
 #define NNP_E_CAPACITY      3   /* batch exceeds the capacity given at creation               */
 #define NNP_E_NOMEM         4   /* device allocation failed                                   */
 #define NNP_E_DEVICE        5   /* a HIP runtime call failed                                  */
@@ -62,9 +63,19 @@ typedef int32_t nnp_status;
 
 /* nnp_batch.flags */
 #define NNP_FLAG_GRAPH      1u  /* replay a captured HIP graph of the whole evaluation while the
-                                   batch shape, every pointer and the stream stay the same
-                                   (first such call runs eagerly and captures); needs a non-null
-                                   stream and is ignored while per-kernel timing is on          */
+                                   batch shape, every pointer, the flags and the stream stay
+                                   the same (first such call runs eagerly and captures); needs
+                                   a non-null stream and is ignored while per-kernel timing is
+                                   on                                                         */
+#define NNP_FLAG_ACCUMULATE 2u  /* add the results to what the outputs hold instead of
+                                   overwriting them (nnp_energy_forces / _f64: out_E and
+                                   out_F; nnp_coupling_eval: its energy and both forces), e.g.
+                                   to sum V_NNP and the coupling term of Eq. 1 in one buffer  */
+
+/* nnp_model_params.create_flags */
+#define NNP_CREATE_TRAINING 1u  /* allocate the training backward's workspace in nnp_create
+                                   (FP32 / FP64 handles); without it the first
+                                   nnp_energy_forces_backward allocates it                    */
 
 typedef struct nnp_handle nnp_handle;
 
@@ -126,6 +137,16 @@ typedef struct {
     int32_t max_mols;             /* capacity: molecules per call */
     int32_t max_atoms_per_mol;    /* capacity: atoms of the largest molecule (<= 1024) */
     int32_t device;               /* HIP device ordinal */
+
+    /* Element table (Eq. 2 takes the atomic numbers Z of the NNP atoms):
+     * host [S], the atomic number of element s (1..127, all distinct), e.g.
+     * {1, 6, 7, 8, 9, 16, 17} for H, C, N, O, F, S, Cl.  With a table, the
+     * batches' species arrays hold atomic numbers and an atomic number
+     * outside the table raises NNP_E_SPECIES on the device flag; NULL: they
+     * hold element indices 0..S-1.  A bad table fails creation with
+     * NNP_E_SPECIES. */
+    const int32_t* atomic_numbers;
+    uint32_t create_flags;        /* 0 or NNP_CREATE_TRAINING */
 } nnp_model_params;
 
 /*
@@ -137,15 +158,20 @@ typedef struct {
     int32_t n_mols;               /* 1..max_mols */
     int32_t n_atoms;              /* 0..max_atoms, must equal mol_offsets[n_mols] */
     const int32_t* mol_offsets;   /* device [n_mols+1], non-decreasing, [0] = 0 */
-    const int32_t* species;       /* device [n_atoms], element indices 0..S-1 */
+    const int32_t* species;       /* device [n_atoms]: atomic numbers on handles created with an
+                                     element table, else element indices 0..S-1 */
     void* stream;                 /* hipStream_t; NULL = the null stream */
-    uint32_t flags;               /* 0 or NNP_FLAG_GRAPH */
+    uint32_t flags;               /* NNP_FLAG_GRAPH | NNP_FLAG_ACCUMULATE */
 } nnp_batch;
 
 /*
  * Create a handle: validate the model, pack its weights for the chosen
  * precision onto the device, and allocate the workspace for the capacities.
- * This is the only call that allocates device memory.
+ * Device memory is allocated here, with two exceptions: the training
+ * backward's workspace (here with NNP_CREATE_TRAINING, else on the first
+ * nnp_energy_forces_backward, which can then fail with NNP_E_NOMEM and must
+ * not be the first such call under graph capture), and the temporary outputs
+ * of nnp_autotune.
  * Returns NNP_OK and *out, or an error (and *out = NULL).
  */
 nnp_status nnp_create(const nnp_model_params* params, nnp_handle** out);
@@ -156,8 +182,8 @@ void nnp_destroy(nnp_handle* h);
 /*
  * Energies and forces (Methods, Eq. 2 and Eq. 3), FP32 / BF16-MLP handles.
  *   coords  device float [n_atoms][3]
- *   out_E   device double [n_mols]     (overwritten)
- *   out_F   device float [n_atoms][3]  (overwritten), may be NULL for energies only
+ *   out_E   device double [n_mols]     (overwritten, or added to with NNP_FLAG_ACCUMULATE)
+ *   out_F   device float [n_atoms][3]  (likewise), may be NULL for energies only
  * No allocation; safe to capture in a HIP graph once the batch shape is fixed.
  */
 nnp_status nnp_energy_forces(nnp_handle* h, const nnp_batch* b, const float* coords,
@@ -196,6 +222,20 @@ nnp_status nnp_energy_forces_backward(nnp_handle* h, const nnp_batch* b, const v
  * Synchronous with respect to the host; the handle must be idle. */
 nnp_status nnp_set_weights(nnp_handle* h, const double* weights);
 
+/* Replace the weights from device memory, for training loops that keep their
+ * parameters on the GPU (Methods, first optimisation: no CPU<->GPU copies):
+ *   params  device [nnp_num_params], packed as nnp_model_params.weights, of
+ *           type NNP_PREC_FP64 (double) or NNP_PREC_FP32 (float);
+ *   stream  hipStream_t the update is enqueued on (NULL: the null stream).
+ * Asynchronous and allocation-free: evaluations enqueued after it on the same
+ * stream see the new weights, and captured graphs stay valid (they read the
+ * same device buffers).  The values are rounded to the handle's precision
+ * exactly as nnp_create rounds host weights, so the result equals a handle
+ * created with these weights.  params must stay valid until the stream
+ * passes the call; evaluations still running on other streams must finish
+ * first. */
+nnp_status nnp_set_params(nnp_handle* h, const void* params, int32_t type, void* stream);
+
 /* Number of packed parameters (the length of weights / grad_params). */
 int64_t nnp_num_params(const nnp_handle* h);
 
@@ -203,7 +243,10 @@ int64_t nnp_num_params(const nnp_handle* h);
 int32_t nnp_aev_dim(const nnp_handle* h);
 
 /* Read and clear the device-side error flag (synchronises the handle's last
- * stream).  *code is NNP_OK, NNP_E_SPECIES or NNP_E_CAPACITY. */
+ * stream).  *code is NNP_OK, NNP_E_SPECIES (an element index or atomic number
+ * outside the table) or NNP_E_CAPACITY (a molecule above max_atoms_per_mol,
+ * rows above the capacity, inconsistent mol_offsets, or an atom with more
+ * neighbours within rcr than the list holds: min(max_atoms_per_mol - 1, 192)). */
 nnp_status nnp_get_device_status(nnp_handle* h, int32_t* code);
 
 /* Per-kernel timing: when enabled, every kernel launch of the handle is
@@ -265,6 +308,14 @@ int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t
  *                         compute units; more share the staging of their
  *                         molecule.  auto: 16 when the capacity gives at
  *                         least 1024 workgroups at 16, else 4.
+ *   NNP_KNOB_FORCE_SUM    1 = forces summed with floating-point atomic adds
+ *                         (the last bits vary from run to run), 2 = every
+ *                         contribution rounded to a 64-bit fixed-point
+ *                         integer (units of 2^-32) and summed with integer
+ *                         adds, converted to the force type once: bitwise
+ *                         identical forces on every run, stream and launch
+ *                         shape (the rest of an evaluation already is).
+ *                         auto: 1.  The autotuner leaves this knob alone.
  *
  * Setting a knob drops the handle's captured graphs.  Invalid knob ids or
  * values return NNP_E_INVALID (a fused path on unsupported widths returns
@@ -277,7 +328,8 @@ enum {
     NNP_KNOB_GEMM_WAVES = 4,
     NNP_KNOB_ATOM_CHUNK = 5,
     NNP_KNOB_L1_PATH = 6,
-    NNP_N_KNOBS = 7
+    NNP_KNOB_FORCE_SUM = 7,
+    NNP_N_KNOBS = 8
 };
 nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value);
 nnp_status nnp_get_knob(nnp_handle* h, int32_t knob, int32_t* value);
@@ -319,8 +371,6 @@ nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, i
  * launch configuration and bitwise repeatable (no atomics).  Sizes above the
  * capacities return NNP_E_CAPACITY; null pointers NNP_E_INVALID (n = 0 sides
  * may pass NULL arrays). */
-#define NNP_FLAG_ACCUMULATE 2u
-
 typedef struct nnp_coupling nnp_coupling;
 nnp_status nnp_coupling_create(int32_t precision, int32_t max_nnp, int32_t max_mm, double coulomb_k,
                                double cutoff, int32_t device, nnp_coupling** out);

@@ -24,14 +24,19 @@ class NNPFunction(torch.autograd.Function):
         E, F = model.energy_forces(coords.detach().contiguous(), species, mol_offsets)
         ctx.model = model
         ctx.params_meta = (params.dtype, params.device)
-        ctx.save_for_backward(coords, species, mol_offsets)
+        # params is saved so that torch's version check refuses a backward
+        # after an in-place change of the weights this forward used
+        ctx.save_for_backward(coords, params, species, mol_offsets)
         ctx.set_materialize_grads(False)
         return E, F
 
     @staticmethod
     def backward(ctx, gE, gF):
-        coords, species, mol_offsets = ctx.saved_tensors
+        coords, params, species, mol_offsets = ctx.saved_tensors
         model: NNP = ctx.model
+        # another forward on the same model may have loaded other weights
+        # since: the backward differentiates at this forward's weights
+        model.sync_params(params)
         need_x, need_w = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if gE is None and gF is None:
             return None, None, None, None, None

@@ -105,9 +105,24 @@ __device__ inline void decode_pair_rot(int p, int n, int& j, int& k) {
 // Element bucketing (three kernels): per-block element counts and molecule
 // checks; one small scan of the block counts into padded bucket starts; a
 // stable scatter of every atom to its bucket row.
+// Element of atom a: the batch's label itself, or, on handles with a table
+// of atomic numbers (zlut != null), the table's index of that atomic number
+// (-1 when absent), written to sp_out for the later kernels.
+__device__ inline int element_of(const int32_t* __restrict__ species, const int8_t* __restrict__ zlut,
+                                 int32_t* __restrict__ sp_out, int a, int S) {
+    int s = species[a];
+    if (zlut) {
+        s = (s >= 0 && s < kZLut) ? (int)zlut[s] : -1;
+        sp_out[a] = s < 0 ? 0 : s;
+    }
+    return s < 0 || s >= S ? -1 : s;
+}
+
 __global__ __launch_bounds__(1024) void k_bucket_count(int A, int B, int S, int max_apm,
                                                        const int32_t* __restrict__ mol_off,
                                                        const int32_t* __restrict__ species,
+                                                       const int8_t* __restrict__ zlut,
+                                                       int32_t* __restrict__ sp_out,
                                                        int32_t* __restrict__ mol_of_atom,
                                                        int32_t* __restrict__ blk_cnt,
                                                        int32_t* __restrict__ flag) {
@@ -132,8 +147,8 @@ __global__ __launch_bounds__(1024) void k_bucket_count(int A, int B, int S, int 
             else hi = mid;
         }
         mol_of_atom[a] = lo;
-        s = species[a];
-        if (s < 0 || s >= S) {
+        s = element_of(species, zlut, sp_out, a, S);
+        if (s < 0) {
             atomicOr(flag, FLAG_SPECIES);
             s = 0;
         }
@@ -271,6 +286,8 @@ __global__ __launch_bounds__(1024) void k_bucket_scatter(int A, int S, const int
 __global__ __launch_bounds__(1024) void k_bucket_one(int A, int B, int S, int max_apm, int row_tile,
                                                      int Rcap, const int32_t* __restrict__ mol_off,
                                                      const int32_t* __restrict__ species,
+                                                     const int8_t* __restrict__ zlut,
+                                                     int32_t* __restrict__ sp_out,
                                                      int32_t* __restrict__ mol_of_atom,
                                                      int32_t* __restrict__ row_of_atom,
                                                      int32_t* __restrict__ atom_of_row,
@@ -296,8 +313,8 @@ __global__ __launch_bounds__(1024) void k_bucket_one(int A, int B, int S, int ma
             else hi = mid;
         }
         mol_of_atom[a] = lo;
-        s = species[a];
-        if (s < 0 || s >= S) {
+        s = element_of(species, zlut, sp_out, a, S);
+        if (s < 0) {
             atomicOr(flag, FLAG_SPECIES);
             s = 0;
         }
@@ -357,19 +374,21 @@ hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* s
     tm.b("prep", st);
     if (nblk <= 1) {
         hipLaunchKernelGGL(k_bucket_one, dim3(1), dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S, sh.max_apm,
-                           sh.row_tile, sh.Rcap, mol_off, species, w.mol_of_atom, w.row_of_atom,
-                           w.atom_of_row, w.tile_species, w.info, w.flag);
+                           sh.row_tile, sh.Rcap, mol_off, species, w.zlut, w.sp, w.mol_of_atom,
+                           w.row_of_atom, w.atom_of_row, w.tile_species, w.info, w.flag);
         tm.e("prep", st);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_bucket_count, dim3(nblk), dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S,
-                       sh.max_apm, mol_off, species, w.mol_of_atom, blk_cnt, w.flag);
+                       sh.max_apm, mol_off, species, w.zlut, w.sp, w.mol_of_atom, blk_cnt, w.flag);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(256), 0, st, nblk, sh.S, sh.row_tile, sh.Rcap,
                        blk_cnt, blk_base, w.atom_of_row, w.tile_species, w.info, w.flag);
+    // on handles with atomic numbers the count kernel has written the
+    // element indices to w.sp
     if (sh.A > 0)
         hipLaunchKernelGGL(k_bucket_scatter, dim3((sh.A + kPrepBlock - 1) / kPrepBlock),
-                           dim3(kPrepBlock), 0, st, sh.A, sh.S, species, blk_base, w.info,
-                           w.row_of_atom, w.atom_of_row);
+                           dim3(kPrepBlock), 0, st, sh.A, sh.S, w.zlut ? w.sp : species, blk_base,
+                           w.info, w.row_of_atom, w.atom_of_row);
     tm.e("prep", st);
     return hipGetLastError();
 }
@@ -419,6 +438,7 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
                                                    T rcr2, const int32_t* __restrict__ mol_off,
                                                    const int32_t* __restrict__ species,
                                                    const T* __restrict__ x, T* __restrict__ F,
+                                                   unsigned long long* __restrict__ Fq,
                                                    uint16_t* __restrict__ nbr,
                                                    int32_t* __restrict__ nbr_cnt,
                                                    int32_t* __restrict__ flag) {
@@ -524,6 +544,11 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
             F[3 * ((size_t)a0 + il) + 1] = T(0);
             F[3 * ((size_t)a0 + il) + 2] = T(0);
         }
+        if (Fq) {
+            Fq[3 * ((size_t)a0 + il) + 0] = 0ull;
+            Fq[3 * ((size_t)a0 + il) + 1] = 0ull;
+            Fq[3 * ((size_t)a0 + il) + 2] = 0ull;
+        }
     }
     uint16_t* my = lst + (size_t)lane * cap;
     int cnt = 0, nang = 0;
@@ -582,6 +607,7 @@ __global__ __launch_bounds__(256) void k_nbr_pairs(int A, int S, int max_apm, in
                                                    const int32_t* __restrict__ mol_off,
                                                    const int32_t* __restrict__ species,
                                                    const T* __restrict__ x, T* __restrict__ F,
+                                                   unsigned long long* __restrict__ Fq,
                                                    uint16_t* __restrict__ nbr,
                                                    int32_t* __restrict__ nbr_cnt,
                                                    int32_t* __restrict__ flag) {
@@ -627,6 +653,7 @@ __global__ __launch_bounds__(256) void k_nbr_pairs(int A, int S, int max_apm, in
         const int il = i0 + ic;
         const T xi0 = tx[3 * il], xi1 = tx[3 * il + 1], xi2 = tx[3 * il + 2];
         if (F && lane < 3) F[3 * ((size_t)a0 + il) + lane] = T(0);
+        if (Fq && lane < 3) Fq[3 * ((size_t)a0 + il) + lane] = 0ull;
         uint16_t* out = nbr + ((size_t)a0 + il) * cap;
         int cnt = 0, nang = 0;
         for (int pass = 0; pass < 2; ++pass) {
@@ -662,9 +689,19 @@ __global__ __launch_bounds__(256) void k_nbr_pairs(int A, int S, int max_apm, in
 template <typename P>
 hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
                              const int32_t* mol_off, const int32_t* species,
-                             const typename P::T* x, typename P::T* F, Work<P>& w, hipStream_t st,
-                             const Timer& tm) {
+                             const typename P::T* x, typename P::T* F, bool accumulate, Work<P>& w,
+                             hipStream_t st, const Timer& tm) {
     typedef typename P::T T;
+    // the neighbour kernels clear the force accumulators of the evaluation:
+    // the integer sums when forces are summed in fixed point, else F itself
+    // unless the forces accumulate onto it
+    unsigned long long* Fq = nullptr;
+    if (F && sh.force_fixed) {
+        Fq = w.Fq;
+        F = nullptr;
+    } else if (accumulate) {
+        F = nullptr;
+    }
     // molecules up to cell_min atoms: one wave per central atom
     {
         const int small = std::min(sh.max_apm, sh.cell_min);
@@ -676,7 +713,7 @@ hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
         if (e != hipSuccess) return e;
         tm.b("neighbours", st);
         hipLaunchKernelGGL(k_nbr_pairs<T>, grid, dim3(256), lds, st, sh.A, sh.S, sh.max_apm, sh.cell_min,
-                           sh.chunk, sh.cap_nbr, c.rca2, c.rcr2, mol_off, species, x, F, w.nbr,
+                           sh.chunk, sh.cap_nbr, c.rca2, c.rcr2, mol_off, species, x, F, Fq, w.nbr,
                            w.nbr_cnt, w.flag);
         tm.e("neighbours", st);
         if ((e = hipGetLastError()) != hipSuccess || sh.max_apm <= sh.cell_min) return e;
@@ -693,8 +730,8 @@ hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
     if (e != hipSuccess) return e;
     tm.b("neighbours", st);
     hipLaunchKernelGGL(k_neighbours<T>, grid, dim3(64), lds, st, sh.A, sh.S, sh.max_apm,
-                       sh.cell_min, sh.cap_nbr, c.rcr, c.rca2, c.rcr2, mol_off, species, x, F, w.nbr,
-                       w.nbr_cnt, w.flag);
+                       sh.cell_min, sh.cap_nbr, c.rcr, c.rca2, c.rcr2, mol_off, species, x, F, Fq,
+                       w.nbr, w.nbr_cnt, w.flag);
     tm.e("neighbours", st);
     return hipGetLastError();
 }
@@ -1319,7 +1356,32 @@ __device__ inline void st4(double* p, const double v[4]) {
     *(double2*)(p + 2) = make_double2(v[2], v[3]);
 }
 
-template <typename P, int NZ>
+// Force accumulators.  Floating point: LDS and global atomic adds, whose
+// order (and so the last bits of F) varies from run to run.  Fixed point:
+// every contribution is scaled by 2^32 and rounded to a 64-bit integer
+// (exact for FP32 contributions above 2^-9 in magnitude), and integer
+// addition is associative, so the sums are bitwise the same whatever the
+// order; the energy kernel turns them back into F.
+template <typename T, bool FIXED> struct ForceAcc;
+template <typename T> struct ForceAcc<T, false> {
+    typedef T V;
+    __device__ static void add(V* p, T v) { lds_add(p, v); }
+    __device__ static void flush(V v, T* F, unsigned long long*, size_t i) {
+        if (v != V(0)) gbl_add(&F[i], v);
+    }
+};
+constexpr double kForceFix = 4294967296.0;   // 2^32
+__device__ inline long long to_fixed(float v) { return __float2ll_rn(v * 4294967296.0f); }
+__device__ inline long long to_fixed(double v) { return __double2ll_rn(v * kForceFix); }
+template <typename T> struct ForceAcc<T, true> {
+    typedef unsigned long long V;
+    __device__ static void add(V* p, T v) { atomicAdd(p, (unsigned long long)to_fixed(v)); }
+    __device__ static void flush(V v, T*, unsigned long long* Fq, size_t i) {
+        if (v != 0ull) atomicAdd(&Fq[i], v);
+    }
+};
+
+template <typename P, int NZ, bool FIXED>
 __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A, int max_apm,
                                                 int chunk, int cap, const int32_t* __restrict__ mol_off,
                                                 const int32_t* __restrict__ species,
@@ -1328,9 +1390,12 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
                                                 const int32_t* __restrict__ nbr_cnt,
                                                 const int32_t* __restrict__ row_of_atom,
                                                 const typename P::TA* __restrict__ dG,
-                                                typename P::T* __restrict__ F) {
+                                                typename P::T* __restrict__ F,
+                                                unsigned long long* __restrict__ Fq) {
     typedef typename P::T T;
     typedef typename P::TA TA;
+    typedef ForceAcc<T, FIXED> Acc;
+    typedef typename Acc::V V;
     constexpr int NA = kNAZ / NZ;
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x;
@@ -1346,14 +1411,14 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
     LdsBump lb(smem);
     ChunkStage<T> cs;
     cs.take(lb, max_apm, cap);
-    T* sF = lb.take<T>(3 * (size_t)max_apm);
+    V* sF = lb.take<V>(3 * (size_t)max_apm);
     T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
     int* nsp = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
     int* nid = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
     T* g = lb.take<T>((size_t)nw * GL) + (size_t)wave * GL;
 
     cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, row_of_atom);
-    for (int t = tid; t < 3 * n; t += blockDim.x) sF[t] = T(0);
+    for (int t = tid; t < 3 * n; t += blockDim.x) sF[t] = V(0);
     __syncthreads();
     for (int ic = wave; ic < nc; ic += nw) {
         const int il = i0 + ic;
@@ -1413,9 +1478,9 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
                 const T u0 = e[0] * inv, u1 = e[1] * inv, u2 = e[2] * inv;
                 const int j = nid[t];
                 // dE/dx_j = dEdr u, dE/dx_i = -dEdr u;  F = -dE/dx
-                lds_add(&sF[3 * j + 0], -dEdr * u0);
-                lds_add(&sF[3 * j + 1], -dEdr * u1);
-                lds_add(&sF[3 * j + 2], -dEdr * u2);
+                Acc::add(&sF[3 * j + 0], -dEdr * u0);
+                Acc::add(&sF[3 * j + 1], -dEdr * u1);
+                Acc::add(&sF[3 * j + 2], -dEdr * u2);
                 fi0 += dEdr * u0;
                 fi1 += dEdr * u1;
                 fi2 += dEdr * u2;
@@ -1480,12 +1545,12 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
             const T gk1 = Drk * uk1 + Dc * (uj1 - cs_ * uk1) * ik;
             const T gk2 = Drk * uk2 + Dc * (uj2 - cs_ * uk2) * ik;
             const int jj = nid[j], kk = nid[k];
-            lds_add(&sF[3 * jj + 0], -gj0);
-            lds_add(&sF[3 * jj + 1], -gj1);
-            lds_add(&sF[3 * jj + 2], -gj2);
-            lds_add(&sF[3 * kk + 0], -gk0);
-            lds_add(&sF[3 * kk + 1], -gk1);
-            lds_add(&sF[3 * kk + 2], -gk2);
+            Acc::add(&sF[3 * jj + 0], -gj0);
+            Acc::add(&sF[3 * jj + 1], -gj1);
+            Acc::add(&sF[3 * jj + 2], -gj2);
+            Acc::add(&sF[3 * kk + 0], -gk0);
+            Acc::add(&sF[3 * kk + 1], -gk1);
+            Acc::add(&sF[3 * kk + 2], -gk2);
             fi0 += gj0 + gk0;
             fi1 += gj1 + gk1;
             fi2 += gj2 + gk2;
@@ -1496,23 +1561,21 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
             fi2 += __shfl_xor(fi2, off);
         }
         if (lane == 0) {
-            lds_add(&sF[3 * il + 0], fi0);
-            lds_add(&sF[3 * il + 1], fi1);
-            lds_add(&sF[3 * il + 2], fi2);
+            Acc::add(&sF[3 * il + 0], fi0);
+            Acc::add(&sF[3 * il + 1], fi1);
+            Acc::add(&sF[3 * il + 2], fi2);
         }
         wave_sync();
     }
     __syncthreads();
-    for (int t = tid; t < 3 * n; t += blockDim.x) {
-        T v = sF[t];
-        if (v != T(0)) gbl_add(&F[3 * (size_t)a0 + t], v);
-    }
+    for (int t = tid; t < 3 * n; t += blockDim.x) Acc::flush(sF[t], F, Fq, 3 * (size_t)a0 + t);
 }
 
 template <typename T>
-static size_t forces_lds(int max_apm, int cap, int S, int nw) {
+static size_t forces_lds(int max_apm, int cap, int S, int nw, bool fixed = false) {
     const int GL = kNR * S + kBlkPad * S * (S + 1) / 2;
-    return ChunkStage<T>::bytes(max_apm, cap) + lds_bytes<T>(3 * (size_t)max_apm) +
+    return ChunkStage<T>::bytes(max_apm, cap) +
+           (fixed ? lds_bytes<unsigned long long>(3 * (size_t)max_apm) : lds_bytes<T>(3 * (size_t)max_apm)) +
            lds_bytes<T>((size_t)nw * cap * kNbStride) + 2 * lds_bytes<int>((size_t)nw * cap) +
            lds_bytes<T>((size_t)nw * GL);
 }
@@ -1525,15 +1588,17 @@ hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
     if (c.Dp > 2 * 16 * 64) return hipErrorInvalidValue;
     dim3 grid(sh.B, (sh.max_apm + sh.chunk - 1) / sh.chunk);
     int nw = kWaves;
-    size_t lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw);
-    while (lds > kMaxLds && nw > 1) lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw /= 2);
+    const bool fixed = sh.force_fixed != 0;
+    size_t lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw, fixed);
+    while (lds > kMaxLds && nw > 1) lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw /= 2, fixed);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    auto kern = c.nZ == 4 ? k_forces<P, 4> : k_forces<P, 8>;
+    auto kern = fixed ? (c.nZ == 4 ? k_forces<P, 4, true> : k_forces<P, 8, true>)
+                      : (c.nZ == 4 ? k_forces<P, 4, false> : k_forces<P, 8, false>);
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("forces", st);
     hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.chunk, sh.cap_nbr,
-                       mol_off, species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.dG, F);
+                       mol_off, species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.dG, F, w.Fq);
     tm.e("forces", st);
     return hipGetLastError();
 }
@@ -1827,6 +1892,9 @@ template hipError_t launch_forces_tan<PrecF32>(const Shape&, const AevConst<floa
 // ==========================================================================
 // energies: one wave per molecule, FP64 sum of the atomic energies in a fixed
 // order.  e_atom = scale * ( mean_m (sum_t Epart + b4) ) + sae_scaled.
+// With fixed-point force sums (Fq != null) the same wave also turns its
+// molecule's integer force sums into F.  accumulate adds E (and F) to what
+// the outputs hold.
 template <typename P>
 __global__ __launch_bounds__(256) void k_energy(int A, int B, int M, int NT, double scale,
                                                 const int32_t* __restrict__ mol_off,
@@ -1835,12 +1903,20 @@ __global__ __launch_bounds__(256) void k_energy(int A, int B, int M, int NT, dou
                                                 const typename P::TA* __restrict__ Epart,
                                                 const typename P::TA* __restrict__ b4,
                                                 const double* __restrict__ sae,
-                                                double* __restrict__ E) {
+                                                double* __restrict__ E,
+                                                const unsigned long long* __restrict__ Fq,
+                                                typename P::T* __restrict__ F, int accumulate) {
+    typedef typename P::T T;
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = lane_id();
     if (b >= B) return;
     int a0 = mol_off[b], a1 = mol_off[b + 1];
     if (a0 < 0 || a1 < a0 || a1 > A) a1 = a0 = 0;
+    if (Fq)
+        for (int t = 3 * a0 + lane; t < 3 * a1; t += 64) {
+            const T f = (T)((double)(long long)Fq[t] * (1.0 / kForceFix));
+            F[t] = accumulate ? F[t] + f : f;
+        }
     double acc = 0.0;
     for (int a = a0 + lane; a < a1; a += 64) {
         int s = species[a];
@@ -1855,17 +1931,21 @@ __global__ __launch_bounds__(256) void k_energy(int A, int B, int M, int NT, dou
         acc += scale * (e / M) + sae[s];
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) E[b] = (a1 > a0) ? acc : 0.0;
+    if (lane == 0) {
+        const double v = (a1 > a0) ? acc : 0.0;
+        E[b] = accumulate ? E[b] + v : v;
+    }
 }
 
 template <typename P>
 hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t* mol_off,
-                         const int32_t* species, Work<P>& w, double* E, hipStream_t st,
-                         const Timer& tm) {
+                         const int32_t* species, Work<P>& w, double* E, typename P::T* F,
+                         bool accumulate, hipStream_t st, const Timer& tm) {
     tm.b("energy", st);
     hipLaunchKernelGGL(k_energy<P>, dim3((sh.B + 3) / 4), dim3(256), 0, st, sh.A, sh.B, sh.M,
                        w.epart_nt, sh.energy_scale, mol_off, species, sh.S, w.row_of_atom,
-                       w.Epart, wt.b4, wt.sae, E);
+                       w.Epart, wt.b4, wt.sae, E, (sh.force_fixed && F) ? w.Fq : nullptr, F,
+                       accumulate ? 1 : 0);
     tm.e("energy", st);
     return hipGetLastError();
 }
@@ -1875,7 +1955,7 @@ hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t
                                        hipStream_t, const Timer&);                             \
     template hipError_t launch_neighbours<P>(const Shape&, const AevConst<P::T>&,              \
                                              const int32_t*, const int32_t*, const P::T*,      \
-                                             P::T*, Work<P>&, hipStream_t, const Timer&);      \
+                                             P::T*, bool, Work<P>&, hipStream_t, const Timer&); \
     template hipError_t launch_aev<P>(const Shape&, const AevConst<P::T>&, const int32_t*,     \
                                       const int32_t*, const P::T*, Work<P>&, P::T*,            \
                                       hipStream_t, const Timer&);                              \
@@ -1886,8 +1966,8 @@ hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t
                                           const int32_t*, const P::T*, const P::T*, Work<P>&,  \
                                           P::TS*, hipStream_t, const Timer&);                  \
     template hipError_t launch_energy<P>(const Shape&, const DevWeights<P>&, const int32_t*,   \
-                                         const int32_t*, Work<P>&, double*, hipStream_t,       \
-                                         const Timer&);
+                                         const int32_t*, Work<P>&, double*, P::T*, bool,       \
+                                         hipStream_t, const Timer&);
 
 NNP_INST(PrecF64)
 NNP_INST(PrecF32)

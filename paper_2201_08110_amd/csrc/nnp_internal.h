@@ -80,6 +80,7 @@ constexpr int kMaxNA = 16;       // angular-distance shifts (<= 32 / 1)
 constexpr int kMaxAtomsPerMol = 1024;
 constexpr int kPrepBlock = 1024;   // atoms per block of the bucketing kernels
 constexpr int kMaxNeighbours = 192;
+constexpr int kZLut = 128;       // atomic numbers a handle's element table may hold: 1..127
 
 // featuriser constants, passed by value to the kernels
 template <typename T> struct AevConst {
@@ -114,6 +115,9 @@ template <typename P> struct Work {
     int32_t* blk;           // [2][n_blocks][kMaxSpecies]  per-block counts / bases
     BucketInfo* info;
     int32_t* flag;
+    const int8_t* zlut;     // [kZLut] element index of each atomic number (-1: none), or null
+                            // when batches carry element indices
+    int32_t* sp;            // [A]  element indices mapped from atomic numbers (zlut != null)
     uint16_t* nbr;          // [A][cap_nbr]  local indices, angular (r < rca) first
     int32_t* nbr_cnt;       // [A]  n_ang | (n_all << 16)
     TS* G;                  // [Rcap][Dp]
@@ -125,6 +129,7 @@ template <typename P> struct Work {
     TA* Epart;              // [Rcap][M][epart_nt]  per-row energy partials
     int epart_nt;           // partials per row and model (set by launch_mlp)
     TA* dG;                 // [Rcap][Dp]
+    unsigned long long* Fq; // [A][3]  fixed-point force sums (2^32 units, two's complement)
 };
 
 // extra workspace of the training backward (allocated on its first call)
@@ -156,7 +161,7 @@ template <> struct FragK<bf16_t> { static constexpr int KM = 32, KL = 8; };
 // A [N][K] row-major matrix in fragment order: fragment (n-tile t, k-step q)
 // occupies 64 KL consecutive elements, lane l's KL elements at l KL, so one
 // wave reads a fragment with one contiguous load.
-template <typename TS> inline size_t frag_index(int n, int k, int K) {
+template <typename TS> __host__ __device__ inline size_t frag_index(int n, int k, int K) {
     constexpr int KM = FragK<TS>::KM, KL = FragK<TS>::KL;
     const int t = n / 16, r = n % 16, q = k / KM, kk = k % KM;
     const int lane = r + 16 * (kk / KL);
@@ -180,6 +185,17 @@ template <typename P> struct DevWeights {
     double* sae;                   // [S] FP64 (already multiplied by energy_scale)
 };
 
+// where each packed parameter goes: the uniform packed layout (per-element
+// networks already mapped into it) and the padded device widths
+struct ParamPack {
+    int S, M, D, Dp, H1, H2, H3;   // device widths (hidden widths padded to 64)
+    int o1, o2;                    // widths of the packed layout's first two hidden layers
+    long net, offb1, offW2, offb2, offW3, offb3, offw4, offb4;
+};
+template <typename P, typename TSRC>
+hipError_t launch_set_params(int64_t n, const TSRC* src, const int32_t* map, const ParamPack& pk,
+                             const DevWeights<P>& dw, hipStream_t st);
+
 struct Shape {
     int S, M, D, Dp, H1, H2, H3;       // H* padded to multiples of 64
     int A, B;                          // atoms, molecules of this call
@@ -197,6 +213,7 @@ struct Shape {
     int cell_min;                      // molecules above this many atoms use cutoff cells
     int tail_tile;                     // fused kernel tile variant (1, 2 or 3)
     int chunk;                         // central atoms per featuriser / force workgroup (4, 8, 16)
+    int force_fixed;                   // 1: forces summed in 64-bit fixed point (bitwise reproducible)
 };
 
 // kernel timing hook (runtime-side); launchers call these around launches
@@ -247,7 +264,7 @@ hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* s
 template <typename P>
 hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
                              const int32_t* mol_off, const int32_t* species,
-                             const typename P::T* x, typename P::T* F_zero, Work<P>& w,
+                             const typename P::T* x, typename P::T* F, bool accumulate, Work<P>& w,
                              hipStream_t st, const Timer& tm);
 template <typename P>
 hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
@@ -301,7 +318,7 @@ hipError_t launch_grad_coords(int A, const int32_t* mol_of_atom, const double* g
                               const typename P::T* F, typename P::T* gx, hipStream_t st);
 template <typename P>
 hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t* mol_off,
-                         const int32_t* species, Work<P>& w, double* E, hipStream_t st,
-                         const Timer& tm);
+                         const int32_t* species, Work<P>& w, double* E, typename P::T* F,
+                         bool accumulate, hipStream_t st, const Timer& tm);
 
 }  // namespace nnp

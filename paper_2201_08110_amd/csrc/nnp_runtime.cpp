@@ -57,11 +57,12 @@ struct EventPair {
 // one captured evaluation, valid for exactly these shapes, pointers and stream
 struct GraphEntry {
     int A = 0, B = 0;
+    uint32_t flags = 0;
     const void* ptr[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipStream_t stream = nullptr;
     hipGraphExec_t exec = nullptr;
-    bool same(int a, int b, const void* const* p, hipStream_t s) const {
-        if (a != A || b != B || s != stream) return false;
+    bool same(int a, int b, uint32_t f, const void* const* p, hipStream_t s) const {
+        if (a != A || b != B || f != flags || s != stream) return false;
         for (int i = 0; i < 5; ++i)
             if (p[i] != ptr[i]) return false;
         return true;
@@ -102,6 +103,7 @@ struct nnp_handle {
     Work<PrecF32> k32{};
     Work<PrecBF16> k16{};
     int32_t* flag = nullptr;
+    int8_t* zlut = nullptr;       // device [kZLut]: element of each atomic number, or null
     hipStream_t last_stream = nullptr;
 
     // training backward workspace (allocated on its first call)
@@ -116,7 +118,7 @@ struct nnp_handle {
     std::vector<GraphEntry> graphs;
 
     // tunable knobs as set by the caller (0 = automatic)
-    int32_t knob[NNP_N_KNOBS] = {0, 0, 0, 0, 0, 0, 0};
+    int32_t knob[NNP_N_KNOBS] = {};
 
     // timing
     bool timing = false;
@@ -337,9 +339,12 @@ template <typename P> nnp_status alloc_work(nnp_handle* h, Work<P>& w) {
     ALLOC(DZ1, sizeof(TS) * R * M * sh.H1);
     ALLOC(Epart, sizeof(TA) * R * M * (sh.H3 / 64));
     ALLOC(dG, sizeof(TA) * R * sh.Dp);
+    ALLOC(Fq, sizeof(unsigned long long) * 3 * A);
+    if (h->zlut) ALLOC(sp, sizeof(int32_t) * A);
 #undef ALLOC
     w.epart_nt = sh.H3 / 64;
     w.flag = h->flag;
+    w.zlut = h->zlut;
     // every row index the kernels may read must be in range from the start
     HIP_TRY(hipMemset(w.row_of_atom, 0, sizeof(int32_t) * A));
     HIP_TRY(hipMemset(w.nbr_cnt, 0, sizeof(int32_t) * A));
@@ -357,7 +362,7 @@ nnp_status check_batch(const nnp_handle* h, const nnp_batch* b) {
     if (b->n_atoms > h->max_atoms) return fail(NNP_E_CAPACITY, "n_atoms exceeds max_atoms");
     if (!b->mol_offsets) return fail(NNP_E_INVALID, "null mol_offsets");
     if (b->n_atoms > 0 && !b->species) return fail(NNP_E_INVALID, "null species");
-    if (b->flags & ~NNP_FLAG_GRAPH) return fail(NNP_E_INVALID, "unknown flags");
+    if (b->flags & ~(NNP_FLAG_GRAPH | NNP_FLAG_ACCUMULATE)) return fail(NNP_E_INVALID, "unknown flags");
     if ((b->flags & NNP_FLAG_GRAPH) && !b->stream)
         return fail(NNP_E_INVALID, "graph replay needs a non-null stream");
     return NNP_OK;
@@ -404,6 +409,7 @@ int32_t knob_value(const nnp_handle* h, int k) {
     case NNP_KNOB_L1_PATH:
         if (v) return v;
         return l1_regs_supported(h) ? 2 : 1;
+    case NNP_KNOB_FORCE_SUM: return v ? v : 1;
     }
     return 0;
 }
@@ -417,8 +423,16 @@ void apply_knobs(nnp_handle* h) {
     h->shape.gemm_waves = knob_value(h, NNP_KNOB_GEMM_WAVES);
     h->shape.chunk = knob_value(h, NNP_KNOB_ATOM_CHUNK);
     h->shape.l1_path = knob_value(h, NNP_KNOB_L1_PATH);
+    h->shape.force_fixed = knob_value(h, NNP_KNOB_FORCE_SUM) == 2;
     for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     h->graphs.clear();
+}
+
+// element indices of the batch's atoms as the kernels after bucketing read
+// them: the batch's own array, or the indices the bucketing kernels mapped
+// from atomic numbers
+template <typename P> const int32_t* elements_of(const Work<P>& w, const nnp_batch* b) {
+    return w.zlut ? w.sp : b->species;
 }
 
 template <typename P>
@@ -428,21 +442,24 @@ nnp_status run_forward(nnp_handle* h, const nnp_batch* b, const typename P::T* x
     Shape sh = h->shape;
     sh.A = b->n_atoms;
     sh.B = b->n_mols;
+    const bool acc = (b->flags & NNP_FLAG_ACCUMULATE) != 0;
     hipStream_t st = (hipStream_t)b->stream;
     h->last_stream = st;
     Work<P>& w = work_of<P>(h);
     const AevConst<T>& c = const_of<T>(h);
     Timer tm = make_timer(h);
     HIP_TRY(launch_prep<P>(sh, b->mol_offsets, b->species, w, st, tm));
+    const int32_t* sp = elements_of(w, b);
     if (sh.A > 0) {
-        HIP_TRY(launch_neighbours<P>(sh, c, b->mol_offsets, b->species, x, F, w, st, tm));
-        HIP_TRY(launch_aev<P>(sh, c, b->mol_offsets, b->species, x, w, aev_out, st, tm));
+        HIP_TRY(launch_neighbours<P>(sh, c, b->mol_offsets, sp, x, F, acc, w, st, tm));
+        HIP_TRY(launch_aev<P>(sh, c, b->mol_offsets, sp, x, w, aev_out, st, tm));
     }
     if (aev_out) return NNP_OK;
     if (sh.A > 0) HIP_TRY(launch_mlp<P>(sh, weights_of<P>(h), w, st, tm));
     if (F && sh.A > 0)
-        HIP_TRY(launch_forces<P>(sh, c, b->mol_offsets, b->species, x, w, F, st, tm));
-    HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), b->mol_offsets, b->species, w, E, st, tm));
+        HIP_TRY(launch_forces<P>(sh, c, b->mol_offsets, sp, x, w, F, st, tm));
+    HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), b->mol_offsets, sp, w, E, sh.A > 0 ? F : nullptr, acc,
+                             st, tm));
     return NNP_OK;
 }
 
@@ -455,7 +472,7 @@ nnp_status run_forward_graph(nnp_handle* h, const nnp_batch* b, const typename P
     hipStream_t st = (hipStream_t)b->stream;
     const void* key[5] = {b->mol_offsets, b->species, x, E, F};
     for (size_t i = 0; i < h->graphs.size(); ++i)
-        if (h->graphs[i].same(b->n_atoms, b->n_mols, key, st)) {
+        if (h->graphs[i].same(b->n_atoms, b->n_mols, b->flags, key, st)) {
             h->last_stream = st;
             HIP_TRY(hipGraphLaunch(h->graphs[i].exec, st));
             return NNP_OK;
@@ -475,6 +492,7 @@ nnp_status run_forward_graph(nnp_handle* h, const nnp_batch* b, const typename P
     GraphEntry ge;
     ge.A = b->n_atoms;
     ge.B = b->n_mols;
+    ge.flags = b->flags;
     for (int i = 0; i < 5; ++i) ge.ptr[i] = key[i];
     ge.stream = st;
     e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
@@ -529,15 +547,19 @@ template <typename P> nnp_status alloc_train(nnp_handle* h) {
 }
 
 template <typename P>
-nnp_status run_backward(nnp_handle* h, const nnp_batch* b, const typename P::T* x,
+nnp_status run_backward(nnp_handle* h, const nnp_batch* bin, const typename P::T* x,
                         const double* gE, const typename P::T* gF, typename P::TA* gp,
                         typename P::T* gx) {
     typedef typename P::T T;
     nnp_status rc = alloc_train<P>(h);
     if (rc) return rc;
+    nnp_batch bb = *bin;   // the internal evaluations overwrite their outputs, eagerly
+    bb.flags = 0;
+    const nnp_batch* b = &bb;
     Shape sh = h->shape;
     sh.A = b->n_atoms;
     sh.B = b->n_mols;
+    sh.force_fixed = 0;    // the force contraction below writes F directly
     hipStream_t st = (hipStream_t)b->stream;
     h->last_stream = st;
     Work<P>& w = work_of<P>(h);
@@ -560,14 +582,15 @@ nnp_status run_backward(nnp_handle* h, const nnp_batch* b, const typename P::T* 
         if (rc) return rc;
         HIP_TRY(launch_fill<P>(gx, 3 * (size_t)sh.A, st));
         if (sh.A > 0)
-            HIP_TRY(launch_forces_tan<P>(sh, c, b->mol_offsets, b->species, x, gF, w, gx, st, tm));
+            HIP_TRY(launch_forces_tan<P>(sh, c, b->mol_offsets, elements_of(w, b), x, gF, w, gx, st, tm));
     }
     HIP_TRY(launch_prep<P>(sh, b->mol_offsets, b->species, w, st, tm));
+    const int32_t* sp = elements_of(w, b);
     if (sh.A > 0) {
-        HIP_TRY(launch_neighbours<P>(sh, c, b->mol_offsets, b->species, x, (T*)nullptr, w, st, tm));
-        HIP_TRY(launch_aev<P>(sh, c, b->mol_offsets, b->species, x, w, (T*)nullptr, st, tm));
+        HIP_TRY(launch_neighbours<P>(sh, c, b->mol_offsets, sp, x, (T*)nullptr, false, w, st, tm));
+        HIP_TRY(launch_aev<P>(sh, c, b->mol_offsets, sp, x, w, (T*)nullptr, st, tm));
         if (has_gF)
-            HIP_TRY(launch_aev_jvp<P>(sh, c, b->mol_offsets, b->species, x, gF, w, tw.GD, st, tm));
+            HIP_TRY(launch_aev_jvp<P>(sh, c, b->mol_offsets, sp, x, gF, w, tw.GD, st, tm));
     }
     if (!has_gF) {
         // the reverse steps read the tangent activations: make them exact zeros
@@ -594,7 +617,7 @@ nnp_status run_backward(nnp_handle* h, const nnp_batch* b, const typename P::T* 
         // gx = tangent - K(gE g - gdot) = -gE F - H gF.
         HIP_TRY(launch_l1_bwd<P>(sh, weights_of<P>(h), w, st, tm));
         HIP_TRY(launch_fill<P>((T*)h->train_F, 3 * (size_t)sh.A, st));
-        HIP_TRY(launch_forces<P>(sh, c, b->mol_offsets, b->species, x, w, (T*)h->train_F, st, tm));
+        HIP_TRY(launch_forces<P>(sh, c, b->mol_offsets, sp, x, w, (T*)h->train_F, st, tm));
         HIP_TRY(launch_sub<T>(3 * (size_t)sh.A, (const T*)h->train_F, gx, st));
     }
     return NNP_OK;
@@ -610,7 +633,8 @@ const char* knob_name(int k) {
          : k == NNP_KNOB_CELL_MIN ? "cell_min"
          : k == NNP_KNOB_TAIL_TILE ? "tail_tile"
          : k == NNP_KNOB_GEMM_WAVES ? "gemm_waves"
-         : k == NNP_KNOB_ATOM_CHUNK ? "atom_chunk" : "l1_path";
+         : k == NNP_KNOB_ATOM_CHUNK ? "atom_chunk"
+         : k == NNP_KNOB_L1_PATH ? "l1_path" : "force_sum";
 }
 
 std::string tune_key(const nnp_handle* h) {
@@ -644,9 +668,11 @@ bool cache_lookup(const char* path, const std::string& key, int32_t knobs[NNP_N_
         if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
         int32_t v[NNP_N_KNOBS];
         bool ok = true;
-        for (int k = 0; k < NNP_N_KNOBS; ++k) ok = ok && json_int(line, knob_name(k), v[k]);
+        for (int k = 0; k < NNP_N_KNOBS; ++k)
+            if (k != NNP_KNOB_FORCE_SUM) ok = ok && json_int(line, knob_name(k), v[k]);
         if (ok) {
-            for (int k = 0; k < NNP_N_KNOBS; ++k) knobs[k] = v[k];
+            for (int k = 0; k < NNP_N_KNOBS; ++k)
+                if (k != NNP_KNOB_FORCE_SUM) knobs[k] = v[k];
             hit = true;
         }
     }
@@ -704,6 +730,8 @@ nnp_status autotune(nnp_handle* h, const nnp_batch* b, const typename P::T* x, i
             cand = {4, 8, 16};
         } else if (k == NNP_KNOB_L1_PATH) {
             if (l1_regs_supported(h)) cand = {1, 2};
+        } else if (k == NNP_KNOB_FORCE_SUM) {
+            // reproducibility is the caller's choice: never tuned
         } else {
             for (int c : {32, 64, 128, 256})
                 if (c < h->max_apm) cand.push_back(c);
@@ -792,6 +820,20 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     if (p->max_atoms_per_mol > kMaxAtomsPerMol)
         return fail(NNP_E_UNSUPPORTED, "max_atoms_per_mol is limited to 1024");
     if (p->max_atoms > (1 << 26)) return fail(NNP_E_INVALID, "max_atoms too large");
+    if (p->create_flags & ~NNP_CREATE_TRAINING) return fail(NNP_E_INVALID, "unknown creation flags");
+    if ((p->create_flags & NNP_CREATE_TRAINING) && p->precision == NNP_PREC_BF16_MLP)
+        return fail(NNP_E_UNSUPPORTED, "the training backward runs on FP32 or FP64 handles");
+    // element table: atomic number -> element index
+    std::vector<int8_t> lut;
+    if (p->atomic_numbers) {
+        lut.assign(kZLut, -1);
+        for (int s = 0; s < S; ++s) {
+            const int z = p->atomic_numbers[s];
+            if (z < 1 || z >= kZLut) return fail(NNP_E_SPECIES, "atomic numbers must be in 1..127");
+            if (lut[z] >= 0) return fail(NNP_E_SPECIES, "atomic number listed twice in the element table");
+            lut[z] = (int8_t)s;
+        }
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return fail(NNP_E_DEVICE, "no HIP device available");
@@ -889,6 +931,13 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     nnp_status rc = e == hipSuccess ? NNP_OK : fail(NNP_E_NOMEM, "flag allocation failed");
     if (rc == NNP_OK && hipMemset(h->flag, 0, sizeof(int32_t)) != hipSuccess)
         rc = fail(NNP_E_DEVICE, "hipMemset failed");
+    if (rc == NNP_OK && !lut.empty()) {
+        h->zlut = (int8_t*)h->dalloc(kZLut, e);
+        if (e != hipSuccess)
+            rc = fail(NNP_E_NOMEM, "element table allocation failed");
+        else if (hipMemcpy(h->zlut, lut.data(), kZLut, hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(NNP_E_DEVICE, "element table upload failed");
+    }
     if (rc == NNP_OK && h->het) {
         h->dmap = (int32_t*)h->dalloc(sizeof(int32_t) * h->pmap.size(), e);
         if (e != hipSuccess)
@@ -908,6 +957,8 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
             if (rc == NNP_OK) rc = alloc_work<PrecBF16>(h, h->k16);
         }
     }
+    if (rc == NNP_OK && (p->create_flags & NNP_CREATE_TRAINING))
+        rc = p->precision == NNP_PREC_FP64 ? alloc_train<PrecF64>(h) : alloc_train<PrecF32>(h);
     if (rc != NNP_OK) {
         std::string msg = g_err;
         nnp_destroy(h);
@@ -1004,6 +1055,47 @@ nnp_status nnp_set_weights(nnp_handle* h, const double* weights) {
     return upload_weights<PrecBF16>(h, h->w16, weights, false);
 }
 
+nnp_status nnp_set_params(nnp_handle* h, const void* params, int32_t type, void* stream) {
+    if (!h || !params) return fail(NNP_E_INVALID, "null handle or params");
+    if (type != NNP_PREC_FP64 && type != NNP_PREC_FP32)
+        return fail(NNP_E_INVALID, "parameter type must be NNP_PREC_FP64 or NNP_PREC_FP32");
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    const NetLayout& nl = h->nl;
+    ParamPack pk{};
+    pk.S = h->S;
+    pk.M = h->M;
+    pk.D = h->D;
+    pk.Dp = h->shape.Dp;
+    pk.H1 = h->shape.H1;
+    pk.H2 = h->shape.H2;
+    pk.H3 = h->shape.H3;
+    pk.o1 = nl.o1;
+    pk.o2 = nl.o2;
+    pk.net = nl.net;
+    pk.offb1 = nl.offb1;
+    pk.offW2 = nl.offW2;
+    pk.offb2 = nl.offb2;
+    pk.offW3 = nl.offW3;
+    pk.offb3 = nl.offb3;
+    pk.offw4 = nl.offw4;
+    pk.offb4 = nl.offb4;
+    const int32_t* map = h->het ? h->dmap : nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (h->precision == NNP_PREC_FP64)
+        e = type == NNP_PREC_FP64 ? launch_set_params<PrecF64>(h->n_params, (const double*)params, map, pk, h->w64, st)
+                                  : launch_set_params<PrecF64>(h->n_params, (const float*)params, map, pk, h->w64, st);
+    else if (h->precision == NNP_PREC_FP32)
+        e = type == NNP_PREC_FP64 ? launch_set_params<PrecF32>(h->n_params, (const double*)params, map, pk, h->w32, st)
+                                  : launch_set_params<PrecF32>(h->n_params, (const float*)params, map, pk, h->w32, st);
+    else
+        e = type == NNP_PREC_FP64 ? launch_set_params<PrecBF16>(h->n_params, (const double*)params, map, pk, h->w16, st)
+                                  : launch_set_params<PrecBF16>(h->n_params, (const float*)params, map, pk, h->w16, st);
+    if (e != hipSuccess) return fail(NNP_E_DEVICE, std::string("parameter update: ") + hipGetErrorString(e));
+    return NNP_OK;
+}
+
 int64_t nnp_num_params(const nnp_handle* h) { return h ? h->n_params : -1; }
 
 int32_t nnp_aev_dim(const nnp_handle* h) { return h ? h->D : -1; }
@@ -1094,6 +1186,8 @@ nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value) {
         if (value == 2 && !l1_regs_supported(h))
             return fail(NNP_E_UNSUPPORTED, "register-operand layer-1 GEMMs need BF16 and 128-row buckets");
         ok = ok || value == 1 || value == 2;
+    } else if (knob == NNP_KNOB_FORCE_SUM) {
+        ok = ok || value == 1 || value == 2;
     } else {
         ok = ok || (value >= 16 && value <= kMaxAtomsPerMol);
     }
@@ -1126,7 +1220,8 @@ nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, i
     std::string timings;
     if (hit) {
         if (!h->graphs.empty()) (void)hipDeviceSynchronize();
-        for (int k = 0; k < NNP_N_KNOBS; ++k) h->knob[k] = cached[k];
+        for (int k = 0; k < NNP_N_KNOBS; ++k)
+            if (k != NNP_KNOB_FORCE_SUM) h->knob[k] = cached[k];
         apply_knobs(h);
     } else {
         if (!h->graphs.empty()) (void)hipDeviceSynchronize();
@@ -1160,6 +1255,25 @@ nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, i
 
 }  // extern "C"
 
+namespace {
+// MM atoms per NNP-side wave: 16, widened (up to 512, the LDS limit of four
+// FP64 chunks) by 16 per 64k MM atoms so the partials stay bounded
+int coupling_chunk(int max_mm) {
+    return 16 * std::min(32, std::max(1, (max_mm + 64 * 1024 - 1) / (64 * 1024)));
+}
+
+nnp_status check_coupling_args(int32_t n_nnp, const void* x_nnp, const void* par_nnp, int32_t n_mm,
+                               const void* x_mm, const void* par_mm, const double* out_E,
+                               const void* F_nnp, const void* F_mm, uint32_t flags) {
+    if (!out_E) return fail(NNP_E_INVALID, "null out_E");
+    if (n_nnp < 0 || n_mm < 0) return fail(NNP_E_INVALID, "negative atom count");
+    if (n_nnp > 0 && (!x_nnp || !par_nnp || !F_nnp)) return fail(NNP_E_INVALID, "null NNP array");
+    if (n_mm > 0 && (!x_mm || !par_mm || !F_mm)) return fail(NNP_E_INVALID, "null MM array");
+    if (flags & ~NNP_FLAG_ACCUMULATE) return fail(NNP_E_INVALID, "unknown flag");
+    return NNP_OK;
+}
+}  // namespace
+
 struct nnp_coupling {
     nnp::CouplingShape cs{};
     int precision = NNP_PREC_FP32;
@@ -1192,9 +1306,7 @@ nnp_status nnp_coupling_create(int32_t precision, int32_t max_nnp, int32_t max_m
     c->cs.cutoff = cutoff;
     c->cs.max_nnp = max_nnp;
     c->cs.max_mm = max_mm;
-    // MM atoms per NNP-side wave: 16, widened (up to 512, the LDS limit of
-    // four FP64 chunks) by 16 per 64k MM atoms so the partials stay bounded
-    c->cs.chunk = 16 * std::min(32, std::max(1, (max_mm + 64 * 1024 - 1) / (64 * 1024)));
+    c->cs.chunk = coupling_chunk(max_mm);
     const size_t tsz = precision == NNP_PREC_FP64 ? sizeof(double) : sizeof(float);
     const size_t n_eblk = (size_t)(max_mm + kCoupleMmPerBlock - 1) / kCoupleMmPerBlock;
     const size_t n_chunks = (size_t)(max_mm + c->cs.chunk - 1) / c->cs.chunk;
@@ -1220,13 +1332,11 @@ void nnp_coupling_destroy(nnp_coupling* c) {
 nnp_status nnp_coupling_eval(nnp_coupling* c, int32_t n_nnp, const void* x_nnp, const void* par_nnp,
                              int32_t n_mm, const void* x_mm, const void* par_mm, double* out_E,
                              void* F_nnp, void* F_mm, void* stream, uint32_t flags) {
-    if (!c || !out_E) return fail(NNP_E_INVALID, "null coupling handle or out_E");
-    if (n_nnp < 0 || n_mm < 0) return fail(NNP_E_INVALID, "negative atom count");
+    if (!c) return fail(NNP_E_INVALID, "null coupling handle");
+    nnp_status rc = check_coupling_args(n_nnp, x_nnp, par_nnp, n_mm, x_mm, par_mm, out_E, F_nnp, F_mm, flags);
+    if (rc) return rc;
     if (n_nnp > c->cs.max_nnp || n_mm > c->cs.max_mm)
         return fail(NNP_E_CAPACITY, "coupling system exceeds the capacity given at creation");
-    if (n_nnp > 0 && (!x_nnp || !par_nnp || !F_nnp)) return fail(NNP_E_INVALID, "null NNP array");
-    if (n_mm > 0 && (!x_mm || !par_mm || !F_mm)) return fail(NNP_E_INVALID, "null MM array");
-    if (flags & ~NNP_FLAG_ACCUMULATE) return fail(NNP_E_INVALID, "unknown flag");
     DeviceGuard dg(c->device);
     if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
     const bool acc = (flags & NNP_FLAG_ACCUMULATE) != 0;

@@ -17,6 +17,10 @@ LIB_PATH = os.path.join(_HERE, "libnnp_hip.so")
 
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 FLAG_GRAPH = 1
+FLAG_ACCUMULATE = 2
+CREATE_TRAINING = 1
+#: atomic numbers of the ANI-2x elements in index order H, C, N, O, F, S, Cl
+ANI2X_Z = (1, 6, 7, 8, 9, 16, 17)
 
 NNP_OK, NNP_E_INVALID, NNP_E_SPECIES, NNP_E_CAPACITY, NNP_E_NOMEM, NNP_E_DEVICE, \
     NNP_E_UNSUPPORTED = range(7)
@@ -42,6 +46,7 @@ class ModelParams(C.Structure):
         ("sae", C.POINTER(C.c_double)), ("energy_scale", C.c_double),
         ("precision", C.c_int32), ("max_atoms", C.c_int32), ("max_mols", C.c_int32),
         ("max_atoms_per_mol", C.c_int32), ("device", C.c_int32),
+        ("atomic_numbers", C.POINTER(C.c_int32)), ("create_flags", C.c_uint32),
     ]
 
 
@@ -54,20 +59,19 @@ _lib = None
 
 #: every symbol include/nnp.h declares
 EXPORTS = ("nnp_create", "nnp_destroy", "nnp_energy_forces", "nnp_energy_forces_f64", "nnp_aev",
-           "nnp_energy_forces_backward", "nnp_set_weights", "nnp_num_params", "nnp_aev_dim",
+           "nnp_energy_forces_backward", "nnp_set_weights", "nnp_set_params", "nnp_num_params",
+           "nnp_aev_dim",
            "nnp_get_device_status", "nnp_set_timing", "nnp_set_timing_only", "nnp_kernel_times",
            "nnp_last_error",
            "nnp_set_knob", "nnp_get_knob", "nnp_autotune",
            "nnp_coupling_create", "nnp_coupling_destroy", "nnp_coupling_eval")
 
-FLAG_ACCUMULATE = 2
-
 #: tunable knobs (include/nnp.h)
 (KNOB_MLP_PATH, KNOB_GEMM_STAGES, KNOB_CELL_MIN, KNOB_TAIL_TILE, KNOB_GEMM_WAVES, KNOB_ATOM_CHUNK,
- KNOB_L1_PATH) = range(7)
+ KNOB_L1_PATH, KNOB_FORCE_SUM) = range(8)
 KNOBS = {"mlp_path": KNOB_MLP_PATH, "gemm_stages": KNOB_GEMM_STAGES, "cell_min": KNOB_CELL_MIN,
          "tail_tile": KNOB_TAIL_TILE, "gemm_waves": KNOB_GEMM_WAVES, "atom_chunk": KNOB_ATOM_CHUNK,
-         "l1_path": KNOB_L1_PATH}
+         "l1_path": KNOB_L1_PATH, "force_sum": KNOB_FORCE_SUM}
 
 
 def load_library(path: str = LIB_PATH):
@@ -94,6 +98,8 @@ def load_library(path: str = LIB_PATH):
     lib.nnp_energy_forces_backward.restype = i32
     lib.nnp_set_weights.argtypes = [vp, P(d)]
     lib.nnp_set_weights.restype = i32
+    lib.nnp_set_params.argtypes = [vp, vp, i32, vp]
+    lib.nnp_set_params.restype = i32
     lib.nnp_num_params.argtypes = [vp]
     lib.nnp_num_params.restype = i64
     lib.nnp_aev_dim.argtypes = [vp]
@@ -138,7 +144,10 @@ class NNP:
 
     def __init__(self, hp: dict, weights, n_models: int, precision: str = "fp32",
                  max_atoms: int = 1024, max_mols: int = 64, max_atoms_per_mol: int = 128,
-                 device: int = 0, sae=None):
+                 device: int = 0, sae=None, atomic_numbers=None, training: bool = False):
+        """atomic_numbers: the element table (e.g. ANI2X_Z); batches then
+        pass atomic numbers as species.  training: allocate the training
+        backward's workspace now rather than on the first backward."""
         lib = load_library()
         self._keep = []
 
@@ -170,6 +179,11 @@ class NNP:
         p.precision = PREC[precision]
         p.max_atoms, p.max_mols, p.max_atoms_per_mol = max_atoms, max_mols, max_atoms_per_mol
         p.device = device
+        if atomic_numbers is not None:
+            z = np.ascontiguousarray(atomic_numbers, dtype=np.int32)
+            self._keep.append(z)
+            p.atomic_numbers = z.ctypes.data_as(C.POINTER(C.c_int32))
+        p.create_flags = CREATE_TRAINING if training else 0
         h = C.c_void_p()
         _check(lib.nnp_create(C.byref(p), C.byref(h)))
         self._keep = []
@@ -217,16 +231,20 @@ class NNP:
 
     # -- API ---------------------------------------------------------------
     def energy_forces(self, coords, species, mol_offsets, forces: bool = True, out=None,
-                      graph: bool = False, stream=None):
+                      graph: bool = False, stream=None, accumulate: bool = False):
         """Energies [B] (float64) and forces [A, 3] of a ragged batch.
 
         graph=True replays a captured HIP graph while shapes, tensors and the
-        stream stay the same (needs a non-default stream)."""
+        stream stay the same (needs a non-default stream).  accumulate=True
+        adds the results to the tensors given in `out`."""
         import torch
         self._need(coords, self.coord_dtype, "coords")
         self._need(species, torch.int32, "species")
         self._need(mol_offsets, torch.int32, "mol_offsets")
-        b = self._batch(species, mol_offsets, stream=stream, flags=FLAG_GRAPH if graph else 0)
+        if accumulate and out is None:
+            raise ValueError("accumulate needs the output tensors in `out`")
+        flags = (FLAG_GRAPH if graph else 0) | (FLAG_ACCUMULATE if accumulate else 0)
+        b = self._batch(species, mol_offsets, stream=stream, flags=flags)
         if out is None:
             E = torch.empty(b.n_mols, dtype=torch.float64, device=coords.device)
             F = torch.empty_like(coords) if forces else None
@@ -269,18 +287,41 @@ class NNP:
         _check(self.lib.nnp_set_weights(self.h, _dp(w)))
         self._synced = None
 
+    def set_params(self, params, stream=None):
+        """Replace the weights from a CUDA tensor (float64 or float32, packed
+        like the weights) on the device, enqueued on `stream` (torch's
+        current stream by default): no host round trip."""
+        import torch
+        if params.dtype == torch.float64:
+            typ = PREC["fp64"]
+        elif params.dtype == torch.float32:
+            typ = PREC["fp32"]
+        else:
+            raise TypeError("params must be float64 or float32")
+        self._need(params, params.dtype, "params")
+        if params.numel() != self.num_params:
+            raise ValueError(f"params has {params.numel()} values, the model {self.num_params}")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(self.lib.nnp_set_params(self.h, params.data_ptr(), typ, s.cuda_stream))
+        self._synced = None
+
     def sync_params(self, params):
-        """Upload a torch tensor of packed master weights unless it is the very
+        """Make the handle hold the weights in `params` unless it is the very
         tensor object uploaded last time with no in-place change since (torch's
         version counter).  The handle keeps a reference to that tensor, so a
         new tensor can never be mistaken for it through a reused address.
-        Writes that bypass the version counter (through `.data`) are not seen:
-        call set_weights after those."""
+        CUDA tensors are copied on the device (nnp_set_params), anything else
+        through host memory.  Writes that bypass the version counter (through
+        `.data`) are not seen: call set_weights or set_params after those."""
         import torch
         last = getattr(self, "_synced", None)
         if last is not None and last[0] is params and last[1] == params._version:
             return
-        self.set_weights(params.detach().to("cpu", dtype=torch.float64).numpy())
+        p = params.detach()
+        if p.is_cuda and p.dtype in (torch.float64, torch.float32):
+            self.set_params(p.contiguous())
+        else:
+            self.set_weights(p.to("cpu", dtype=torch.float64).numpy())
         self._synced = (params, params._version)
 
     @property
@@ -380,3 +421,4 @@ class Coupling:
                                           Fn.data_ptr(), Fm.data_ptr(), s.cuda_stream,
                                           FLAG_ACCUMULATE if accumulate else 0))
         return E, Fn, Fm
+

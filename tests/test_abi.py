@@ -82,6 +82,33 @@ def test_create_rejects_bad_element_widths(hp, change, code):
     assert h.value is None
 
 
+@pytest.mark.parametrize("table,code", [([1, 6, 7, 8, 9, 16, 6], 2), ([1, 6, 7, 8, 9, 16, 0], 2),
+                                        ([1, 6, 7, 8, 9, 16, 128], 2), ([-1, 6, 7, 8, 9, 16, 17], 2)])
+def test_create_rejects_bad_element_table(hp, table, code):
+    """An element table with a repeated or impossible atomic number is
+    refused at creation with NNP_E_SPECIES, before any device work."""
+    nnp, lib = _lib()
+    z = np.array(table, dtype=np.int32)
+    w = np.zeros(synth.net_size(hp["widths"]) * 7)
+    p, keep = _params(nnp, hp, w, atomic_numbers=z.ctypes.data_as(C.POINTER(C.c_int32)))
+    keep.append(z)
+    h = C.c_void_p(123)
+    assert lib.nnp_create(C.byref(p), C.byref(h)) == code
+    assert h.value is None
+    assert b"atomic number" in lib.nnp_last_error()
+
+
+@pytest.mark.parametrize("flags,prec,code", [(2, 1, 1), (1, 2, 6)])
+def test_create_rejects_bad_creation_flags(hp, flags, prec, code):
+    """Unknown creation flags; a training workspace on a BF16 handle."""
+    nnp, lib = _lib()
+    w = np.zeros(synth.net_size(hp["widths"]) * 7)
+    p, keep = _params(nnp, hp, w, create_flags=flags, precision=prec)
+    h = C.c_void_p(123)
+    assert lib.nnp_create(C.byref(p), C.byref(h)) == code
+    assert h.value is None
+
+
 def test_null_arguments():
     nnp, lib = _lib()
     h = C.c_void_p()
@@ -90,6 +117,7 @@ def test_null_arguments():
     assert lib.nnp_energy_forces_f64(None, None, None, None, None) == nnp.NNP_E_INVALID
     assert lib.nnp_aev(None, None, None, None) == nnp.NNP_E_INVALID
     assert lib.nnp_set_weights(None, None) == nnp.NNP_E_INVALID
+    assert lib.nnp_set_params(None, None, 0, None) == nnp.NNP_E_INVALID
     assert lib.nnp_num_params(None) == -1
     assert lib.nnp_aev_dim(None) == -1
     v = C.c_int32(0)
@@ -117,7 +145,7 @@ def test_knob_ids_match_header():
     assert ids == {"MLP_PATH": nnp.KNOB_MLP_PATH, "GEMM_STAGES": nnp.KNOB_GEMM_STAGES,
                    "CELL_MIN": nnp.KNOB_CELL_MIN, "TAIL_TILE": nnp.KNOB_TAIL_TILE,
                    "GEMM_WAVES": nnp.KNOB_GEMM_WAVES, "ATOM_CHUNK": nnp.KNOB_ATOM_CHUNK,
-                   "L1_PATH": nnp.KNOB_L1_PATH}
+                   "L1_PATH": nnp.KNOB_L1_PATH, "FORCE_SUM": nnp.KNOB_FORCE_SUM}
     assert set(nnp.KNOBS.values()) == set(ids.values())
 
 

@@ -3,13 +3,14 @@
 Tolerances (per molecule, kcal/mol and kcal/mol/A):
   FP64 handle     relative 1e-10 on energies and AEVs, 1e-9 on forces
   FP32 handle     |dE|/atoms <= 1e-4,  force RMSE <= 1e-3   (target accuracy)
-  BF16-MLP handle bounds derived in the tests from bf16's 8-bit mantissa
+  BF16-MLP handle |dE|/atoms <= 0.1 sqrt(8/M), force RMSE <= 1e-2 RMS(F)
+                  (derived in tests/gpu_util.py from bf16's 8-bit significand)
 """
 import numpy as np
 import pytest
 
 from paper_2201_08110_amd import synth
-from tests.gpu_util import errors, make_handle, oracle_inputs, to_device, torch_cuda
+from tests.gpu_util import BF16_FORCE_RMS_FRAC, bf16_de_bar, errors, make_handle, oracle_inputs, to_device, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -104,11 +105,10 @@ def test_batch_equals_single_molecules(hp):
 def test_bf16_mlp_replicas(orc, hp, n_mols):
     """BF16 network GEMMs (FP32 accumulate), FP32 AEV and forces, 16 replicas.
 
-    Bound: operands are rounded to bf16 (relative 2^-9 each); with K-term dot
-    products of random-sign terms the relative error of an atomic energy
-    stays near 2^-9 * sqrt(layers), i.e. ~5e-3 of a typical |e| of ~200
-    kcal/mol -> ~1 kcal/mol/atom; forces likewise ~5e-3 relative.  The test
-    asserts |dE|/atom <= 2 kcal/mol and force RMSE <= 1e-2 * RMS(F).
+    Bound (derived in tests/gpu_util.py from bf16's 8-bit significand): the
+    ensemble energy per atom is off by ~0.03 kcal/mol at M = 8; the test
+    asserts |dE|/atom <= 0.1 kcal/mol (~3 sigma) and force RMSE <= 1e-2 *
+    RMS(F).
     """
     torch = torch_cuda()
     b = synth.config_batch(5, n_mols=n_mols)   # 768 atoms: one bucketing block; 1920: three
@@ -119,8 +119,8 @@ def test_bf16_mlp_replicas(orc, hp, n_mols):
     frms = np.sqrt(np.mean(Fo ** 2))
     print("bf16: |dE|/atom max", dE.max(), "median", np.median(dE), "force RMSE max", rmse.max(),
           "RMS(F)", frms)
-    assert dE.max() <= 2.0
-    assert rmse.max() <= 1e-2 * frms
+    assert dE.max() <= bf16_de_bar(8)
+    assert rmse.max() <= BF16_FORCE_RMS_FRAC * frms
 
 
 def test_device_flags(hp):
@@ -252,4 +252,4 @@ def test_full_size_replicas_sampled(orc, hp):
     dE, rmse = errors(E[pick], F[rows], Eo, Fo, sub_off)
     frms = np.sqrt(np.mean(Fo ** 2))
     print("full size, sampled", pick, "|dE|/atom max", dE.max(), "RMSE max", rmse.max(), "RMS(F)", frms)
-    assert dE.max() <= 2.0 and rmse.max() <= 1e-2 * frms
+    assert dE.max() <= bf16_de_bar(8) and rmse.max() <= BF16_FORCE_RMS_FRAC * frms
