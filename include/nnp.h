@@ -379,6 +379,32 @@ nnp_status nnp_coupling_eval(nnp_coupling* c, int32_t n_nnp, const void* x_nnp, 
                              int32_t n_mm, const void* x_mm, const void* par_mm, double* out_E,
                              void* F_nnp, void* F_mm, void* stream, uint32_t flags);
 
+/*
+ * nnp_coupling_eval without a handle and without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, result
+ * and flags as nnp_coupling_eval on a handle of this precision, coulomb_k and
+ * cutoff; runs on the current HIP device.
+ *
+ * Its partial sums live in a static device array of 8 MiB that the library
+ * holds on every GPU it runs on until the process ends: ceil(n_mm / 64)
+ * doubles plus 3 n_nnp ceil(n_mm / chunk) values of the operand type, where
+ * chunk is the handle's MM-atoms-per-wave rule widened (up to 512) until they
+ * fit.  The 64-atom ligand in 47,648 MM atoms needs 2.3 MB (FP32) or 4.6 MB
+ * (FP64).  Larger systems, or n_nnp > 1024 or n_mm > 2^22, return
+ * NNP_E_CAPACITY before anything is launched.  The first call on a device
+ * looks up that device's copy of the array (no allocation).
+ *
+ * Every call on one GPU shares that array: calls that overlap in time on one
+ * GPU (two streams, two host threads) race and give wrong results; serialise
+ * them.  Nothing in the array needs clearing: every partial a call reads is
+ * written earlier in the same call.
+ */
+nnp_status nnp_coupling_eval_noalloc(int32_t precision, double coulomb_k, double cutoff, int32_t n_nnp,
+                                     const void* x_nnp, const void* par_nnp, int32_t n_mm,
+                                     const void* x_mm, const void* par_mm, double* out_E, void* F_nnp,
+                                     void* F_mm, void* stream, uint32_t flags);
+
 /* Message of the calling thread's last host-side error ("" if none). */
 const char* nnp_last_error(void);
 

@@ -224,6 +224,40 @@ hipError_t launch_coupling(const CouplingShape& cs, int n_nnp, const T* x_nnp, c
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free coupling entry point: the per-block energy
+// partials and the per-chunk NNP force partials live in this array instead
+// of a handle's workspace.  Every GPU the library runs on holds its own copy
+// for the lifetime of the process; host code uses only the device address
+// obtained below, never the array's name.
+static __device__ __align__(256) unsigned char scratch[kCoupleScratchBytes];
+
+hipError_t coupling_scratch(void** ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        // raise the pair kernel's dynamic-LDS limit now (its largest size),
+        // so later calls do no host-side set-up
+        e = ensure_lds((const void*)k_couple_pairs<float>, sizeof(float) * kCoupleVals * 4 * 512);
+        if (e == hipSuccess)
+            e = ensure_lds((const void*)k_couple_pairs<double>, sizeof(double) * kCoupleVals * 4 * 512);
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
 template hipError_t launch_coupling<float>(const CouplingShape&, int, const float*, const float*, int,
                                            const float*, const float*, double*, float*, float*,
                                            double*, float*, bool, hipStream_t);

@@ -252,6 +252,11 @@ struct CouplingShape {
     int max_nnp, max_mm;
     int chunk;          // MM atoms per workgroup of the NNP-side force kernel
 };
+// Bytes of the per-device static scratch behind nnp_coupling_eval_noalloc
+// and its device address on the current device (looked up once per device).
+constexpr size_t kCoupleScratchBytes = (size_t)8 << 20;
+hipError_t coupling_scratch(void** ptr);
+
 template <typename T>
 hipError_t launch_coupling(const CouplingShape& cs, int n_nnp, const T* x_nnp, const T* par_nnp,
                            int n_mm, const T* x_mm, const T* par_mm, double* E, T* F_nnp, T* F_mm,

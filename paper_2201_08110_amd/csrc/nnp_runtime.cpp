@@ -1354,4 +1354,51 @@ nnp_status nnp_coupling_eval(nnp_coupling* c, int32_t n_nnp, const void* x_nnp, 
     return NNP_OK;
 }
 
+nnp_status nnp_coupling_eval_noalloc(int32_t precision, double coulomb_k, double cutoff, int32_t n_nnp,
+                                     const void* x_nnp, const void* par_nnp, int32_t n_mm,
+                                     const void* x_mm, const void* par_mm, double* out_E, void* F_nnp,
+                                     void* F_mm, void* stream, uint32_t flags) {
+    if (precision != NNP_PREC_FP64 && precision != NNP_PREC_FP32)
+        return fail(NNP_E_INVALID, "coupling precision must be FP64 or FP32");
+    if (!std::isfinite(coulomb_k) || !(cutoff >= 0.0) || !std::isfinite(cutoff))
+        return fail(NNP_E_INVALID, "coulomb_k must be finite and cutoff >= 0");
+    nnp_status rc = check_coupling_args(n_nnp, x_nnp, par_nnp, n_mm, x_mm, par_mm, out_E, F_nnp, F_mm, flags);
+    if (rc) return rc;
+    if (n_nnp > 1024 || n_mm > (1 << 22))
+        return fail(NNP_E_CAPACITY, "coupling system above 1024 NNP or 2^22 MM atoms");
+    void* scratch = nullptr;
+    hipError_t e = coupling_scratch(&scratch);
+    if (e != hipSuccess) return fail(NNP_E_DEVICE, std::string("coupling scratch: ") + hipGetErrorString(e));
+    // the partials: [ceil(n_mm / 64)] doubles, then [3 n_nnp][ceil(n_mm / chunk)]
+    // of the operand type; a chunk wider than the handle's rule (up to 512 MM
+    // atoms) is taken when that makes them fit
+    const size_t tsz = precision == NNP_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const size_t e_bytes = (((size_t)(n_mm + kCoupleMmPerBlock - 1) / kCoupleMmPerBlock) * sizeof(double) + 255) &
+                           ~(size_t)255;
+    CouplingShape cs{};
+    cs.coulomb_k = coulomb_k;
+    cs.cutoff = cutoff;
+    cs.max_nnp = std::max(n_nnp, 1);
+    cs.max_mm = std::max(n_mm, 1);
+    cs.chunk = coupling_chunk(cs.max_mm);
+    auto f_bytes = [&](int chunk) { return tsz * 3 * (size_t)n_nnp * (size_t)((n_mm + chunk - 1) / chunk); };
+    while (e_bytes + f_bytes(cs.chunk) > kCoupleScratchBytes && cs.chunk < 512) cs.chunk += 16;
+    if (e_bytes + f_bytes(cs.chunk) > kCoupleScratchBytes)
+        return fail(NNP_E_CAPACITY, "coupling partials exceed the static scratch (8 MiB)");
+    double* e_part = (double*)scratch;
+    void* f_part = (char*)scratch + e_bytes;
+    const bool acc = (flags & NNP_FLAG_ACCUMULATE) != 0;
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == NNP_PREC_FP64)
+        e = launch_coupling<double>(cs, n_nnp, (const double*)x_nnp, (const double*)par_nnp, n_mm,
+                                    (const double*)x_mm, (const double*)par_mm, out_E, (double*)F_nnp,
+                                    (double*)F_mm, e_part, (double*)f_part, acc, st);
+    else
+        e = launch_coupling<float>(cs, n_nnp, (const float*)x_nnp, (const float*)par_nnp, n_mm,
+                                   (const float*)x_mm, (const float*)par_mm, out_E, (float*)F_nnp,
+                                   (float*)F_mm, e_part, (float*)f_part, acc, st);
+    if (e != hipSuccess) return fail(NNP_E_DEVICE, std::string("coupling launch: ") + hipGetErrorString(e));
+    return NNP_OK;
+}
+
 }  // extern "C"

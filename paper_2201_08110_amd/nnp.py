@@ -64,7 +64,8 @@ EXPORTS = ("nnp_create", "nnp_destroy", "nnp_energy_forces", "nnp_energy_forces_
            "nnp_get_device_status", "nnp_set_timing", "nnp_set_timing_only", "nnp_kernel_times",
            "nnp_last_error",
            "nnp_set_knob", "nnp_get_knob", "nnp_autotune",
-           "nnp_coupling_create", "nnp_coupling_destroy", "nnp_coupling_eval")
+           "nnp_coupling_create", "nnp_coupling_destroy", "nnp_coupling_eval",
+           "nnp_coupling_eval_noalloc")
 
 #: tunable knobs (include/nnp.h)
 (KNOB_MLP_PATH, KNOB_GEMM_STAGES, KNOB_CELL_MIN, KNOB_TAIL_TILE, KNOB_GEMM_WAVES, KNOB_ATOM_CHUNK,
@@ -126,6 +127,9 @@ def load_library(path: str = LIB_PATH):
     lib.nnp_coupling_destroy.restype = None
     lib.nnp_coupling_eval.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, C.c_uint32]
     lib.nnp_coupling_eval.restype = i32
+    lib.nnp_coupling_eval_noalloc.argtypes = [i32, d, d, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp,
+                                              C.c_uint32]
+    lib.nnp_coupling_eval_noalloc.restype = i32
     _lib = lib
     return lib
 
@@ -422,3 +426,31 @@ class Coupling:
                                           FLAG_ACCUMULATE if accumulate else 0))
         return E, Fn, Fm
 
+
+def coupling_noalloc(x_nnp, par_nnp, x_mm, par_mm, coulomb_k: float, cutoff: float = 0.0,
+                     out=None, accumulate: bool = False, stream=None):
+    """The coupling of `Coupling.__call__` through the handle-free,
+    allocation-free entry point (static per-device scratch; calls on one GPU
+    must not overlap).  Outputs are allocated here unless `out` is given."""
+    import torch
+    lib = load_library()
+    if x_nnp.dtype == torch.float64:
+        prec, dt = PREC["fp64"], torch.float64
+    elif x_nnp.dtype == torch.float32:
+        prec, dt = PREC["fp32"], torch.float32
+    else:
+        raise TypeError("coordinates must be float32 or float64")
+    for t, name in ((x_nnp, "x_nnp"), (par_nnp, "par_nnp"), (x_mm, "x_mm"), (par_mm, "par_mm")):
+        NNP._need(t, dt, name)
+    if out is None:
+        E = torch.zeros(1, dtype=torch.float64, device=x_nnp.device)
+        Fn, Fm = torch.zeros_like(x_nnp), torch.zeros_like(x_mm)
+    else:
+        E, Fn, Fm = out
+    s = stream if stream is not None else torch.cuda.current_stream(x_nnp.device)
+    _check(lib.nnp_coupling_eval_noalloc(prec, float(coulomb_k), float(cutoff), x_nnp.shape[0],
+                                         x_nnp.data_ptr(), par_nnp.data_ptr(), x_mm.shape[0],
+                                         x_mm.data_ptr(), par_mm.data_ptr(), E.data_ptr(),
+                                         Fn.data_ptr(), Fm.data_ptr(), s.cuda_stream,
+                                         FLAG_ACCUMULATE if accumulate else 0))
+    return E, Fn, Fm

@@ -109,6 +109,24 @@ def test_create_rejects_bad_creation_flags(hp, flags, prec, code):
     assert h.value is None
 
 
+def test_noalloc_coupling_rejects_on_host():
+    """The allocation-free coupling call validates everything on the host
+    before it looks up its scratch (no GPU needed to get these errors)."""
+    nnp, lib = _lib()
+    E = (C.c_double * 1)()
+    x = (C.c_double * 3)()
+    call = lib.nnp_coupling_eval_noalloc
+    assert call(7, 332.0, 0.0, 1, x, x, 1, x, x, E, x, x, None, 0) == nnp.NNP_E_INVALID      # precision
+    assert call(0, float("inf"), 0.0, 1, x, x, 1, x, x, E, x, x, None, 0) == nnp.NNP_E_INVALID
+    assert call(0, 332.0, -1.0, 1, x, x, 1, x, x, E, x, x, None, 0) == nnp.NNP_E_INVALID
+    assert call(0, 332.0, 0.0, 1, x, x, 1, x, x, None, x, x, None, 0) == nnp.NNP_E_INVALID    # out_E
+    assert call(0, 332.0, 0.0, 1, None, x, 1, x, x, E, x, x, None, 0) == nnp.NNP_E_INVALID
+    assert call(0, 332.0, 0.0, -1, x, x, 1, x, x, E, x, x, None, 0) == nnp.NNP_E_INVALID
+    assert call(0, 332.0, 0.0, 1, x, x, 1, x, x, E, x, x, None, 4) == nnp.NNP_E_INVALID       # flag
+    assert call(0, 332.0, 0.0, 1025, x, x, 1, x, x, E, x, x, None, 0) == nnp.NNP_E_CAPACITY
+    assert call(0, 332.0, 0.0, 1, x, x, (1 << 22) + 1, x, x, E, x, x, None, 0) == nnp.NNP_E_CAPACITY
+
+
 def test_null_arguments():
     nnp, lib = _lib()
     h = C.c_void_p()
