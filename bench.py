@@ -32,6 +32,72 @@ METRIC = "atom energy+force evals/s (8-model ensemble), batched BF16 vs plain FP
 
 # MI355X published peaks
 PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}
+HBM_BW = 8.0e12            # bytes/s
+# plain (non-packed) FP32 VALU: 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz; the
+# transcendental unit (exp2, log2, sin, cos, sqrt, rcp) runs at a quarter of
+# the lane rate: 256 x 16 x 2.4 GHz
+VALU_FP32 = 78.6e12
+TRANS_RATE = 256 * 16 * 2.4e9
+
+# Algorithmic work of the featuriser terms (counted once per unordered pair
+# and per angular triple, whatever the kernels recompute):
+#   radial, per unordered pair within rcr: 16 Gaussians + the cosine cutoff
+#     forward (17 transcendentals), the same with its derivative backward (18);
+#   angular, per triple (i; {j,k}) within rca: 8 distance Gaussians, 4 powers
+#     (log2 + exp2 each) and one square root forward (17, ~110 FLOP), the same
+#     recomputed with their derivatives backward (18, ~250 FLOP);
+#   per-pair distance geometry ~10 FLOP each way.
+TRANS_PAIR_FWD, TRANS_PAIR_BWD = 17, 18
+TRANS_TRIPLE_FWD, TRANS_TRIPLE_BWD = 17, 18
+FLOP_PAIR_FWD, FLOP_PAIR_BWD = 60, 90
+FLOP_TRIPLE_FWD, FLOP_TRIPLE_BWD = 110, 250
+
+
+def geometry_counts(batch, rcr, rca):
+    """Unordered pairs within rcr and angular triples (i; {j<k}) with both
+    r_ij, r_ik < rca, counted from the batch's coordinates."""
+    o = np.asarray(batch.mol_offsets)
+    x = np.asarray(batch.coords)
+    pairs = triples = 0
+    sizes = np.diff(o)
+    # molecules of one size in one vectorised block
+    for n in np.unique(sizes):
+        if n < 2:
+            continue
+        idx = np.nonzero(sizes == n)[0]
+        xs = np.stack([x[o[m]:o[m] + n] for m in idx])             # [k, n, 3]
+        d2 = ((xs[:, :, None, :] - xs[:, None, :, :]) ** 2).sum(-1)
+        eye = np.eye(n, dtype=bool)[None]
+        pairs += int(((d2 < rcr * rcr) & ~eye).sum()) // 2
+        na = ((d2 < rca * rca) & ~eye).sum(-1)
+        triples += int((na * (na - 1) // 2).sum())
+    return pairs, triples
+
+
+def stage_floors(hp, M, n_atoms, pairs, triples, g_bytes, dg_bytes, mfma_peak=PEAK["bf16"]):
+    """Per-stage lower bounds (seconds) of one evaluation: the larger of the
+    MFMA time (networks), the VALU and transcendental times (featuriser,
+    forces, CELU) and the HBM time of the bytes each stage must move in this
+    staging (AEV rows out of the featuriser, dE/dAEV rows into the force
+    kernel).  The sum over stages is the step floor."""
+    f = mlp_flops_per_atom(hp, M)
+    w = hp["widths"]
+    mlp_flops = (f["mlp_l1_fwd"] + f["mlp_tail"] + f["mlp_l1_bwd"]) * n_atoms
+    celu_exps = M * sum(w[1:-1]) * n_atoms
+    aev_trans = TRANS_PAIR_FWD * pairs + TRANS_TRIPLE_FWD * triples
+    aev_flops = FLOP_PAIR_FWD * pairs + FLOP_TRIPLE_FWD * triples
+    frc_trans = TRANS_PAIR_BWD * pairs + TRANS_TRIPLE_BWD * triples
+    frc_flops = FLOP_PAIR_BWD * pairs + FLOP_TRIPLE_BWD * triples
+    st = {
+        "networks": {"mfma_s": mlp_flops / mfma_peak, "trans_s": celu_exps / TRANS_RATE},
+        "aev": {"trans_s": aev_trans / TRANS_RATE, "valu_s": aev_flops / VALU_FP32,
+                "hbm_s": (g_bytes + 12 * n_atoms) / HBM_BW},
+        "forces": {"trans_s": frc_trans / TRANS_RATE, "valu_s": frc_flops / VALU_FP32,
+                   "hbm_s": (dg_bytes + 24 * n_atoms) / HBM_BW},
+    }
+    for v in st.values():
+        v["floor_s"] = max(v.values())
+    return st
 
 
 def mlp_flops_per_atom(hp, M):
@@ -121,19 +187,97 @@ def stored_traffic(kernel):
     return None
 
 
-def cpu_baseline(hp, w, M, make_sample, budget_s=12.0):
-    """Oracle on bounded samples of the workload until ~budget_s of CPU work."""
+def _omp_threads(n):
+    """OpenMP thread count of the calling thread (the oracle's parallel
+    regions use it)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+    except (OSError, AttributeError):
+        pass
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _sub_batch(batch, mols):
+    """Species, coordinates, offsets and atom rows of some molecules."""
+    o = np.asarray(batch.mol_offsets)
+    rows = np.concatenate([np.arange(o[m], o[m + 1]) for m in mols])
+    off = np.concatenate([[0], np.cumsum([o[m + 1] - o[m] for m in mols])]).astype(np.int64)
+    return np.asarray(batch.species)[rows], np.asarray(batch.coords)[rows], off, rows
+
+
+def accuracy_of(E, F, Eo, Fo, offsets):
+    """Per-molecule |dE|/atom, force RMSE and largest force-component error
+    (kcal/mol, kcal/mol/A) against the oracle."""
+    sizes = np.diff(offsets)
+    dE = np.abs(E - Eo) / np.maximum(sizes, 1)
+    rmse = np.array([np.sqrt(np.mean((F[a:b] - Fo[a:b]) ** 2)) for a, b in zip(offsets[:-1], offsets[1:])
+                     if b > a])
+    dF = np.abs(F - Fo)
+    return {"molecules": int(len(sizes)), "dE_per_atom_max": float(dE.max()),
+            "dE_per_atom_median": float(np.median(dE)), "force_rmse_max": float(rmse.max()),
+            "force_rmse_median": float(np.median(rmse)), "force_component_abs_err_max": float(dF.max()),
+            "force_rms": float(np.sqrt(np.mean(Fo ** 2)))}
+
+
+def cpu_leg(hp, w, M, b5, jobs, synth):
+    """The FP64 C oracle as the CPU baseline (the whole headline batch once
+    on every host thread, and the 64-atom ligand on one and on every thread)
+    and, from the same oracle, the accuracy of each timed form: its energies
+    and forces against the oracle on the inputs the path receives
+    (FP32-rounded coordinates and weights)."""
     import oracle
-    atoms, elapsed, first = 0, 0.0, None
-    b = make_sample()
-    while elapsed < budget_s:
-        t0 = time.perf_counter()
-        E, F = oracle.energy_forces(hp, w, M, b.species, b.coords, b.mol_offsets)
-        elapsed += time.perf_counter() - t0
-        atoms += b.n_atoms
-        if first is None:
-            first = (b, E, F)
-    return atoms / elapsed, atoms, elapsed, oracle.num_threads(), first
+    n_all = oracle.num_threads()
+    wo = synth.round_to_fp32(w)
+    t0 = time.perf_counter()
+    E5o, F5o = oracle.energy_forces(hp, wo, M, b5.species, synth.round_to_fp32(b5.coords), b5.mol_offsets)
+    t_all = time.perf_counter() - t0
+    b2 = synth.config_batch(2)
+
+    def ligand_rate(threads, budget):
+        _omp_threads(threads)
+        n, t = 0, 0.0
+        while t < budget:
+            t0 = time.perf_counter()
+            oracle.energy_forces(hp, w, M, b2.species, b2.coords, b2.mol_offsets)
+            t += time.perf_counter() - t0
+            n += 1
+        return t / n
+
+    t1 = ligand_rate(1, 3.0)
+    tn = ligand_rate(n_all, 1.0)
+    _omp_threads(n_all)
+    base = {"value": b5.n_atoms / t_all, "unit": "atom-evals/s", "cores": n_all, "kind": "oracle",
+            "sample": f"the whole headline batch ({b5.n_atoms} atoms) once on {n_all} threads: {t_all:.1f} s, FP64",
+            "cpu_model": cpu_model(),
+            "one_core": {"value": b2.n_atoms / t1, "unit": "atom-evals/s",
+                         "sample": f"the 64-atom ligand, 8 models, 1 thread: {t1 * 1e3:.1f} ms per evaluation"},
+            "ligand_64_all_cores": {"value": b2.n_atoms / tn, "unit": "atom-evals/s",
+                                    "sample": f"the 64-atom ligand on {n_all} threads: {tn * 1e3:.1f} ms"}}
+    acc = {}
+    for where, b, prec, E, F, mols in jobs:
+        if b is b5 and mols is None:
+            Eo, Fo, Es, Fs, off = E5o, F5o, E, F, np.asarray(b5.mol_offsets)
+        else:
+            mols = list(range(b.n_mols)) if mols is None else mols
+            sp, xc, off, rows = _sub_batch(b, mols)
+            Eo, Fo = oracle.energy_forces(hp, wo, M, sp, synth.round_to_fp32(xc), off)
+            Es, Fs = np.asarray(E)[mols], np.asarray(F)[rows]
+        a = accuracy_of(Es, Fs, Eo, Fo, np.asarray(off))
+        a["vs"] = "FP64 oracle on the FP32-rounded coordinates and weights the path receives"
+        a["precision"] = prec
+        acc[where] = a
+    return base, acc
 
 
 # flops of one coupling pair as counted here: distance (8), reciprocal and
@@ -292,6 +436,10 @@ def main():
     ap.add_argument("--no-coupling", action="store_true", help="skip the NNP-MM coupling form")
     ap.add_argument("--no-overlap", action="store_true",
                     help="skip the NNP/MM step overlapped with an MM stand-in")
+    ap.add_argument("--profile-only", choices=["ligand_fp32", "ligand_bf16", "ragged_fp32", "ragged_bf16"],
+                    default=None,
+                    help="run only this workload (steps evaluations after warmup, graph replays) and "
+                         "print its timing: a short run for a kernel trace of that form")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one elementwise copy (negation) of this many MiB (a "
                          "reference dispatch for HBM traffic counters)")
@@ -319,6 +467,19 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    accuracy_jobs = []   # (where, batch, precision, E, F, molecules compared or None = all)
+
+    if args.profile_only:
+        wl, prec = args.profile_only.split("_")
+        b = synth.config_batch(2 if wl == "ligand" else 3)
+        apm = 64 if wl == "ligand" else 120
+        hq = nnp.NNP(hp, w, M, prec, max_atoms=b.n_atoms, max_mols=b.n_mols, max_atoms_per_mol=apm)
+        secq, _, _, _, _ = run_form(torch, hq, b, args.steps, args.warmup, timing=False, graph=True)
+        print(json.dumps({"profile_only": args.profile_only, "atoms": int(b.n_atoms),
+                          "us_per_eval": secq * 1e6, "steps": args.steps}))
+        hq.close()
+        return
+
     # ---- headline: batched BF16-MLP replicas -----------------------------
     b5 = synth.config_batch(5, n_mols=args.replicas)
     h5 = nnp.NNP(hp, w, M, "bf16", max_atoms=b5.n_atoms, max_mols=b5.n_mols, max_atoms_per_mol=48)
@@ -327,15 +488,20 @@ def main():
     # events around that kernel only (each event record between kernels
     # costs GPU time, ~60 us per evaluation for all of them), plus
     # per-evaluation events; `value` and the roofline come from it.
-    _, kt_all, _, _, _ = run_form(torch, h5, b5, min(args.steps, 20), args.warmup, timing=True)
+    cal_steps = min(args.steps, 20)
+    _, kt_all, _, _, _ = run_form(torch, h5, b5, cal_steps, args.warmup, timing=True)
     flops = mlp_flops_per_atom(hp, M)
-    per_kernel = {k: {"launches": c, "avg_us": 1e3 * ms / max(c, 1)} for k, (c, ms) in kt_all.items()}
+    # per evaluation: the pipelined evaluation launches each kernel once per
+    # half-batch (the two launches of one kernel never overlap), so a
+    # kernel's time per evaluation is the sum of its launches
+    per_kernel = {k: {"launches_per_eval": c / cal_steps, "avg_us": 1e3 * ms / cal_steps}
+                  for k, (c, ms) in kt_all.items()}
     gemms = {k: v for k, v in per_kernel.items() if k in flops}
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"]) if per_kernel else None
     sec, kt, E5, F5, steps_ms = run_form(torch, h5, b5, args.steps, args.warmup, timing=True,
                                          per_step=True, only=dom)
     value = b5.n_atoms / sec
-    dom_us = 1e3 * kt[dom][1] / max(kt[dom][0], 1) if dom in kt else None
+    dom_us = 1e3 * kt[dom][1] / args.steps if dom in kt else None
     roof = None
     if dom in flops and dom_us:
         achieved = flops[dom] * b5.n_atoms / (dom_us * 1e-6)
@@ -345,9 +511,26 @@ def main():
                 "flops_per_launch": flops[dom] * b5.n_atoms}
     mlp_total_us = sum(v["avg_us"] for v in gemms.values())
     mlp_flops = sum(flops[k] for k in gemms) * b5.n_atoms
+    # every kernel against its own bound; the step against the sum of the
+    # stage floors (Sigma_stages max(flops / peak, transcendentals / rate,
+    # bytes / HBM) / measured time)
+    pairs5, triples5 = geometry_counts(b5, hp["rcr"], hp["rca"])
+    D = synth.aev_dim(hp)
+    st5 = stage_floors(hp, M, b5.n_atoms, pairs5, triples5, g_bytes=2 * D * b5.n_atoms,
+                       dg_bytes=4 * D * b5.n_atoms)
     for k, v in per_kernel.items():
         if k in flops:
             v["tflops"] = flops[k] * b5.n_atoms / (v["avg_us"] * 1e-6) / 1e12
+            v["bound"], v["floor_us"] = "mfma", flops[k] * b5.n_atoms / PEAK["bf16"] * 1e6
+        elif k in ("aev", "forces"):
+            fl = st5[k]
+            v["bound"] = max(("trans", fl["trans_s"]), ("valu", fl["valu_s"]), ("hbm", fl["hbm_s"]),
+                             key=lambda t: t[1])[0]
+            v["floor_us"] = fl["floor_s"] * 1e6
+        else:
+            continue
+        v["frac"] = v["floor_us"] / v["avg_us"]
+    step_floor = sum(v["floor_s"] for v in st5.values())
 
     out = {
         "metric": METRIC, "value": value, "unit": "atom-evals/s", "n_gpus": 1,
@@ -360,29 +543,55 @@ def main():
         "roofline": roof,
         "ms_per_eval_p10_p50_p90": [float(np.percentile(steps_ms, q)) for q in (10, 50, 90)],
         "kernels": per_kernel,
-        "kernels_timing": "calibration pass with every launch timed; the timed region times only "
-                          f"{dom} ({dom_us:.1f} us avg there)" if dom_us else None,
+        "kernels_timing": "calibration pass with every launch timed (microseconds per evaluation, summed "
+                          "over its launches); the timed region times only "
+                          f"{dom} ({dom_us:.1f} us per evaluation there)" if dom_us else None,
+        "pipeline": h5.get_knob("pipeline"),
         "mlp_gemm_tflops": mlp_flops / (mlp_total_us * 1e-6) / 1e12 if mlp_total_us else None,
+        "step_roofline": {
+            "floor_us": step_floor * 1e6, "frac": step_floor / sec,
+            "stages_us": {k: {kk.replace("_s", "_us"): vv * 1e6 for kk, vv in v.items()}
+                          for k, v in st5.items()},
+            "pairs": pairs5, "triples": triples5,
+            "definition": "sum over stages (networks, featuriser, forces) of max(MFMA FLOPs / 2.5 PFLOP/s, "
+                          "transcendentals / 9.83 T/s, VALU FLOPs / 78.6 TFLOP/s, bytes crossing HBM between "
+                          "stages / 8 TB/s), divided by ms_per_step"},
     }
 
     # ---- plain FP32 single ligand ----------------------------------------
     if not args.no_plain:
         b2 = synth.config_batch(2)
+        # the single molecule is bound by streaming the weights of the
+        # elements it holds once per evaluation (all 7 here)
+        n_el = len(np.unique(b2.species))
+        net_params = synth.net_size(hp["widths"])
         h2 = nnp.NNP(hp, w, M, "fp32", max_atoms=b2.n_atoms, max_mols=1, max_atoms_per_mol=64)
         sec2, _, _, _, _ = run_form(torch, h2, b2, max(args.steps, 200), args.warmup, timing=False)
-        sec2g, _, _, _, _ = run_form(torch, h2, b2, max(args.steps, 200), args.warmup,
-                                     timing=False, graph=True)
+        sec2g, _, E2, F2, _ = run_form(torch, h2, b2, max(args.steps, 200), args.warmup,
+                                       timing=False, graph=True)
+        wbytes = 4 * n_el * M * net_params
         out["plain_fp32"] = {"workload": "single 64-atom ligand, 8-model ensemble, FP32",
                              "value": b2.n_atoms / sec2g, "unit": "atom-evals/s",
                              "us_per_eval": sec2g * 1e6, "us_per_eval_eager": sec2 * 1e6,
-                             "launch": "one captured HIP graph per evaluation"}
+                             "launch": "one captured HIP graph per evaluation",
+                             "roofline": {"bound": "hbm", "achieved": wbytes / sec2g / 1e9,
+                                          "peak": HBM_BW / 1e9, "unit": "GB/s",
+                                          "frac": wbytes / HBM_BW / sec2g, "bytes_per_eval": wbytes,
+                                          "what": f"FP32 weights of the {n_el} elements present, read once"}}
+        accuracy_jobs.append(("plain_fp32", b2, "fp32", E2, F2, None))
         h2.close()
         h2 = nnp.NNP(hp, w, M, "bf16", max_atoms=b2.n_atoms, max_mols=1, max_atoms_per_mol=64)
-        sec2b, _, _, _, _ = run_form(torch, h2, b2, max(args.steps, 200), args.warmup,
-                                     timing=False, graph=True)
+        sec2b, _, E2b, F2b, _ = run_form(torch, h2, b2, max(args.steps, 200), args.warmup,
+                                         timing=False, graph=True)
+        wbytes = 2 * n_el * M * net_params
         out["plain_bf16"] = {"workload": "single 64-atom ligand, 8-model ensemble, BF16 networks",
                              "value": b2.n_atoms / sec2b, "unit": "atom-evals/s",
-                             "us_per_eval": sec2b * 1e6, "launch": "one captured HIP graph per evaluation"}
+                             "us_per_eval": sec2b * 1e6, "launch": "one captured HIP graph per evaluation",
+                             "roofline": {"bound": "hbm", "achieved": wbytes / sec2b / 1e9,
+                                          "peak": HBM_BW / 1e9, "unit": "GB/s",
+                                          "frac": wbytes / HBM_BW / sec2b, "bytes_per_eval": wbytes,
+                                          "what": f"BF16 weights of the {n_el} elements present, read once"}}
+        accuracy_jobs.append(("plain_bf16", b2, "bf16", E2b, F2b, None))
         h2.close()
 
     # ---- like-for-like batched forms: both precisions on the replica batch
@@ -390,6 +599,11 @@ def main():
     if not args.no_forms:
         forms = {}
         b3 = synth.config_batch(3)
+        sizes3 = np.diff(b3.mol_offsets)
+        pick3 = sorted({int(np.argmin(sizes3)), int(np.argmax(sizes3))}
+                       | set(np.random.default_rng(13).choice(b3.n_mols, 32, replace=False).tolist()))
+        pairs3, triples3 = geometry_counts(b3, hp["rcr"], hp["rca"])
+        D = synth.aev_dim(hp)
         for name, b, apm in (("replicas_1024x48", b5, 48), ("ragged_512", b3, 120)):
             for prec in ("fp32", "bf16"):
                 if name == "replicas_1024x48" and prec == "bf16":
@@ -398,9 +612,27 @@ def main():
                     continue
                 hf = nnp.NNP(hp, w, M, prec, max_atoms=b.n_atoms, max_mols=b.n_mols,
                              max_atoms_per_mol=apm)
-                secf, _, _, _, _ = run_form(torch, hf, b, 20, 3, timing=False)
-                forms[f"{name}_{prec}"] = {"atom_evals_per_s": b.n_atoms / secf,
-                                           "ms_per_eval": secf * 1e3, "atoms": int(b.n_atoms)}
+                entry = {}
+                if name == "ragged_512":
+                    # the ragged batch as its workload runs it: variants chosen
+                    # by the autotuner, then one captured graph per evaluation
+                    dev = torch.device("cuda:0")
+                    rep_ = hf.autotune(torch.tensor(b.coords, dtype=torch.float32, device=dev),
+                                       torch.tensor(b.species, dtype=torch.int32, device=dev),
+                                       torch.tensor(b.mol_offsets, dtype=torch.int32, device=dev), reps=3)
+                    entry["autotuned"] = rep_.get("chosen")
+                secf, _, Ef, Ff, _ = run_form(torch, hf, b, 20, 3, timing=False, graph=True)
+                p_, t_ = (pairs3, triples3) if name == "ragged_512" else (pairs5, triples5)
+                gb = (2 if prec == "bf16" else 4) * D * b.n_atoms
+                stf = stage_floors(hp, M, b.n_atoms, p_, t_, g_bytes=gb, dg_bytes=4 * D * b.n_atoms,
+                                   mfma_peak=PEAK["bf16" if prec == "bf16" else "fp32"])
+                fl = sum(v["floor_s"] for v in stf.values())
+                entry.update({"atom_evals_per_s": b.n_atoms / secf, "ms_per_eval": secf * 1e3,
+                              "atoms": int(b.n_atoms), "launch": "one captured HIP graph per evaluation",
+                              "step_roofline_frac": fl / secf, "step_floor_us": fl * 1e6})
+                forms[f"{name}_{prec}"] = entry
+                accuracy_jobs.append((f"batched_forms.{name}_{prec}", b, prec, Ef, Ff,
+                                      pick3 if name == "ragged_512" else list(range(16))))
                 hf.close()
         out["batched_forms"] = forms
 
@@ -435,30 +667,18 @@ def main():
     if not args.no_coupling:
         out["coupling"] = coupling_form(torch, nnp, synth, args)
 
-    # ---- CPU baseline + accuracy on the sample ---------------------------
+    # ---- CPU leg: the oracle as the CPU baseline, and the accuracy of every
+    # timed form against it ------------------------------------------------
     if not args.no_cpu:
-        nsamp = 16
-
-        def sample():
-            return synth.config_batch(5, n_mols=nsamp)
-
-        rate, atoms, el, cores, first = cpu_baseline(hp, w, M, sample)
-        out["cpu_baseline"] = {"value": rate, "unit": "atom-evals/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": f"first {nsamp} replicas ({nsamp * 48} atoms) of the workload, "
-                                         f"repeated: {atoms} atom-evals in {el:.1f} s, FP64"}
-        b, Eo, Fo = first
-        # the timed GPU run holds the same first replicas (same seed stream)
-        n = b.n_atoms
-        dE = np.abs(E5[:nsamp] - Eo) / 48.0
-        rmse = np.sqrt(np.mean((F5[:n].reshape(nsamp, 48, 3) - Fo.reshape(nsamp, 48, 3)) ** 2,
-                               axis=(1, 2)))
-        out["accuracy"] = {"vs": "FP64 oracle, FP64 master weights", "replicas": nsamp,
-                           "dE_per_atom_max": float(dE.max()),
-                           "dE_per_atom_median": float(np.median(dE)),
-                           "force_rmse_max": float(rmse.max()),
-                           "force_rmse_median": float(np.median(rmse)),
-                           "force_rms": float(np.sqrt(np.mean(Fo ** 2)))}
+        accuracy_jobs.insert(0, ("accuracy", b5, "bf16", E5, F5, None))
+        out["cpu_baseline"], acc = cpu_leg(hp, w, M, b5, accuracy_jobs, synth)
+        for key, a in acc.items():
+            if key == "accuracy":
+                out["accuracy"] = a
+            elif key.startswith("batched_forms."):
+                out["batched_forms"][key.split(".", 1)[1]]["accuracy"] = a
+            else:
+                out[key]["accuracy"] = a
     h5.close()
     print(json.dumps(out))
 

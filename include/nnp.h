@@ -67,6 +67,10 @@ typedef int32_t nnp_status;
                                    the same (first such call runs eagerly and captures); needs
                                    a non-null stream and is ignored while per-kernel timing is
                                    on                                                         */
+#define NNP_FLAG_DEVICE_COUNTS 4u /* the batch's molecule and atom counts are read on the device
+                                   from nnp_batch.counts (see there); n_mols and n_atoms are
+                                   then upper bounds, and a captured graph serves every batch
+                                   within the same rounded bounds                             */
 #define NNP_FLAG_ACCUMULATE 2u  /* add the results to what the outputs hold instead of
                                    overwriting them (nnp_energy_forces / _f64: out_E and
                                    out_F; nnp_coupling_eval: its energy and both forces), e.g.
@@ -153,6 +157,22 @@ typedef struct {
  * One evaluation's batch: n_mols molecules in CSR form.  Atoms of molecule b
  * are [mol_offsets[b], mol_offsets[b+1]) of the coordinate/species arrays.
  * Molecules never interact; an empty molecule has zero energy.
+ *
+ * Device-side counts (NNP_FLAG_DEVICE_COUNTS; the batching of many ragged
+ * molecules in one graph-captured launch, Methods, third optimisation): the
+ * call reads {n_mols, n_atoms} from the device array `counts` when it runs,
+ * and the host fields n_mols and n_atoms are upper bounds of those counts
+ * (within the capacities).  The library sizes its launches for the bounds
+ * rounded up to powers of two (capped at the capacities), and with
+ * NNP_FLAG_GRAPH it keys its captured graph on those rounded bounds instead
+ * of the exact sizes: a caller that writes a new batch (coordinates,
+ * species, offsets and counts) into the same device buffers replays the same
+ * graph, with no re-capture, for every batch within the bounds.  The arrays
+ * need hold only the batch itself (mol_offsets [counts[0]+1], atoms
+ * [counts[1]]); out_E receives counts[0] energies.  Counts above the rounded
+ * bounds, or offsets that do not end at counts[1], set NNP_E_CAPACITY on the
+ * device flag.  nnp_aev, nnp_autotune and nnp_energy_forces_backward take
+ * host counts only (NNP_E_UNSUPPORTED).
  */
 typedef struct {
     int32_t n_mols;               /* 1..max_mols */
@@ -161,7 +181,8 @@ typedef struct {
     const int32_t* species;       /* device [n_atoms]: atomic numbers on handles created with an
                                      element table, else element indices 0..S-1 */
     void* stream;                 /* hipStream_t; NULL = the null stream */
-    uint32_t flags;               /* NNP_FLAG_GRAPH | NNP_FLAG_ACCUMULATE */
+    uint32_t flags;               /* NNP_FLAG_GRAPH | NNP_FLAG_ACCUMULATE | NNP_FLAG_DEVICE_COUNTS */
+    const int32_t* counts;        /* device [2] {n_mols, n_atoms} with NNP_FLAG_DEVICE_COUNTS, else unused */
 } nnp_batch;
 
 /*
@@ -238,6 +259,11 @@ nnp_status nnp_set_params(nnp_handle* h, const void* params, int32_t type, void*
 
 /* Number of packed parameters (the length of weights / grad_params). */
 int64_t nnp_num_params(const nnp_handle* h);
+
+/* Graph replay bookkeeping of a handle: evaluations captured into a graph
+ * and graph replays since creation, and graphs currently cached (each
+ * pointer may be NULL). */
+nnp_status nnp_graph_stats(const nnp_handle* h, int64_t* captures, int64_t* replays, int32_t* cached);
 
 /* AEV dimension D of the handle's featuriser. */
 int32_t nnp_aev_dim(const nnp_handle* h);
@@ -316,6 +342,20 @@ int32_t nnp_kernel_times(nnp_handle* h, int32_t cap, const char** names, int64_t
  *                         identical forces on every run, stream and launch
  *                         shape (the rest of an evaluation already is).
  *                         auto: 1.  The autotuner leaves this knob alone.
+ *   NNP_KNOB_FORCE_PATH   force kernel: 1 = each atom's dE/dAEV row staged in
+ *                         LDS, 2 = read from global memory (cache hits),
+ *                         leaving the LDS to the force sums.  auto: 2.
+ *   NNP_KNOB_PIPELINE     1 = one evaluation on the batch's stream; 2 = the
+ *                         molecules split in two halves evaluated on two
+ *                         streams (the handle's own second stream, forked from
+ *                         and joined back into the batch's), so that one half's
+ *                         featuriser and force kernels run beside the other
+ *                         half's network kernels.  Needs a second set of row
+ *                         buffers, allocated when the knob is first set to 2
+ *                         (by nnp_set_knob or the autotuner).  Batches of one
+ *                         molecule, device counts and nnp_aev run as one part.
+ *                         auto: 1 (each kernel of one part already fills the
+ *                         chip; the overlap has measured slower).
  *
  * Setting a knob drops the handle's captured graphs.  Invalid knob ids or
  * values return NNP_E_INVALID (a fused path on unsupported widths returns
@@ -329,7 +369,9 @@ enum {
     NNP_KNOB_ATOM_CHUNK = 5,
     NNP_KNOB_L1_PATH = 6,
     NNP_KNOB_FORCE_SUM = 7,
-    NNP_N_KNOBS = 8
+    NNP_KNOB_FORCE_PATH = 8,
+    NNP_KNOB_PIPELINE = 9,
+    NNP_N_KNOBS = 10
 };
 nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value);
 nnp_status nnp_get_knob(nnp_handle* h, int32_t knob, int32_t* value);

@@ -69,9 +69,10 @@ __device__ inline int pair_index(int b, int c, int S) {
 }
 
 // pair number p of the n(n-1)/2 pairs {j<k} of 0..n-1, row-major in j
-__host__ __device__ inline void decode_pair(int p, int n, int& j, int& k) {
+__device__ inline void decode_pair(int p, int n, int& j, int& k) {
+    // estimate from the hardware square root, corrected by the loops below
     float t = (float)(2 * n - 1);
-    int jj = (int)((t - sqrtf(fmaxf(t * t - 8.0f * (float)p, 0.0f))) * 0.5f);
+    int jj = (int)((t - __builtin_amdgcn_sqrtf(fmaxf(t * t - 8.0f * (float)p, 0.0f))) * 0.5f);
     jj = jj < 0 ? 0 : (jj > n - 2 ? n - 2 : jj);
     // start(j) = j (2n - j - 1) / 2
     while (jj > 0 && (jj * (2 * n - jj - 1)) / 2 > p) --jj;
@@ -118,7 +119,21 @@ __device__ inline int element_of(const int32_t* __restrict__ species, const int8
     return s < 0 || s >= S ? -1 : s;
 }
 
-__global__ __launch_bounds__(1024) void k_bucket_count(int A, int B, int S, int max_apm,
+// Atom range of a call: [mol_off[0], mol_off[B]).  A whole batch starts at 0
+// and ends at its atom count (A, or the device count dA); a sub-batch (one
+// part of a pipelined evaluation, sub = 1) may start anywhere and holds at
+// most A atoms.  Per-atom arrays are indexed by absolute atom number.
+__device__ inline bool atom_range(int A, int B, const int32_t* __restrict__ dA,
+                                  const int32_t* __restrict__ mol_off, int sub, int& a0, int& a1) {
+    a0 = mol_off[0];
+    a1 = mol_off[B];
+    const bool ok = sub ? (a0 >= 0 && a1 >= a0 && a1 - a0 <= A) : (a0 == 0 && a1 == (dA ? *dA : A));
+    if (!ok) a1 = a0;
+    return ok;
+}
+
+__global__ __launch_bounds__(1024) void k_bucket_count(int A, int B, int S, int max_apm, int sub,
+                                                       const int32_t* __restrict__ dA,
                                                        const int32_t* __restrict__ mol_off,
                                                        const int32_t* __restrict__ species,
                                                        const int8_t* __restrict__ zlut,
@@ -128,18 +143,19 @@ __global__ __launch_bounds__(1024) void k_bucket_count(int A, int B, int S, int 
                                                        int32_t* __restrict__ flag) {
     __shared__ int wcnt[kPrepBlock / 64][kMaxSpecies];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, blk = blockIdx.x;
-    if (blk == 0 && tid == 0 && (mol_off[0] != 0 || mol_off[B] != A)) atomicOr(flag, FLAG_CAPACITY);
+    int A0, A1;
+    if (!atom_range(A, B, dA, mol_off, sub, A0, A1) && blk == 0 && tid == 0) atomicOr(flag, FLAG_CAPACITY);
     // molecule ranges are checked once, by one thread per molecule
     const int b = blk * kPrepBlock + tid;
     if (b < B) {
-        const int a0 = mol_off[b], a1 = mol_off[b + 1];
-        if (a0 < 0 || a1 < a0 || a1 > A || a1 - a0 > max_apm) atomicOr(flag, FLAG_CAPACITY);
+        const int m0 = mol_off[b], m1 = mol_off[b + 1];
+        if (m0 < A0 || m1 < m0 || m1 > A1 || m1 - m0 > max_apm) atomicOr(flag, FLAG_CAPACITY);
     }
     // per atom: its molecule (last b with mol_off[b] <= a, by bisection) and
     // its element, counted per wave with ballots
-    const int a = blk * kPrepBlock + tid;
+    const int a = A0 + blk * kPrepBlock + tid;
     int s = -1;
-    if (a < A) {
+    if (a < A1) {
         int lo = 0, hi = B;   // mol_off[lo] <= a < mol_off[hi] for valid offsets
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -251,16 +267,21 @@ __global__ __launch_bounds__(256) void k_bucket_scan(int nblk, int S, int row_ti
         for (int r = base[q] + tot[q] + tid; r < base[q + 1] && r < rows; r += nt) atom_of_row[r] = -1;
 }
 
-__global__ __launch_bounds__(1024) void k_bucket_scatter(int A, int S, const int32_t* __restrict__ species,
+__global__ __launch_bounds__(1024) void k_bucket_scatter(int A, int B, int S, int sub,
+                                                         const int32_t* __restrict__ dA,
+                                                         const int32_t* __restrict__ mol_off,
+                                                         const int32_t* __restrict__ species,
                                                          const int32_t* __restrict__ blk_base,
                                                          const BucketInfo* __restrict__ info,
                                                          int32_t* __restrict__ row_of_atom,
                                                          int32_t* __restrict__ atom_of_row) {
     __shared__ int wcnt[kPrepBlock / 64][kMaxSpecies];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, blk = blockIdx.x;
-    const int a = blk * kPrepBlock + tid;
+    int A0, A1;
+    atom_range(A, B, dA, mol_off, sub, A0, A1);
+    const int a = A0 + blk * kPrepBlock + tid;
     int s = -1;
-    if (a < A) {
+    if (a < A1) {
         s = species[a];
         if (s < 0 || s >= S) s = 0;
     }
@@ -284,7 +305,8 @@ __global__ __launch_bounds__(1024) void k_bucket_scatter(int A, int S, const int
 // The three steps in one workgroup, for batches of at most kPrepBlock atoms
 // and molecules (one launch instead of three on small batches); same results.
 __global__ __launch_bounds__(1024) void k_bucket_one(int A, int B, int S, int max_apm, int row_tile,
-                                                     int Rcap, const int32_t* __restrict__ mol_off,
+                                                     int Rcap, int sub, const int32_t* __restrict__ dA,
+                                                     const int32_t* __restrict__ mol_off,
                                                      const int32_t* __restrict__ species,
                                                      const int8_t* __restrict__ zlut,
                                                      int32_t* __restrict__ sp_out,
@@ -298,14 +320,15 @@ __global__ __launch_bounds__(1024) void k_bucket_one(int A, int B, int S, int ma
     __shared__ int tot[kMaxSpecies];
     __shared__ int base[kMaxSpecies + 1];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    if (tid == 0 && (mol_off[0] != 0 || mol_off[B] != A)) atomicOr(flag, FLAG_CAPACITY);
+    int A0, A1;
+    if (!atom_range(A, B, dA, mol_off, sub, A0, A1) && tid == 0) atomicOr(flag, FLAG_CAPACITY);
     if (tid < B) {
-        const int a0 = mol_off[tid], a1 = mol_off[tid + 1];
-        if (a0 < 0 || a1 < a0 || a1 > A || a1 - a0 > max_apm) atomicOr(flag, FLAG_CAPACITY);
+        const int m0 = mol_off[tid], m1 = mol_off[tid + 1];
+        if (m0 < A0 || m1 < m0 || m1 > A1 || m1 - m0 > max_apm) atomicOr(flag, FLAG_CAPACITY);
     }
-    const int a = tid;
+    const int a = A0 + tid;
     int s = -1;
-    if (a < A) {
+    if (a < A1) {
         int lo = 0, hi = B;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -365,30 +388,61 @@ __global__ __launch_bounds__(1024) void k_bucket_one(int A, int B, int S, int ma
     }
 }
 
+// Batches whose counts live on the device: the call's launches are sized for
+// the bounds B and A (host), and this kernel copies the caller's offsets of
+// the counts[0] real molecules into the workspace, padding the rest of the
+// bound with empty molecules at counts[1] atoms, so every later kernel sees
+// a batch of B molecules of which the padding ones do nothing.  Counts
+// outside the bounds set the capacity flag and run an empty batch.
+__global__ __launch_bounds__(1024) void k_stage_batch(int B, int A, const int32_t* __restrict__ counts,
+                                                      const int32_t* __restrict__ mol_off,
+                                                      int32_t* __restrict__ moff, int32_t* __restrict__ dcnt,
+                                                      int32_t* __restrict__ flag) {
+    int Br = counts[0], Ar = counts[1];
+    // the offsets must end at the atom count (k_bucket_count checks the rest)
+    if (Br < 0 || Br > B || Ar < 0 || Ar > A || (Br > 0 ? mol_off[Br] : 0) != Ar || mol_off[0] != 0) {
+        if (threadIdx.x == 0) atomicOr(flag, FLAG_CAPACITY);
+        Br = 0;
+        Ar = 0;
+    }
+    for (int b = threadIdx.x; b <= B; b += blockDim.x) moff[b] = (b <= Br && Br > 0) ? mol_off[b] : Ar;
+    if (threadIdx.x == 0) {
+        dcnt[0] = Br;
+        dcnt[1] = Ar;
+    }
+}
+
+hipError_t launch_stage_batch(int B, int A, const int32_t* counts, const int32_t* mol_off, int32_t* moff,
+                              int32_t* dcnt, int32_t* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_stage_batch, dim3(1), dim3(1024), 0, st, B, A, counts, mol_off, moff, dcnt, flag);
+    return hipGetLastError();
+}
+
 template <typename P>
 hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* species,
                        Work<P>& w, hipStream_t st, const Timer& tm) {
     const int nblk = std::max((sh.A + kPrepBlock - 1) / kPrepBlock, (sh.B + kPrepBlock - 1) / kPrepBlock);
     int32_t* blk_cnt = w.blk;
     int32_t* blk_base = w.blk + (size_t)nblk * kMaxSpecies;
+    const int32_t* dA = sh.dev_counts ? w.dcnt + 1 : nullptr;
     tm.b("prep", st);
     if (nblk <= 1) {
         hipLaunchKernelGGL(k_bucket_one, dim3(1), dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S, sh.max_apm,
-                           sh.row_tile, sh.Rcap, mol_off, species, w.zlut, w.sp, w.mol_of_atom,
+                           sh.row_tile, sh.Rcap, sh.sub, dA, mol_off, species, w.zlut, w.sp, w.mol_of_atom,
                            w.row_of_atom, w.atom_of_row, w.tile_species, w.info, w.flag);
         tm.e("prep", st);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_bucket_count, dim3(nblk), dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S,
-                       sh.max_apm, mol_off, species, w.zlut, w.sp, w.mol_of_atom, blk_cnt, w.flag);
+                       sh.max_apm, sh.sub, dA, mol_off, species, w.zlut, w.sp, w.mol_of_atom, blk_cnt, w.flag);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(256), 0, st, nblk, sh.S, sh.row_tile, sh.Rcap,
                        blk_cnt, blk_base, w.atom_of_row, w.tile_species, w.info, w.flag);
     // on handles with atomic numbers the count kernel has written the
     // element indices to w.sp
     if (sh.A > 0)
         hipLaunchKernelGGL(k_bucket_scatter, dim3((sh.A + kPrepBlock - 1) / kPrepBlock),
-                           dim3(kPrepBlock), 0, st, sh.A, sh.S, w.zlut ? w.sp : species, blk_base,
-                           w.info, w.row_of_atom, w.atom_of_row);
+                           dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S, sh.sub, dA, mol_off,
+                           w.zlut ? w.sp : species, blk_base, w.info, w.row_of_atom, w.atom_of_row);
     tm.e("prep", st);
     return hipGetLastError();
 }
@@ -933,7 +987,10 @@ __device__ inline void pair_of(const AtomLists<T>& al, int NB, int S, int p, int
     const int u = p - al.bst[lo];
     if (a < b) {
         const int nb = al.aoff[b + 1] - al.aoff[b];
-        const int q = u / nb;
+        // u / nb through the float reciprocal, corrected (u < 2^16)
+        int q = (int)((float)u * __builtin_amdgcn_rcpf((float)nb));
+        if (q * nb > u) --q;
+        if ((q + 1) * nb <= u) ++q;
         j = al.aoff[a] + q;
         k = al.aoff[b] + (u - q * nb);
     } else {
@@ -1381,7 +1438,7 @@ template <typename T> struct ForceAcc<T, true> {
     }
 };
 
-template <typename P, int NZ, bool FIXED>
+template <typename P, int NZ, bool FIXED, bool GD>
 __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A, int max_apm,
                                                 int chunk, int cap, const int32_t* __restrict__ mol_off,
                                                 const int32_t* __restrict__ species,
@@ -1415,7 +1472,11 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
     T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
     int* nsp = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
     int* nid = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
-    T* g = lb.take<T>((size_t)nw * GL) + (size_t)wave * GL;
+    // the atom's dE/dAEV row: staged in LDS (blocks kBlkPad apart), or read
+    // straight from global memory (GD: L1/L2 hits, the LDS left to the
+    // force sums)
+    T* g = GD ? nullptr : lb.take<T>((size_t)nw * GL) + (size_t)wave * GL;
+    constexpr int BS = GD ? kNAZ : kBlkPad;
 
     cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, row_of_atom);
     for (int t = tid; t < 3 * n; t += blockDim.x) sF[t] = V(0);
@@ -1424,9 +1485,10 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
         const int il = i0 + ic;
         const int cnt = cs.ccnt[ic];
         const int nang = cnt & 0xffff, nall = cnt >> 16;
+        const TA* gsrc = dG + (size_t)cs.crow[ic] * c.Dp;
         // the atom's dE/dAEV row: 16 values per lane and load, all in flight
         // before the first use; groups of 16 never straddle a block
-        {
+        if constexpr (!GD) {
             const TA* src = dG + (size_t)cs.crow[ic] * c.Dp;
             TA v[2][16];
 #pragma unroll
@@ -1461,7 +1523,14 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
                 const T* e = nb + kNbStride * t;
                 const T r = e[3], fc = e[4], dfc = e[5];
                 T gg[4];
-                ld4(g + kNR * nsp[t] + 4 * q, gg);
+                if constexpr (GD) {
+                    TA ga[4];
+                    ld4(gsrc + kNR * nsp[t] + 4 * q, ga);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) gg[kk] = (T)ga[kk];
+                } else {
+                    ld4(g + kNR * nsp[t] + 4 * q, gg);
+                }
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const T d = r - c.shf_r[4 * q + kk];
@@ -1504,7 +1573,8 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
             const T fcj = ej[6], fck = ek[6], dfcj = ej[7], dfck = ek[7];
             const T fcc = fcj * fck;
             const T rm = T(0.5) * (rj + rk);
-            const T* gb = g + RL + kBlkPad * pair_index(nsp[j], nsp[k], S);
+            const int pb = RL + BS * pair_index(nsp[j], nsp[k], S);
+            const T* gb = GD ? nullptr : g + pb;
             T fz[NZ], dfz[NZ];
 #pragma unroll
             for (int z = 0; z < NZ; ++z) {
@@ -1526,7 +1596,14 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
 #pragma unroll
                 for (int z4 = 0; z4 < NZ; z4 += 4) {
                     T gg[4];
-                    ld4(gb + NZ * a + z4, gg);
+                    if constexpr (GD) {
+                        TA ga[4];
+                        ld4(gsrc + pb + NZ * a + z4, ga);
+#pragma unroll
+                        for (int z = 0; z < 4; ++z) gg[z] = (T)ga[z];
+                    } else {
+                        ld4(gb + NZ * a + z4, gg);
+                    }
 #pragma unroll
                     for (int z = 0; z < 4; ++z) {
                         sg += gg[z] * fz[z4 + z];
@@ -1572,12 +1649,12 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
 }
 
 template <typename T>
-static size_t forces_lds(int max_apm, int cap, int S, int nw, bool fixed = false) {
+static size_t forces_lds(int max_apm, int cap, int S, int nw, bool fixed = false, bool gd = false) {
     const int GL = kNR * S + kBlkPad * S * (S + 1) / 2;
     return ChunkStage<T>::bytes(max_apm, cap) +
            (fixed ? lds_bytes<unsigned long long>(3 * (size_t)max_apm) : lds_bytes<T>(3 * (size_t)max_apm)) +
            lds_bytes<T>((size_t)nw * cap * kNbStride) + 2 * lds_bytes<int>((size_t)nw * cap) +
-           lds_bytes<T>((size_t)nw * GL);
+           (gd ? 0 : lds_bytes<T>((size_t)nw * GL));
 }
 
 template <typename P>
@@ -1588,12 +1665,14 @@ hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
     if (c.Dp > 2 * 16 * 64) return hipErrorInvalidValue;
     dim3 grid(sh.B, (sh.max_apm + sh.chunk - 1) / sh.chunk);
     int nw = kWaves;
-    const bool fixed = sh.force_fixed != 0;
-    size_t lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw, fixed);
-    while (lds > kMaxLds && nw > 1) lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw /= 2, fixed);
+    const bool fixed = sh.force_fixed != 0, gd = sh.force_path == 2;
+    size_t lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw, fixed, gd);
+    while (lds > kMaxLds && nw > 1) lds = forces_lds<T>(sh.max_apm, sh.cap_nbr, sh.S, nw /= 2, fixed, gd);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    auto kern = fixed ? (c.nZ == 4 ? k_forces<P, 4, true> : k_forces<P, 8, true>)
-                      : (c.nZ == 4 ? k_forces<P, 4, false> : k_forces<P, 8, false>);
+    auto kern = gd ? (fixed ? (c.nZ == 4 ? k_forces<P, 4, true, true> : k_forces<P, 8, true, true>)
+                            : (c.nZ == 4 ? k_forces<P, 4, false, true> : k_forces<P, 8, false, true>))
+                   : (fixed ? (c.nZ == 4 ? k_forces<P, 4, true, false> : k_forces<P, 8, true, false>)
+                            : (c.nZ == 4 ? k_forces<P, 4, false, false> : k_forces<P, 8, false, false>));
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("forces", st);
@@ -1905,11 +1984,12 @@ __global__ __launch_bounds__(256) void k_energy(int A, int B, int M, int NT, dou
                                                 const double* __restrict__ sae,
                                                 double* __restrict__ E,
                                                 const unsigned long long* __restrict__ Fq,
-                                                typename P::T* __restrict__ F, int accumulate) {
+                                                typename P::T* __restrict__ F, int accumulate,
+                                                const int32_t* __restrict__ dcnt) {
     typedef typename P::T T;
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = lane_id();
-    if (b >= B) return;
+    if (b >= B || (dcnt && b >= dcnt[0])) return;   // past the batch (or its padding)
     int a0 = mol_off[b], a1 = mol_off[b + 1];
     if (a0 < 0 || a1 < a0 || a1 > A) a1 = a0 = 0;
     if (Fq)
@@ -1945,7 +2025,7 @@ hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t
     hipLaunchKernelGGL(k_energy<P>, dim3((sh.B + 3) / 4), dim3(256), 0, st, sh.A, sh.B, sh.M,
                        w.epart_nt, sh.energy_scale, mol_off, species, sh.S, w.row_of_atom,
                        w.Epart, wt.b4, wt.sae, E, (sh.force_fixed && F) ? w.Fq : nullptr, F,
-                       accumulate ? 1 : 0);
+                       accumulate ? 1 : 0, sh.dev_counts ? w.dcnt : nullptr);
     tm.e("energy", st);
     return hipGetLastError();
 }

@@ -130,6 +130,8 @@ template <typename P> struct Work {
     int epart_nt;           // partials per row and model (set by launch_mlp)
     TA* dG;                 // [Rcap][Dp]
     unsigned long long* Fq; // [A][3]  fixed-point force sums (2^32 units, two's complement)
+    int32_t* moff;          // [max_mols+1]  offsets padded to the launch bound (device counts)
+    int32_t* dcnt;          // [2]  the batch's molecule and atom counts (device counts)
 };
 
 // extra workspace of the training backward (allocated on its first call)
@@ -214,7 +216,14 @@ struct Shape {
     int tail_tile;                     // fused kernel tile variant (1, 2 or 3)
     int chunk;                         // central atoms per featuriser / force workgroup (4, 8, 16)
     int force_fixed;                   // 1: forces summed in 64-bit fixed point (bitwise reproducible)
+    int force_path;                    // force kernel: 1 dE/dAEV row staged in LDS, 2 read from global
+    int h3_used;                       // layer-3 width before padding (the widest element network's)
+    int dev_counts;                    // 1: A and B are launch bounds; the counts are in Work::dcnt
+    int sub;                           // 1: one part of a pipelined evaluation (atoms need not start at 0)
+    int pipeline;                      // 2: large batches evaluated as two pipelined parts on two streams
 };
+hipError_t launch_stage_batch(int B, int A, const int32_t* counts, const int32_t* mol_off, int32_t* moff,
+                              int32_t* dcnt, int32_t* flag, hipStream_t st);
 
 // kernel timing hook (runtime-side); launchers call these around launches
 struct Timer {

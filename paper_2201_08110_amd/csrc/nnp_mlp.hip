@@ -793,31 +793,34 @@ template <typename TS> struct Sliced {
 // MFMAs of step t; the empty asm with a memory clobber keeps the compiler from
 // sinking those loads next to their use, so two k-steps of MFMAs (and the
 // other waves) cover the L2 latency.
-template <typename TS, int BM, int FM, int FN, int K>
+// K: the reduction length used; KS: the K the fragment-ordered matrix is
+// stored with (its k-steps per n-tile)
+template <typename TS, int BM, int FM, int FN, int K, int KS = K>
 __device__ inline void tail_product(typename MF<TS>::Acc (&acc)[FM][FN], const TS* As, int m0,
                                     const TS* __restrict__ Bf, int nt0, int lane) {
     typedef MF<TS> mf;
     typedef Sliced<TS> L;
     typedef typename mf::Frag Frag;
-    constexpr int NS = K / mf::KM, PD = 2;
+    constexpr int NS = K / mf::KM, NSS = KS / mf::KM, PD = 2;
+    static_assert(K % mf::KM == 0 && K <= KS, "reduction length");
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
-    const TS* Bl = Bf + (size_t)nt0 * NS * 64 * mf::KL + lane * mf::KL;
+    const TS* Bl = Bf + (size_t)nt0 * NSS * 64 * mf::KL + lane * mf::KL;
     Frag bq[PD + 1][FN];
 #pragma unroll
     for (int t = 0; t < PD && t < NS; ++t)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) bq[t][j] = *(const Frag*)(Bl + ((size_t)j * NS + t) * 64 * mf::KL);
+        for (int j = 0; j < FN; ++j) bq[t][j] = *(const Frag*)(Bl + ((size_t)j * NSS + t) * 64 * mf::KL);
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
         if (t + PD < NS) {
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-                bq[(t + PD) % (PD + 1)][j] = *(const Frag*)(Bl + ((size_t)j * NS + t + PD) * 64 * mf::KL);
+                bq[(t + PD) % (PD + 1)][j] = *(const Frag*)(Bl + ((size_t)j * NSS + t + PD) * 64 * mf::KL);
         }
         asm volatile("" ::: "memory");
         const int kf = t * mf::KM + (lane >> 4) * mf::KL;
@@ -877,7 +880,10 @@ struct TailShape {
     static constexpr size_t lds_bytes() { return hs + (u1 > u2 ? u1 : u2) + sizeof(typename P::TA) * BM * 4 + par; }
 };
 
-template <typename P, int BM, int TW, int H1, int H2, int H3>
+// H3 is the stored (padded) width of layer 3, H3L <= H3 the width the
+// products use: the weights past H3L are zero padding, so layer 3 forward
+// computes only H3L outputs and its backward reduces over H3L
+template <typename P, int BM, int TW, int H1, int H2, int H3, int H3L = H3>
 __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
     typedef typename P::TS TS;
     typedef typename P::TA TA;
@@ -964,45 +970,53 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
         }
     }
     __syncthreads();   // H2 complete; the H1 tile is dead from here on
-    // ---- layer 3 forward, output layer, dE/dz3
+    // ---- layer 3 forward, output layer, dE/dz3: the H3L / 16 column tiles
+    // dealt to the four waves as evenly as they go (160: 2, 3, 2, 3), each
+    // wave running a product with its own static tile count
     {
-        constexpr int FN = H3 / 64;
-        Acc acc[FM][FN];
-        const int n0 = wn * (H3 / 4);
-        tail_product<TS, BM, FM, FN, H2>(acc, Hs, m0, g.W3f + sz * H3 * H2, n0 / 16, lane);
-        const TA* b3 = sb3;
-        const TA* w4 = sw4;
-        TA part[FM];
+        constexpr int F3 = H3L / 16, FNX = (F3 + 3) / 4;
+        const int f0 = (wn * F3) / 4, fn = ((wn + 1) * F3) / 4 - f0;
+        auto layer3 = [&](auto fn_c) {
+            constexpr int FN = decltype(fn_c)::value;
+            Acc acc[FM][FN];
+            const int n0 = 16 * f0;
+            tail_product<TS, BM, FM, FN, H2>(acc, Hs, m0, g.W3f + sz * H3 * H2, f0, lane);
+            const TA* b3 = sb3;
+            const TA* w4 = sw4;
+            TA part[FM];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) part[i] = 0;
+            for (int i = 0; i < FM; ++i) part[i] = 0;
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int c = n0 + j * 16 + cl;
-            TA bb[4], ww[4];
+            for (int j = 0; j < FN; ++j) {
+                const int c = n0 + j * 16 + cl;
+                TA bb[4], ww[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                bb[q] = b3[c + q * ST];
-                ww[q] = w4[c + q * ST];
+                for (int q = 0; q < 4; ++q) {
+                    bb[q] = b3[c + q * ST];
+                    ww[q] = w4[c + q * ST];
+                }
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    TA v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const TA zz = (TA)acc[i][j][q] + bb[q];
+                        part[i] += ww[q] * celu(zz, g.alpha, g.inv_alpha);
+                        v[q] = dcelu_z(zz, g.inv_alpha) * ww[q] * g.gscale;
+                    }
+                    LdsQuad<TS, ST>::st(Us, BM, m0 + i * 16 + rl, c, v);
+                }
             }
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
-                TA v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const TA zz = (TA)acc[i][j][q] + bb[q];
-                    part[i] += ww[q] * celu(zz, g.alpha, g.inv_alpha);
-                    v[q] = dcelu_z(zz, g.inv_alpha) * ww[q] * g.gscale;
-                }
-                LdsQuad<TS, ST>::st(Us, BM, m0 + i * 16 + rl, c, v);
+                TA v = part[i];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                if (lane < 16) red[(m0 + i * 16 + lane) * 4 + wn] = v;
             }
-        }
-#pragma unroll
-        for (int i = 0; i < FM; ++i) {
-            TA v = part[i];
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
-            if (lane < 16) red[(m0 + i * 16 + lane) * 4 + wn] = v;
-        }
+        };
+        if (fn == FNX || F3 % 4 == 0) layer3(std::integral_constant<int, FNX>{});
+        else layer3(std::integral_constant<int, (FNX > 1 ? FNX - 1 : 1)>{});
     }
     __syncthreads();   // DZ3 and the energy partials complete
     if (tid < BM) {
@@ -1016,7 +1030,7 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
         constexpr int FN = H2 / 64;
         Acc acc[FM][FN];
         const int n0 = wn * (H2 / 4);
-        tail_product<TS, BM, FM, FN, H3>(acc, Us, m0, g.W3Tf + sz * H2 * H3, n0 / 16, lane);
+        tail_product<TS, BM, FM, FN, H3L, H3>(acc, Us, m0, g.W3Tf + sz * H2 * H3, n0 / 16, lane);
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int c = n0 + j * 16 + cl;
@@ -1082,7 +1096,7 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
 // padded to 192); other widths take the per-layer GEMMs
 constexpr int kTailH1 = 256, kTailH2 = 192, kTailH3 = 192;
 
-template <typename P, int BM, int TW>
+template <typename P, int BM, int TW, int H3L = kTailH3>
 static hipError_t run_tail(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, hipStream_t st,
                            const Timer& tm) {
     typedef typename P::TA TA;
@@ -1100,7 +1114,7 @@ static hipError_t run_tail(const Shape& sh, const DevWeights<P>& wt, Work<P>& w,
     a.nm = sh.Rcap / BM;
     const int T = a.nm * sh.M;
     const size_t lds = TailShape<P, BM, kTailH1, kTailH2, kTailH3>::lds_bytes();
-    auto kern = k_tail<P, BM, TW, kTailH1, kTailH2, kTailH3>;
+    auto kern = k_tail<P, BM, TW, kTailH1, kTailH2, kTailH3, H3L>;
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("mlp_tail", st);
@@ -1164,7 +1178,7 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     typedef typename P::TA TA;
     typedef Cfg<P, BM> C;
     const int M = sh.M, H1 = sh.H1, H2 = sh.H2, H3 = sh.H3, Dp = sh.Dp;
-    hipError_t e;
+    hipError_t e = hipSuccess;
     GemmArgs<P> base{};
     base.tile_species = w.tile_species;
     base.row_tile = sh.row_tile;
@@ -1203,10 +1217,16 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
         // fused layers 2-3 forward and backward
         w.epart_nt = 1;
         constexpr int TB = TailBM<P>::v, TH = TB / 2 >= 16 ? TB / 2 : 16;
-        if (BM == 16) e = run_tail<P, 16, 1>(sh, wt, w, st, tm);
-        else if (sh.tail_tile == 2) e = run_tail<P, TH, 1>(sh, wt, w, st, tm);
-        else if (sh.tail_tile == 3 && TB >= 32) e = run_tail<P, TB, TB >= 32 ? 2 : 1>(sh, wt, w, st, tm);
-        else e = run_tail<P, TB, 1>(sh, wt, w, st, tm);
+        // layer 3 of at most 160 outputs (ANI-2x): products over the 160 real
+        // columns, not the 192 the storage is padded to
+        const bool n160 = sh.h3_used <= 160;
+        if (BM == 16) e = n160 ? run_tail<P, 16, 1, 160>(sh, wt, w, st, tm) : run_tail<P, 16, 1>(sh, wt, w, st, tm);
+        else if (sh.tail_tile == 2)
+            e = n160 ? run_tail<P, TH, 1, 160>(sh, wt, w, st, tm) : run_tail<P, TH, 1>(sh, wt, w, st, tm);
+        else if (sh.tail_tile == 3 && TB >= 32)
+            e = n160 ? run_tail<P, TB, TB >= 32 ? 2 : 1, 160>(sh, wt, w, st, tm)
+                     : run_tail<P, TB, TB >= 32 ? 2 : 1>(sh, wt, w, st, tm);
+        else e = n160 ? run_tail<P, TB, 1, 160>(sh, wt, w, st, tm) : run_tail<P, TB, 1>(sh, wt, w, st, tm);
         if (e) return e;
         return mlp_l1_bwd<P, BM>(sh, wt, w, base, st, tm);
     }

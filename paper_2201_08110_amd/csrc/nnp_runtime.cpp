@@ -58,12 +58,12 @@ struct EventPair {
 struct GraphEntry {
     int A = 0, B = 0;
     uint32_t flags = 0;
-    const void* ptr[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const void* ptr[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     hipStream_t stream = nullptr;
     hipGraphExec_t exec = nullptr;
     bool same(int a, int b, uint32_t f, const void* const* p, hipStream_t s) const {
         if (a != A || b != B || f != flags || s != stream) return false;
-        for (int i = 0; i < 5; ++i)
+        for (int i = 0; i < 6; ++i)
             if (p[i] != ptr[i]) return false;
         return true;
     }
@@ -102,6 +102,15 @@ struct nnp_handle {
     Work<PrecF64> k64{};
     Work<PrecF32> k32{};
     Work<PrecBF16> k16{};
+    // the second part of a pipelined evaluation: its own row buffers (the
+    // per-atom arrays are shared, indexed by absolute atom number), a second
+    // stream (default priority) and the events that order the two parts
+    bool pipe_ready = false;
+    Work<PrecF64> k64b{};
+    Work<PrecF32> k32b{};
+    Work<PrecBF16> k16b{};
+    hipStream_t st2 = nullptr;
+    hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t* flag = nullptr;
     int8_t* zlut = nullptr;       // device [kZLut]: element of each atomic number, or null
     hipStream_t last_stream = nullptr;
@@ -114,8 +123,10 @@ struct nnp_handle {
     double* train_E = nullptr;    // [max_mols]
     NetLayout nl{};
 
-    // captured evaluations (most recent last)
+    // captured evaluations (most recent last), and how often graphs were
+    // captured and replayed
     std::vector<GraphEntry> graphs;
+    int64_t n_captures = 0, n_replays = 0;
 
     // tunable knobs as set by the caller (0 = automatic)
     int32_t knob[NNP_N_KNOBS] = {};
@@ -308,6 +319,43 @@ template <typename P> nnp_status upload_weights(nnp_handle* h, DevWeights<P>& dw
     return NNP_OK;
 }
 
+// Row buffers of the pipeline's second part (sized for the whole capacity:
+// one part may hold nearly every atom); the per-atom arrays are the first
+// workspace's.
+template <typename P> nnp_status alloc_work2(nnp_handle* h, const Work<P>& w1, Work<P>& w) {
+    typedef typename P::TS TS;
+    typedef typename P::TA TA;
+    const Shape& sh = h->shape;
+    const size_t A = (size_t)std::max(h->max_atoms, 1), R = sh.Rcap;
+    const int M = sh.M;
+    hipError_t e = hipSuccess;
+    w = w1;
+#define ALLOC(field, bytes)                                                              \
+    do {                                                                                 \
+        w.field = (decltype(w.field))h->dalloc(bytes, e);                                \
+        if (e != hipSuccess)                                                             \
+            return fail(e == hipErrorOutOfMemory ? NNP_E_NOMEM : NNP_E_DEVICE,           \
+                        std::string("pipeline workspace ") + #field + ": " + hipGetErrorString(e)); \
+    } while (0)
+    ALLOC(atom_of_row, sizeof(int32_t) * R);
+    ALLOC(tile_species, sizeof(int32_t) * (R / sh.row_tile));
+    ALLOC(info, sizeof(BucketInfo));
+    const size_t nblk = (std::max(A, (size_t)h->max_mols) + kPrepBlock - 1) / kPrepBlock + 1;
+    ALLOC(blk, sizeof(int32_t) * 2 * kMaxSpecies * nblk);
+    ALLOC(G, sizeof(TS) * R * sh.Dp);
+    ALLOC(H1, sizeof(TS) * R * M * sh.H1);
+    ALLOC(H2, sizeof(TS) * R * M * sh.H2);
+    ALLOC(DZ3, sizeof(TS) * R * M * sh.H3);
+    ALLOC(DZ2, sizeof(TS) * R * M * sh.H2);
+    ALLOC(DZ1, sizeof(TS) * R * M * sh.H1);
+    ALLOC(Epart, sizeof(TA) * R * M * (sh.H3 / 64));
+    ALLOC(dG, sizeof(TA) * R * sh.Dp);
+#undef ALLOC
+    HIP_TRY(hipMemset(w.info, 0, sizeof(BucketInfo)));
+    HIP_TRY(hipMemset(w.G, 0, sizeof(TS) * R * sh.Dp));
+    return NNP_OK;
+}
+
 template <typename P> nnp_status alloc_work(nnp_handle* h, Work<P>& w) {
     typedef typename P::TS TS;
     typedef typename P::TA TA;
@@ -340,6 +388,8 @@ template <typename P> nnp_status alloc_work(nnp_handle* h, Work<P>& w) {
     ALLOC(Epart, sizeof(TA) * R * M * (sh.H3 / 64));
     ALLOC(dG, sizeof(TA) * R * sh.Dp);
     ALLOC(Fq, sizeof(unsigned long long) * 3 * A);
+    ALLOC(moff, sizeof(int32_t) * ((size_t)h->max_mols + 1));
+    ALLOC(dcnt, sizeof(int32_t) * 2);
     if (h->zlut) ALLOC(sp, sizeof(int32_t) * A);
 #undef ALLOC
     w.epart_nt = sh.H3 / 64;
@@ -362,7 +412,10 @@ nnp_status check_batch(const nnp_handle* h, const nnp_batch* b) {
     if (b->n_atoms > h->max_atoms) return fail(NNP_E_CAPACITY, "n_atoms exceeds max_atoms");
     if (!b->mol_offsets) return fail(NNP_E_INVALID, "null mol_offsets");
     if (b->n_atoms > 0 && !b->species) return fail(NNP_E_INVALID, "null species");
-    if (b->flags & ~(NNP_FLAG_GRAPH | NNP_FLAG_ACCUMULATE)) return fail(NNP_E_INVALID, "unknown flags");
+    if (b->flags & ~(NNP_FLAG_GRAPH | NNP_FLAG_ACCUMULATE | NNP_FLAG_DEVICE_COUNTS))
+        return fail(NNP_E_INVALID, "unknown flags");
+    if ((b->flags & NNP_FLAG_DEVICE_COUNTS) && !b->counts)
+        return fail(NNP_E_INVALID, "NNP_FLAG_DEVICE_COUNTS needs the device counts");
     if ((b->flags & NNP_FLAG_GRAPH) && !b->stream)
         return fail(NNP_E_INVALID, "graph replay needs a non-null stream");
     return NNP_OK;
@@ -372,6 +425,10 @@ template <typename P> Work<P>& work_of(nnp_handle* h);
 template <> Work<PrecF64>& work_of<PrecF64>(nnp_handle* h) { return h->k64; }
 template <> Work<PrecF32>& work_of<PrecF32>(nnp_handle* h) { return h->k32; }
 template <> Work<PrecBF16>& work_of<PrecBF16>(nnp_handle* h) { return h->k16; }
+template <typename P> Work<P>& work2_of(nnp_handle* h);
+template <> Work<PrecF64>& work2_of<PrecF64>(nnp_handle* h) { return h->k64b; }
+template <> Work<PrecF32>& work2_of<PrecF32>(nnp_handle* h) { return h->k32b; }
+template <> Work<PrecBF16>& work2_of<PrecBF16>(nnp_handle* h) { return h->k16b; }
 template <typename P> DevWeights<P>& weights_of(nnp_handle* h);
 template <> DevWeights<PrecF64>& weights_of<PrecF64>(nnp_handle* h) { return h->w64; }
 template <> DevWeights<PrecF32>& weights_of<PrecF32>(nnp_handle* h) { return h->w32; }
@@ -410,6 +467,8 @@ int32_t knob_value(const nnp_handle* h, int k) {
         if (v) return v;
         return l1_regs_supported(h) ? 2 : 1;
     case NNP_KNOB_FORCE_SUM: return v ? v : 1;
+    case NNP_KNOB_FORCE_PATH: return v ? v : 2;
+    case NNP_KNOB_PIPELINE: return v ? v : 1;
     }
     return 0;
 }
@@ -424,6 +483,8 @@ void apply_knobs(nnp_handle* h) {
     h->shape.chunk = knob_value(h, NNP_KNOB_ATOM_CHUNK);
     h->shape.l1_path = knob_value(h, NNP_KNOB_L1_PATH);
     h->shape.force_fixed = knob_value(h, NNP_KNOB_FORCE_SUM) == 2;
+    h->shape.force_path = knob_value(h, NNP_KNOB_FORCE_PATH);
+    h->shape.pipeline = knob_value(h, NNP_KNOB_PIPELINE);
     for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     h->graphs.clear();
 }
@@ -435,31 +496,143 @@ template <typename P> const int32_t* elements_of(const Work<P>& w, const nnp_bat
     return w.zlut ? w.sp : b->species;
 }
 
+// launch bounds of a batch with device-side counts: the host's upper bounds
+// rounded up to powers of two (at most the capacity), so batches of many
+// sizes share one captured graph
+int pow2_bound(int v, int cap) {
+    int p = 1;
+    while (p < v && p < cap) p <<= 1;
+    return std::min(p, cap);
+}
+void launch_bounds(const nnp_handle* h, const nnp_batch* b, int& A, int& B) {
+    A = b->n_atoms;
+    B = b->n_mols;
+    if (b->flags & NNP_FLAG_DEVICE_COUNTS) {
+        A = pow2_bound(std::max(A, 1), h->max_atoms);
+        B = pow2_bound(std::max(B, 1), h->max_mols);
+    }
+}
+
+// The three stages of an evaluation of molecules [moff[0], moff[B]):
+// featurisation (bucketing, neighbour lists, AEV rows), the networks, and
+// the forces and energies.
+template <typename P>
+nnp_status stage_features(nnp_handle* h, const Shape& sh, const int32_t* moff, const int32_t* species,
+                          const typename P::T* x, typename P::T* F, bool acc, Work<P>& w, hipStream_t st,
+                          const Timer& tm) {
+    const AevConst<typename P::T>& c = const_of<typename P::T>(h);
+    HIP_TRY(launch_prep<P>(sh, moff, species, w, st, tm));
+    const int32_t* sp = w.zlut ? w.sp : species;
+    if (sh.A > 0) {
+        HIP_TRY(launch_neighbours<P>(sh, c, moff, sp, x, F, acc, w, st, tm));
+        HIP_TRY(launch_aev<P>(sh, c, moff, sp, x, w, nullptr, st, tm));
+    }
+    return NNP_OK;
+}
+template <typename P>
+nnp_status stage_finish(nnp_handle* h, const Shape& sh, const int32_t* moff, const int32_t* species,
+                        const typename P::T* x, double* E, typename P::T* F, bool acc, Work<P>& w,
+                        hipStream_t st, const Timer& tm) {
+    const AevConst<typename P::T>& c = const_of<typename P::T>(h);
+    const int32_t* sp = w.zlut ? w.sp : species;
+    if (F && sh.A > 0) HIP_TRY(launch_forces<P>(sh, c, moff, sp, x, w, F, st, tm));
+    HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), moff, sp, w, E, sh.A > 0 ? F : nullptr, acc, st, tm));
+    return NNP_OK;
+}
+
+// Pipelined evaluation in two parts (molecules [0, B/2) and [B/2, B)) on two
+// streams: the second part's featurisation (vector ALU work) runs while the
+// first part's networks (matrix-core work) run, and the first part's forces
+// while the second part's networks run; the two network stages run one after
+// the other, so no two instances of a kernel run together.
+// The pipeline's second workspace, stream and events, made when the knob
+// first selects the pipelined evaluation (at creation when it is the
+// automatic choice).
+nnp_status ensure_pipeline(nnp_handle* h) {
+    if (h->shape.pipeline != 2 || h->pipe_ready) return NNP_OK;
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
+    nnp_status rc;
+    if (h->precision == NNP_PREC_FP64) rc = alloc_work2<PrecF64>(h, h->k64, h->k64b);
+    else if (h->precision == NNP_PREC_FP32) rc = alloc_work2<PrecF32>(h, h->k32, h->k32b);
+    else rc = alloc_work2<PrecBF16>(h, h->k16, h->k16b);
+    if (rc) return rc;
+    if (!h->st2) HIP_TRY(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking));
+    for (auto& e : h->pev)
+        if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->pipe_ready = true;
+    return NNP_OK;
+}
+
+template <typename P>
+nnp_status run_forward_split(nnp_handle* h, const nnp_batch* b, const typename P::T* x, double* E,
+                             typename P::T* F) {
+    const bool acc = (b->flags & NNP_FLAG_ACCUMULATE) != 0;
+    hipStream_t st = (hipStream_t)b->stream, st2 = h->st2;
+    h->last_stream = st;
+    Shape s1 = h->shape, s2 = h->shape;
+    const int B1 = b->n_mols / 2;
+    s1.A = s2.A = b->n_atoms;   // launch bound of each part
+    s1.B = B1;
+    s2.B = b->n_mols - B1;
+    s1.sub = s2.sub = 1;
+    const int32_t* m1 = b->mol_offsets;
+    const int32_t* m2 = b->mol_offsets + B1;
+    Work<P>& w1 = work_of<P>(h);
+    Work<P>& w2 = work2_of<P>(h);
+    Timer tm = make_timer(h);
+    HIP_TRY(hipEventRecord(h->pev[0], st));
+    HIP_TRY(hipStreamWaitEvent(st2, h->pev[0], 0));
+    nnp_status rc = stage_features<P>(h, s1, m1, b->species, x, F, acc, w1, st, tm);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(h->pev[1], st));
+    HIP_TRY(hipStreamWaitEvent(st2, h->pev[1], 0));
+    if ((rc = stage_features<P>(h, s2, m2, b->species, x, F, acc, w2, st2, tm))) return rc;
+    HIP_TRY(launch_mlp<P>(s1, weights_of<P>(h), w1, st, tm));
+    HIP_TRY(hipEventRecord(h->pev[2], st));
+    HIP_TRY(hipStreamWaitEvent(st2, h->pev[2], 0));
+    HIP_TRY(launch_mlp<P>(s2, weights_of<P>(h), w2, st2, tm));
+    if ((rc = stage_finish<P>(h, s1, m1, b->species, x, E, F, acc, w1, st, tm))) return rc;
+    if ((rc = stage_finish<P>(h, s2, m2, b->species, x, E + B1, F, acc, w2, st2, tm))) return rc;
+    HIP_TRY(hipEventRecord(h->pev[3], st2));
+    HIP_TRY(hipStreamWaitEvent(st, h->pev[3], 0));
+    return NNP_OK;
+}
+
 template <typename P>
 nnp_status run_forward(nnp_handle* h, const nnp_batch* b, const typename P::T* x, double* E,
                        typename P::T* F, typename P::T* aev_out) {
     typedef typename P::T T;
+    if (h->shape.pipeline == 2 && h->pipe_ready && !aev_out && b->n_mols >= 2 &&
+        !(b->flags & NNP_FLAG_DEVICE_COUNTS))
+        return run_forward_split<P>(h, b, x, E, F);
     Shape sh = h->shape;
-    sh.A = b->n_atoms;
-    sh.B = b->n_mols;
+    launch_bounds(h, b, sh.A, sh.B);
+    sh.dev_counts = (b->flags & NNP_FLAG_DEVICE_COUNTS) ? 1 : 0;
     const bool acc = (b->flags & NNP_FLAG_ACCUMULATE) != 0;
     hipStream_t st = (hipStream_t)b->stream;
     h->last_stream = st;
     Work<P>& w = work_of<P>(h);
     const AevConst<T>& c = const_of<T>(h);
     Timer tm = make_timer(h);
-    HIP_TRY(launch_prep<P>(sh, b->mol_offsets, b->species, w, st, tm));
+    const int32_t* moff = b->mol_offsets;
+    if (sh.dev_counts) {
+        tm.b("prep", st);
+        HIP_TRY(launch_stage_batch(sh.B, sh.A, b->counts, b->mol_offsets, w.moff, w.dcnt, w.flag, st));
+        tm.e("prep", st);
+        moff = w.moff;
+    }
+    HIP_TRY(launch_prep<P>(sh, moff, b->species, w, st, tm));
     const int32_t* sp = elements_of(w, b);
     if (sh.A > 0) {
-        HIP_TRY(launch_neighbours<P>(sh, c, b->mol_offsets, sp, x, F, acc, w, st, tm));
-        HIP_TRY(launch_aev<P>(sh, c, b->mol_offsets, sp, x, w, aev_out, st, tm));
+        HIP_TRY(launch_neighbours<P>(sh, c, moff, sp, x, F, acc, w, st, tm));
+        HIP_TRY(launch_aev<P>(sh, c, moff, sp, x, w, aev_out, st, tm));
     }
     if (aev_out) return NNP_OK;
     if (sh.A > 0) HIP_TRY(launch_mlp<P>(sh, weights_of<P>(h), w, st, tm));
     if (F && sh.A > 0)
-        HIP_TRY(launch_forces<P>(sh, c, b->mol_offsets, sp, x, w, F, st, tm));
-    HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), b->mol_offsets, sp, w, E, sh.A > 0 ? F : nullptr, acc,
-                             st, tm));
+        HIP_TRY(launch_forces<P>(sh, c, moff, sp, x, w, F, st, tm));
+    HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), moff, sp, w, E, sh.A > 0 ? F : nullptr, acc, st, tm));
     return NNP_OK;
 }
 
@@ -470,11 +643,14 @@ template <typename P>
 nnp_status run_forward_graph(nnp_handle* h, const nnp_batch* b, const typename P::T* x, double* E,
                              typename P::T* F) {
     hipStream_t st = (hipStream_t)b->stream;
-    const void* key[5] = {b->mol_offsets, b->species, x, E, F};
+    const void* key[6] = {b->mol_offsets, b->species, x, E, F, b->counts};
+    int kA, kB;
+    launch_bounds(h, b, kA, kB);
     for (size_t i = 0; i < h->graphs.size(); ++i)
-        if (h->graphs[i].same(b->n_atoms, b->n_mols, b->flags, key, st)) {
+        if (h->graphs[i].same(kA, kB, b->flags, key, st)) {
             h->last_stream = st;
             HIP_TRY(hipGraphLaunch(h->graphs[i].exec, st));
+            ++h->n_replays;
             return NNP_OK;
         }
     nnp_status rc = run_forward<P>(h, b, x, E, F, nullptr);
@@ -490,10 +666,10 @@ nnp_status run_forward_graph(nnp_handle* h, const nnp_batch* b, const typename P
         return NNP_OK;
     }
     GraphEntry ge;
-    ge.A = b->n_atoms;
-    ge.B = b->n_mols;
+    ge.A = kA;
+    ge.B = kB;
     ge.flags = b->flags;
-    for (int i = 0; i < 5; ++i) ge.ptr[i] = key[i];
+    for (int i = 0; i < 6; ++i) ge.ptr[i] = key[i];
     ge.stream = st;
     e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
@@ -503,6 +679,7 @@ nnp_status run_forward_graph(nnp_handle* h, const nnp_batch* b, const typename P
         h->graphs.erase(h->graphs.begin());
     }
     h->graphs.push_back(ge);
+    ++h->n_captures;
     return NNP_OK;
 }
 
@@ -553,6 +730,8 @@ nnp_status run_backward(nnp_handle* h, const nnp_batch* bin, const typename P::T
     typedef typename P::T T;
     nnp_status rc = alloc_train<P>(h);
     if (rc) return rc;
+    if (bin->flags & NNP_FLAG_DEVICE_COUNTS)
+        return fail(NNP_E_UNSUPPORTED, "the training backward takes host counts");
     nnp_batch bb = *bin;   // the internal evaluations overwrite their outputs, eagerly
     bb.flags = 0;
     const nnp_batch* b = &bb;
@@ -634,7 +813,9 @@ const char* knob_name(int k) {
          : k == NNP_KNOB_TAIL_TILE ? "tail_tile"
          : k == NNP_KNOB_GEMM_WAVES ? "gemm_waves"
          : k == NNP_KNOB_ATOM_CHUNK ? "atom_chunk"
-         : k == NNP_KNOB_L1_PATH ? "l1_path" : "force_sum";
+         : k == NNP_KNOB_L1_PATH ? "l1_path"
+         : k == NNP_KNOB_FORCE_SUM ? "force_sum"
+         : k == NNP_KNOB_FORCE_PATH ? "force_path" : "pipeline";
 }
 
 std::string tune_key(const nnp_handle* h) {
@@ -732,6 +913,10 @@ nnp_status autotune(nnp_handle* h, const nnp_batch* b, const typename P::T* x, i
             if (l1_regs_supported(h)) cand = {1, 2};
         } else if (k == NNP_KNOB_FORCE_SUM) {
             // reproducibility is the caller's choice: never tuned
+        } else if (k == NNP_KNOB_FORCE_PATH) {
+            cand = {1, 2};
+        } else if (k == NNP_KNOB_PIPELINE) {
+            if (h->max_mols >= 2) cand = {1, 2};
         } else {
             for (int c : {32, 64, 128, 256})
                 if (c < h->max_apm) cand.push_back(c);
@@ -746,6 +931,7 @@ nnp_status autotune(nnp_handle* h, const nnp_batch* b, const typename P::T* x, i
         for (int32_t v : cand) {
             h->knob[k] = v;
             apply_knobs(h);
+            if ((rc = ensure_pipeline(h))) break;
             double us = 0;
             rc = time_eval<P>(h, b, x, E, F, reps, us);
             if (rc) break;
@@ -911,6 +1097,7 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     sh.H1 = pad_to(wi[1], 64);
     sh.H2 = pad_to(wi[2], 64);
     sh.H3 = pad_to(wi[3], 64);
+    sh.h3_used = wi[3];
     sh.row_tile = (p->max_atoms <= 256 || p->precision == NNP_PREC_FP64) ? 16 : 128;
     sh.Rcap = pad_to(p->max_atoms + S * (sh.row_tile - 1), sh.row_tile);
     sh.cap_nbr = std::max(1, std::min(h->max_apm - 1, kMaxNeighbours));
@@ -957,6 +1144,7 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
             if (rc == NNP_OK) rc = alloc_work<PrecBF16>(h, h->k16);
         }
     }
+    if (rc == NNP_OK) rc = ensure_pipeline(h);
     if (rc == NNP_OK && (p->create_flags & NNP_CREATE_TRAINING))
         rc = p->precision == NNP_PREC_FP64 ? alloc_train<PrecF64>(h) : alloc_train<PrecF32>(h);
     if (rc != NNP_OK) {
@@ -980,6 +1168,9 @@ void nnp_destroy(nnp_handle* h) {
     }
     for (auto e : h->free_events) (void)hipEventDestroy(e);
     for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto e : h->pev)
+        if (e) (void)hipEventDestroy(e);
+    if (h->st2) (void)hipStreamDestroy(h->st2);
     delete h;
 }
 
@@ -1017,6 +1208,7 @@ nnp_status nnp_energy_forces_f64(nnp_handle* h, const nnp_batch* b, const double
 nnp_status nnp_aev(nnp_handle* h, const nnp_batch* b, const void* coords, void* out_aev) {
     nnp_status rc = check_batch(h, b);
     if (rc) return rc;
+    if (b->flags & NNP_FLAG_DEVICE_COUNTS) return fail(NNP_E_UNSUPPORTED, "nnp_aev takes host counts");
     if (!out_aev || (b->n_atoms > 0 && !coords)) return fail(NNP_E_INVALID, "null coords or out_aev");
     DeviceGuard dg(h->device);
     if (!dg.ok) return fail(NNP_E_DEVICE, "hipSetDevice failed");
@@ -1097,6 +1289,14 @@ nnp_status nnp_set_params(nnp_handle* h, const void* params, int32_t type, void*
 }
 
 int64_t nnp_num_params(const nnp_handle* h) { return h ? h->n_params : -1; }
+
+nnp_status nnp_graph_stats(const nnp_handle* h, int64_t* captures, int64_t* replays, int32_t* cached) {
+    if (!h) return fail(NNP_E_INVALID, "null handle");
+    if (captures) *captures = h->n_captures;
+    if (replays) *replays = h->n_replays;
+    if (cached) *cached = (int32_t)h->graphs.size();
+    return NNP_OK;
+}
 
 int32_t nnp_aev_dim(const nnp_handle* h) { return h ? h->D : -1; }
 
@@ -1188,6 +1388,8 @@ nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value) {
         ok = ok || value == 1 || value == 2;
     } else if (knob == NNP_KNOB_FORCE_SUM) {
         ok = ok || value == 1 || value == 2;
+    } else if (knob == NNP_KNOB_FORCE_PATH || knob == NNP_KNOB_PIPELINE) {
+        ok = ok || value == 1 || value == 2;
     } else {
         ok = ok || (value >= 16 && value <= kMaxAtomsPerMol);
     }
@@ -1196,7 +1398,7 @@ nnp_status nnp_set_knob(nnp_handle* h, int32_t knob, int32_t value) {
     if (!h->graphs.empty()) (void)hipDeviceSynchronize();
     h->knob[knob] = value;
     apply_knobs(h);
-    return NNP_OK;
+    return ensure_pipeline(h);
 }
 
 nnp_status nnp_get_knob(nnp_handle* h, int32_t knob, int32_t* value) {
@@ -1210,6 +1412,7 @@ nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, i
                         const char* cache_path, char* report, int32_t report_cap) {
     nnp_status rc = check_batch(h, b);
     if (rc) return rc;
+    if (b->flags & NNP_FLAG_DEVICE_COUNTS) return fail(NNP_E_UNSUPPORTED, "the autotuner takes host counts");
     if (reps < 1 || reps > 1000) return fail(NNP_E_INVALID, "reps must be in 1..1000");
     if (b->n_atoms > 0 && !coords) return fail(NNP_E_INVALID, "null coords");
     DeviceGuard dg(h->device);
@@ -1223,6 +1426,7 @@ nnp_status nnp_autotune(nnp_handle* h, const nnp_batch* b, const void* coords, i
         for (int k = 0; k < NNP_N_KNOBS; ++k)
             if (k != NNP_KNOB_FORCE_SUM) h->knob[k] = cached[k];
         apply_knobs(h);
+        if ((rc = ensure_pipeline(h))) return rc;
     } else {
         if (!h->graphs.empty()) (void)hipDeviceSynchronize();
         if (h->precision == NNP_PREC_FP64)

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libnnp_hip.so")
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 FLAG_GRAPH = 1
 FLAG_ACCUMULATE = 2
+FLAG_DEVICE_COUNTS = 4
 CREATE_TRAINING = 1
 #: atomic numbers of the ANI-2x elements in index order H, C, N, O, F, S, Cl
 ANI2X_Z = (1, 6, 7, 8, 9, 16, 17)
@@ -52,7 +53,8 @@ class ModelParams(C.Structure):
 
 class Batch(C.Structure):
     _fields_ = [("n_mols", C.c_int32), ("n_atoms", C.c_int32), ("mol_offsets", C.c_void_p),
-                ("species", C.c_void_p), ("stream", C.c_void_p), ("flags", C.c_uint32)]
+                ("species", C.c_void_p), ("stream", C.c_void_p), ("flags", C.c_uint32),
+                ("counts", C.c_void_p)]
 
 
 _lib = None
@@ -60,7 +62,7 @@ _lib = None
 #: every symbol include/nnp.h declares
 EXPORTS = ("nnp_create", "nnp_destroy", "nnp_energy_forces", "nnp_energy_forces_f64", "nnp_aev",
            "nnp_energy_forces_backward", "nnp_set_weights", "nnp_set_params", "nnp_num_params",
-           "nnp_aev_dim",
+           "nnp_graph_stats", "nnp_aev_dim",
            "nnp_get_device_status", "nnp_set_timing", "nnp_set_timing_only", "nnp_kernel_times",
            "nnp_last_error",
            "nnp_set_knob", "nnp_get_knob", "nnp_autotune",
@@ -69,10 +71,11 @@ EXPORTS = ("nnp_create", "nnp_destroy", "nnp_energy_forces", "nnp_energy_forces_
 
 #: tunable knobs (include/nnp.h)
 (KNOB_MLP_PATH, KNOB_GEMM_STAGES, KNOB_CELL_MIN, KNOB_TAIL_TILE, KNOB_GEMM_WAVES, KNOB_ATOM_CHUNK,
- KNOB_L1_PATH, KNOB_FORCE_SUM) = range(8)
+ KNOB_L1_PATH, KNOB_FORCE_SUM, KNOB_FORCE_PATH, KNOB_PIPELINE) = range(10)
 KNOBS = {"mlp_path": KNOB_MLP_PATH, "gemm_stages": KNOB_GEMM_STAGES, "cell_min": KNOB_CELL_MIN,
          "tail_tile": KNOB_TAIL_TILE, "gemm_waves": KNOB_GEMM_WAVES, "atom_chunk": KNOB_ATOM_CHUNK,
-         "l1_path": KNOB_L1_PATH, "force_sum": KNOB_FORCE_SUM}
+         "l1_path": KNOB_L1_PATH, "force_sum": KNOB_FORCE_SUM, "force_path": KNOB_FORCE_PATH,
+         "pipeline": KNOB_PIPELINE}
 
 
 def load_library(path: str = LIB_PATH):
@@ -103,6 +106,8 @@ def load_library(path: str = LIB_PATH):
     lib.nnp_set_params.restype = i32
     lib.nnp_num_params.argtypes = [vp]
     lib.nnp_num_params.restype = i64
+    lib.nnp_graph_stats.argtypes = [vp, P(i64), P(i64), P(i32)]
+    lib.nnp_graph_stats.restype = i32
     lib.nnp_aev_dim.argtypes = [vp]
     lib.nnp_aev_dim.restype = i32
     lib.nnp_get_device_status.argtypes = [vp, P(i32)]
@@ -235,12 +240,17 @@ class NNP:
 
     # -- API ---------------------------------------------------------------
     def energy_forces(self, coords, species, mol_offsets, forces: bool = True, out=None,
-                      graph: bool = False, stream=None, accumulate: bool = False):
+                      graph: bool = False, stream=None, accumulate: bool = False, counts=None,
+                      bounds=None):
         """Energies [B] (float64) and forces [A, 3] of a ragged batch.
 
         graph=True replays a captured HIP graph while shapes, tensors and the
         stream stay the same (needs a non-default stream).  accumulate=True
-        adds the results to the tensors given in `out`."""
+        adds the results to the tensors given in `out`.  counts: an int32
+        CUDA tensor {n_mols, n_atoms} read on the device, with bounds =
+        (max molecules, max atoms) of the call (default: the tensors'
+        lengths); with graph=True every batch within the same rounded bounds
+        replays one graph."""
         import torch
         self._need(coords, self.coord_dtype, "coords")
         self._need(species, torch.int32, "species")
@@ -248,7 +258,14 @@ class NNP:
         if accumulate and out is None:
             raise ValueError("accumulate needs the output tensors in `out`")
         flags = (FLAG_GRAPH if graph else 0) | (FLAG_ACCUMULATE if accumulate else 0)
+        if counts is not None:
+            self._need(counts, torch.int32, "counts")
+            flags |= FLAG_DEVICE_COUNTS
         b = self._batch(species, mol_offsets, stream=stream, flags=flags)
+        if counts is not None:
+            b.counts = counts.data_ptr()
+            if bounds is not None:
+                b.n_mols, b.n_atoms = int(bounds[0]), int(bounds[1])
         if out is None:
             E = torch.empty(b.n_mols, dtype=torch.float64, device=coords.device)
             F = torch.empty_like(coords) if forces else None
@@ -327,6 +344,12 @@ class NNP:
         else:
             self.set_weights(p.to("cpu", dtype=torch.float64).numpy())
         self._synced = (params, params._version)
+
+    def graph_stats(self) -> dict:
+        """Captures and replays of evaluation graphs, and graphs cached."""
+        c, r, n = C.c_int64(0), C.c_int64(0), C.c_int32(0)
+        _check(self.lib.nnp_graph_stats(self.h, C.byref(c), C.byref(r), C.byref(n)))
+        return {"captures": int(c.value), "replays": int(r.value), "cached": int(n.value)}
 
     @property
     def num_params(self) -> int:

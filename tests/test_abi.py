@@ -163,7 +163,8 @@ def test_knob_ids_match_header():
     assert ids == {"MLP_PATH": nnp.KNOB_MLP_PATH, "GEMM_STAGES": nnp.KNOB_GEMM_STAGES,
                    "CELL_MIN": nnp.KNOB_CELL_MIN, "TAIL_TILE": nnp.KNOB_TAIL_TILE,
                    "GEMM_WAVES": nnp.KNOB_GEMM_WAVES, "ATOM_CHUNK": nnp.KNOB_ATOM_CHUNK,
-                   "L1_PATH": nnp.KNOB_L1_PATH, "FORCE_SUM": nnp.KNOB_FORCE_SUM}
+                   "L1_PATH": nnp.KNOB_L1_PATH, "FORCE_SUM": nnp.KNOB_FORCE_SUM,
+                   "FORCE_PATH": nnp.KNOB_FORCE_PATH, "PIPELINE": nnp.KNOB_PIPELINE}
     assert set(nnp.KNOBS.values()) == set(ids.values())
 
 

@@ -22,6 +22,9 @@ VARIANTS += [dict(mlp_path=1, gemm_stages=2, cell_min=128, tail_tile=t) for t in
 VARIANTS += [dict(mlp_path=1, gemm_stages=g, cell_min=128, tail_tile=1, gemm_waves=8) for g in (2, 3)]
 VARIANTS += [dict(mlp_path=2, gemm_stages=2, cell_min=c, tail_tile=1, gemm_waves=4, atom_chunk=a)
              for a, c in ((16, 32), (8, 1024), (4, 128))]
+# the force kernel with the dE/dAEV row staged in LDS (global reads by default)
+VARIANTS += [dict(mlp_path=1, gemm_stages=2, cell_min=c, tail_tile=1, atom_chunk=a, force_path=1)
+             for a, c in ((16, 32), (4, 1024))]
 
 
 def _batch():

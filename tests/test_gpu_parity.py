@@ -30,19 +30,26 @@ def _oracle(orc, hp, w, M, prec, batch):
     return orc.energy_forces(hp, wo, M, batch.species, xo, batch.mol_offsets)
 
 
-def test_aev_fp64_and_fp32(orc, hp):
+@pytest.mark.parametrize("which", ["cfg1", "ragged"])
+def test_aev_fp64_and_fp32(orc, hp, which):
+    """AEV rows against the oracle, element by element: the 24-atom
+    molecule, and a ragged batch (one-atom and empty molecules, 7 elements,
+    a molecule listed through cutoff cells)."""
     torch = torch_cuda()
-    b = synth.config_batch(1)
+    b = synth.config_batch(1) if which == "cfg1" else synth.random_batch(39, [1, 0, 17, 150, 9, 64])
     w = synth.xavier_weights(1, hp["widths"])
     for prec, tol in (("fp64", 1e-12), ("fp32", 2e-6)):
         h = make_handle(hp, w, 1, prec, b)
         dt = torch.float64 if prec == "fp64" else torch.float32
         x, sp, off = to_device(torch, b, dt)
         G = h.aev(x, sp, off).double().cpu().numpy()
+        G2 = h.aev(x, sp, off).double().cpu().numpy()
+        assert np.array_equal(G, G2)          # every slot summed in a fixed order
         xo, _ = oracle_inputs(b, w, prec)
-        Go = orc.aev(hp, b.species, xo)
+        Go = np.concatenate([orc.aev(hp, b.species[a:c], xo[a:c])
+                             for a, c in zip(b.mol_offsets[:-1], b.mol_offsets[1:]) if c > a])
         scale = np.abs(Go).max()
-        print(prec, "max |dAEV| / max|AEV| =", np.abs(G - Go).max() / scale)
+        print(prec, which, "max |dAEV| / max|AEV| =", np.abs(G - Go).max() / scale)
         np.testing.assert_allclose(G, Go, rtol=tol, atol=tol * scale)
 
 
