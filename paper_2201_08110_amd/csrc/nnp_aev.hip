@@ -1006,11 +1006,11 @@ __device__ inline void pair_of(const AtomLists<T>& al, int NB, int S, int p, int
 // G[row_of_atom[a]] in the GEMM operand type, optionally also to aev_out[a]
 // (atom order, unpadded).  Every AEV slot is owned by one lane: radial slot
 // (s, k) by lane (group s % 4, shift k) summing over the neighbours of
-// element s; angular slot q of block b by the lane pair (q, q + 32), which
-// split block b's pair range by parity and combine with one shuffle.  Pair
-// factors (NA distance terms, NZ angle terms) are computed once per pair,
-// 64 pairs at a time, into LDS.  The row is assembled in LDS and leaves in
-// 16-byte stores.
+// element s; angular slot q of a block by lane q of one half-wave (the
+// blocks meeting a 64-pair batch are dealt to the two halves in turn, and a
+// block's pairs are contiguous).  Pair factors (NA distance
+// terms, NZ angle terms) are computed once per pair, 64 pairs at a time,
+// into LDS.  The row is assembled in LDS and leaves in 16-byte stores.
 template <typename P, int NZ>
 __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
                                              int chunk, int cap, const int32_t* __restrict__ mol_off,
@@ -1124,35 +1124,41 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
                 }
             }
             wave_sync();
-            // blocks meeting this batch (one ballot over the block list, then
-            // only those); lanes q and q + 32 take alternate pairs
-            const unsigned long long live =
-                __ballot(lane < NB && al.bst[lane] < al.bst[lane + 1] && al.bst[lane] < p0 + nbat &&
-                         al.bst[lane + 1] > p0);
-            for (unsigned long long mset = live; mset; mset &= mset - 1) {
-                const int bl = __builtin_ctzll(mset);
-                const int s0 = max(al.bst[bl], p0), e0 = min(al.bst[bl + 1], p0 + nbat);
-                // two accumulators, four pairs' factors in flight
+            // blocks meeting this batch, taken two at a time: the first by
+            // lanes 0..31, the second by lanes 32..63, each half summing its
+            // block's pairs in order (four pairs' factors in flight); block
+            // bounds travel lane to lane through readlane
+            const int blo = lane < NB ? al.bst[lane] : 0, bhi = lane < NB ? al.bst[lane + 1] : 0;
+            unsigned long long mset = __ballot(lane < NB && blo < bhi && blo < p0 + nbat && bhi > p0);
+            while (mset) {
+                const int bA = __builtin_ctzll(mset);
+                mset &= mset - 1;
+                const int bB = mset ? __builtin_ctzll(mset) : bA;
+                const bool two = mset != 0;
+                mset &= mset - 1;
+                const int bl = h ? bB : bA;
+                const int lo = h ? __builtin_amdgcn_readlane(blo, bB) : __builtin_amdgcn_readlane(blo, bA);
+                const int hi = h ? __builtin_amdgcn_readlane(bhi, bB) : __builtin_amdgcn_readlane(bhi, bA);
+                const int s0 = max(lo, p0) - p0;
+                const int e0 = (h && !two) ? s0 : min(hi, p0 + nbat) - p0;
                 T acc = T(0), acc1 = T(0);
-                int p = s0 + h;
-                for (; p + 6 < e0; p += 8) {
+                int p = s0;
+                for (; p + 4 <= e0; p += 4) {
                     T fa[4], fz[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const T* f = pf + PF * (p + 2 * u - p0);
+                        const T* f = pf + PF * (p + u);
                         fa[u] = f[qa];
                         fz[u] = f[NA + qz];
                     }
                     acc += fa[0] * fz[0] + fa[2] * fz[2];
                     acc1 += fa[1] * fz[1] + fa[3] * fz[3];
                 }
-                for (; p < e0; p += 2) {
-                    const T* f = pf + PF * (p - p0);
+                for (; p < e0; ++p) {
+                    const T* f = pf + PF * p;
                     acc += f[qa] * f[NA + qz];
                 }
-                acc += acc1;
-                acc += __shfl_xor(acc, 32);
-                if (h == 0) row[RL + kNAZ * bl + q] += acc;
+                if (s0 < e0) row[RL + kNAZ * bl + q] += acc + acc1;
             }
             wave_sync();
         }

@@ -89,23 +89,27 @@ enum { EPI_CELU = 0, EPI_L3F = 1, EPI_DSIG = 2, EPI_ACC = 3, EPI_RAW = 4, EPI_RE
 // CELU and its derivative, branch-free (the exponential is taken of min(z, 0)
 // and always finite); ial = 1 / alpha.  CELU'(z) is recovered from a stored
 // h = CELU(z): h >= 0 <=> z >= 0, and exp(z / alpha) = 1 + h / alpha.
+// (float: the scaled argument is clamped, min(z c, 0) = min(z, 0) c for c > 0,
+// so the minimum takes a product and needs no NaN canonicalisation of z)
 __device__ inline float celu(float z, float al, float ial) {
-    const float e = __builtin_amdgcn_exp2f(fminf(z, 0.f) * (ial * 1.44269504088896341f));
-    return z >= 0.f ? z : al * (e - 1.f);
+    const float e = __builtin_amdgcn_exp2f(fminf(z * (ial * 1.44269504088896341f), 0.f));
+    return z >= 0.f ? z : __builtin_fmaf(al, e, -al);
 }
 __device__ inline double celu(double z, double al, double ial) {
     const double e = expm1(fmin(z, 0.0) * ial);
     return z >= 0.0 ? z : al * e;
 }
 __device__ inline float dcelu_z(float z, float ial) {
-    const float e = __builtin_amdgcn_exp2f(fminf(z, 0.f) * (ial * 1.44269504088896341f));
-    return z >= 0.f ? 1.f : e;
+    // exp2 of the clamped argument is exactly 1 for z >= 0
+    return __builtin_amdgcn_exp2f(fminf(z * (ial * 1.44269504088896341f), 0.f));
 }
 __device__ inline double dcelu_z(double z, double ial) {
     const double e = exp(fmin(z, 0.0) * ial);
     return z >= 0.0 ? 1.0 : e;
 }
-template <typename TA> __device__ inline TA dcelu_h(TA h, TA ial) { return h >= TA(0) ? TA(1) : TA(1) + h * ial; }
+// (1 + h / alpha >= 1 exactly when h >= 0, so the minimum selects the branch)
+__device__ inline float dcelu_h(float h, float ial) { return fminf(__builtin_fmaf(h, ial, 1.f), 1.f); }
+__device__ inline double dcelu_h(double h, double ial) { return h >= 0.0 ? 1.0 : 1.0 + h * ial; }
 
 template <typename P> struct GemmArgs {
     typedef typename P::TS TS;
@@ -787,28 +791,37 @@ template <typename TS> struct Sliced {
     }
 };
 
+// element type of the MFMA accumulators for operand type TS
+template <typename TS> using AccE = typename std::conditional<std::is_same<TS, double>::value, double, float>::type;
+
 // acc = A rows m0 + [0, 16 FM) (LDS, sliced, BM rows, K columns) x B^T, B
 // n-tiles nt0 + [0, FN) of a matrix in fragment order (one contiguous 64-lane
-// load per fragment).  The B fragments of k-step t+2 are requested before the
+// load per fragment).  The B fragments of k-step t+PD are requested before the
 // MFMAs of step t; the empty asm with a memory clobber keeps the compiler from
-// sinking those loads next to their use, so two k-steps of MFMAs (and the
+// sinking those loads next to their use, so PD k-steps of MFMAs (and the
 // other waves) cover the L2 latency.
 // K: the reduction length used; KS: the K the fragment-ordered matrix is
-// stored with (its k-steps per n-tile)
+// stored with (its k-steps per n-tile); bias, if given, points at the bias of
+// this lane's first column and starts the accumulators there.
 template <typename TS, int BM, int FM, int FN, int K, int KS = K>
 __device__ inline void tail_product(typename MF<TS>::Acc (&acc)[FM][FN], const TS* As, int m0,
-                                    const TS* __restrict__ Bf, int nt0, int lane) {
+                                    const TS* __restrict__ Bf, int nt0, int lane,
+                                    const AccE<TS>* bias = nullptr) {
     typedef MF<TS> mf;
     typedef Sliced<TS> L;
     typedef typename mf::Frag Frag;
-    constexpr int NS = K / mf::KM, NSS = KS / mf::KM, PD = 2;
+    // prefetch distance in k-steps: a bf16 fragment covers 32 of K, an
+    // FP32 / FP64 one only 4, so those look 8 steps ahead
+    constexpr int NS = K / mf::KM, NSS = KS / mf::KM, PD = mf::KM == 4 ? 8 : 2;
     static_assert(K % mf::KM == 0 && K <= KS, "reduction length");
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+        for (int r = 0; r < 4; ++r) {
+            const AccE<TS> b0 = bias ? bias[j * 16 + r * mf::kColStride] : AccE<TS>(0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+            for (int i = 0; i < FM; ++i) acc[i][j][r] = b0;
+        }
     const TS* Bl = Bf + (size_t)nt0 * NSS * 64 * mf::KL + lane * mf::KL;
     Frag bq[PD + 1][FN];
 #pragma unroll
@@ -952,19 +965,15 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
         constexpr int FN = H2 / 64;
         Acc acc[FM][FN];
         const int n0 = wn * (H2 / 4);
-        tail_product<TS, BM, FM, FN, H1>(acc, Us, m0, g.W2f + sz * H2 * H1, n0 / 16, lane);
-        const TA* b2 = sb2;
+        tail_product<TS, BM, FM, FN, H1>(acc, Us, m0, g.W2f + sz * H2 * H1, n0 / 16, lane, sb2 + n0 + cl);
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int c = n0 + j * 16 + cl;
-            TA bb[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) bb[q] = b2[c + q * ST];
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
                 TA v[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = celu((TA)acc[i][j][q] + bb[q], g.alpha, g.inv_alpha);
+                for (int q = 0; q < 4; ++q) v[q] = celu((TA)acc[i][j][q], g.alpha, g.inv_alpha);
                 LdsQuad<TS, ST>::st(Hs, BM, m0 + i * 16 + rl, c, v);
             }
         }
@@ -980,8 +989,7 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
             constexpr int FN = decltype(fn_c)::value;
             Acc acc[FM][FN];
             const int n0 = 16 * f0;
-            tail_product<TS, BM, FM, FN, H2>(acc, Hs, m0, g.W3f + sz * H3 * H2, f0, lane);
-            const TA* b3 = sb3;
+            tail_product<TS, BM, FM, FN, H2>(acc, Hs, m0, g.W3f + sz * H3 * H2, f0, lane, sb3 + n0 + cl);
             const TA* w4 = sw4;
             TA part[FM];
 #pragma unroll
@@ -989,20 +997,20 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
                 const int c = n0 + j * 16 + cl;
-                TA bb[4], ww[4];
+                TA ww[4], wg[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    bb[q] = b3[c + q * ST];
                     ww[q] = w4[c + q * ST];
+                    wg[q] = ww[q] * g.gscale;
                 }
 #pragma unroll
                 for (int i = 0; i < FM; ++i) {
                     TA v[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const TA zz = (TA)acc[i][j][q] + bb[q];
+                        const TA zz = (TA)acc[i][j][q];
                         part[i] += ww[q] * celu(zz, g.alpha, g.inv_alpha);
-                        v[q] = dcelu_z(zz, g.inv_alpha) * ww[q] * g.gscale;
+                        v[q] = dcelu_z(zz, g.inv_alpha) * wg[q];
                     }
                     LdsQuad<TS, ST>::st(Us, BM, m0 + i * 16 + rl, c, v);
                 }
