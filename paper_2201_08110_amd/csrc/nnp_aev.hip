@@ -868,6 +868,44 @@ __device__ inline void load_neighbours(const AevConst<T>& c, const T* __restrict
     }
 }
 
+// The record's ninth word (padding otherwise) carries its tag: neighbour
+// index j << 8 | element of j, so the featuriser and force kernels keep no
+// per-neighbour index arrays beside the records.
+__device__ inline void put_tag(float* e, int v) { e[8] = __int_as_float(v); }
+__device__ inline void put_tag(double* e, int v) { e[8] = (double)v; }
+__device__ inline int tag_of(const float* e) { return __float_as_int(e[8]); }
+__device__ inline int tag_of(const double* e) { return (int)e[8]; }
+static_assert(kNbStride >= 9, "record tag slot");
+
+// load_neighbours with the tag in the record instead of nsp / nid
+template <typename T>
+__device__ inline void load_records(const AevConst<T>& c, const T* __restrict__ sx,
+                                    const int* __restrict__ ssp,
+                                    const uint16_t* __restrict__ nb_list, int nang, int nall,
+                                    int il, T* __restrict__ nb) {
+    const T xi0 = sx[3 * il], xi1 = sx[3 * il + 1], xi2 = sx[3 * il + 2];
+    for (int t = lane_id(); t < nall; t += 64) {
+        const int j = nb_list[t];
+        const T d0 = sx[3 * j] - xi0, d1 = sx[3 * j + 1] - xi1, d2 = sx[3 * j + 2] - xi2;
+        const T r = m_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        T* e = nb + kNbStride * t;
+        e[0] = d0;
+        e[1] = d1;
+        e[2] = d2;
+        e[3] = r;
+        e[4] = T(0.5) * m_cos(c.pi_rcr * r) + T(0.5);
+        e[5] = -T(0.5) * c.pi_rcr * m_sin(c.pi_rcr * r);
+        if (t < nang) {
+            e[6] = T(0.5) * m_cos(c.pi_rca * r) + T(0.5);
+            e[7] = -T(0.5) * c.pi_rca * m_sin(c.pi_rca * r);
+        } else {
+            e[6] = T(0);
+            e[7] = T(0);
+        }
+        put_tag(e, (j << 8) | ssp[j]);
+    }
+}
+
 // 16-byte row pieces: zero four values of an LDS row; store 16 bytes of
 // output elements converted from the featuriser type
 __device__ inline void zero4(float* p) { *(float4*)p = make_float4(0.f, 0.f, 0.f, 0.f); }
@@ -928,16 +966,15 @@ __device__ inline void block_elements(int L, int S, int& a, int& b) {
     b = aa + (L - base);
 }
 
-// Fill aoff / roff / bst for one atom (wave-wide); nsp[t] = element of
+// Fill aoff / roff / bst for one atom (wave-wide); sp_of(t) = element of
 // neighbour t.  Returns the number of angular pairs.
-template <typename T>
-__device__ inline int atom_lists(const AtomLists<T>& al, const int* __restrict__ nsp, int nang,
-                                 int nall, int S) {
+template <typename T, typename SpOf>
+__device__ inline int atom_lists(const AtomLists<T>& al, SpOf sp_of, int nang, int nall, int S) {
     const int lane = lane_id();
     int ca = 0, cr = 0;   // lane s (< S): neighbours of element s in each run
     for (int t0 = 0; t0 < nall; t0 += 64) {
         const int t = t0 + lane;
-        const int sp = t < nall ? nsp[t] : -1;
+        const int sp = t < nall ? sp_of(t) : -1;
         for (int s = 0; s < S; ++s) {
             const int na = __popcll(__ballot(sp == s && t < nang));
             const int nr = __popcll(__ballot(sp == s && t >= nang));
@@ -1039,8 +1076,6 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
     ChunkStage<T> cs;
     cs.take(lb, max_apm, cap);
     T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
-    int* nsp = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
-    int* nid = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
     T* row = lb.take<T>((size_t)nw * c.Dp) + (size_t)wave * c.Dp;
     T* pf = lb.take<T>((size_t)nw * 64 * PF) + (size_t)wave * 64 * PF;
     AtomLists<T> al;
@@ -1056,11 +1091,11 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
         const int il = i0 + ic;
         const int cnt = cs.ccnt[ic];
         const int nang = cnt & 0xffff, nall = cnt >> 16;
-        load_neighbours(c, cs.sx, cs.ssp, cs.clst + (size_t)ic * cap, nang, nall, il, nb, nsp, nid);
+        load_records(c, cs.sx, cs.ssp, cs.clst + (size_t)ic * cap, nang, nall, il, nb);
         // zero the angular blocks and the padding (radial slots are all written)
         for (int e = RL + 4 * lane; e < c.Dp; e += 256) zero4(row + e);
         wave_sync();
-        const int npair = atom_lists(al, nsp, nang, nall, S);
+        const int npair = atom_lists(al, [&](int t) { return tag_of(nb + kNbStride * t) & 0xff; }, nang, nall, S);
         wave_sync();
 
         // ---- radial: lane (group g, shift k) owns slots (s, k), s = g mod 4
@@ -1180,8 +1215,8 @@ template <typename T>
 static size_t aev_lds(int max_apm, int cap, int Dp, int NZ, int nw) {
     const int PF = kNAZ / NZ + NZ;
     return ChunkStage<T>::bytes(max_apm, cap) + lds_bytes<T>((size_t)nw * cap * kNbStride) +
-           2 * lds_bytes<int>((size_t)nw * cap) + lds_bytes<T>((size_t)nw * Dp) +
-           lds_bytes<T>((size_t)nw * 64 * PF) + (size_t)nw * AtomLists<T>::bytes();
+           lds_bytes<T>((size_t)nw * Dp) + lds_bytes<T>((size_t)nw * 64 * PF) +
+           (size_t)nw * AtomLists<T>::bytes();
 }
 
 template <typename P>
@@ -1445,7 +1480,7 @@ template <typename T> struct ForceAcc<T, true> {
 };
 
 template <typename P, int NZ, bool FIXED, bool GD>
-__global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A, int max_apm,
+__global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_forces(AevConst<typename P::T> c, int A, int max_apm,
                                                 int chunk, int cap, const int32_t* __restrict__ mol_off,
                                                 const int32_t* __restrict__ species,
                                                 const typename P::T* __restrict__ x,
@@ -1476,8 +1511,6 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
     cs.take(lb, max_apm, cap);
     V* sF = lb.take<V>(3 * (size_t)max_apm);
     T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
-    int* nsp = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
-    int* nid = lb.take<int>((size_t)nw * cap) + (size_t)wave * cap;
     // the atom's dE/dAEV row: staged in LDS (blocks kBlkPad apart), or read
     // straight from global memory (GD: L1/L2 hits, the LDS left to the
     // force sums)
@@ -1517,7 +1550,7 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
                 }
             }
         }
-        load_neighbours(c, cs.sx, cs.ssp, cs.clst + (size_t)ic * cap, nang, nall, il, nb, nsp, nid);
+        load_records(c, cs.sx, cs.ssp, cs.clst + (size_t)ic * cap, nang, nall, il, nb);
         wave_sync();
         T fi0 = 0, fi1 = 0, fi2 = 0;   // force on the central atom, per lane
         // radial: lane per (neighbour, group of 4 shifts)
@@ -1528,14 +1561,15 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
             if (act) {
                 const T* e = nb + kNbStride * t;
                 const T r = e[3], fc = e[4], dfc = e[5];
+                const int st = tag_of(e) & 0xff;
                 T gg[4];
                 if constexpr (GD) {
                     TA ga[4];
-                    ld4(gsrc + kNR * nsp[t] + 4 * q, ga);
+                    ld4(gsrc + kNR * st + 4 * q, ga);
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) gg[kk] = (T)ga[kk];
                 } else {
-                    ld4(g + kNR * nsp[t] + 4 * q, gg);
+                    ld4(g + kNR * st + 4 * q, gg);
                 }
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
@@ -1551,7 +1585,7 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
                 const T* e = nb + kNbStride * t;
                 const T inv = m_rcp(e[3]);
                 const T u0 = e[0] * inv, u1 = e[1] * inv, u2 = e[2] * inv;
-                const int j = nid[t];
+                const int j = tag_of(e) >> 8;
                 // dE/dx_j = dEdr u, dE/dx_i = -dEdr u;  F = -dE/dx
                 Acc::add(&sF[3 * j + 0], -dEdr * u0);
                 Acc::add(&sF[3 * j + 1], -dEdr * u1);
@@ -1579,7 +1613,8 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
             const T fcj = ej[6], fck = ek[6], dfcj = ej[7], dfck = ek[7];
             const T fcc = fcj * fck;
             const T rm = T(0.5) * (rj + rk);
-            const int pb = RL + BS * pair_index(nsp[j], nsp[k], S);
+            const int tj = tag_of(ej), tk = tag_of(ek);
+            const int pb = RL + BS * pair_index(tj & 0xff, tk & 0xff, S);
             const T* gb = GD ? nullptr : g + pb;
             T fz[NZ], dfz[NZ];
 #pragma unroll
@@ -1627,7 +1662,7 @@ __global__ __launch_bounds__(256) void k_forces(AevConst<typename P::T> c, int A
             const T gk0 = Drk * uk0 + Dc * (uj0 - cs_ * uk0) * ik;
             const T gk1 = Drk * uk1 + Dc * (uj1 - cs_ * uk1) * ik;
             const T gk2 = Drk * uk2 + Dc * (uj2 - cs_ * uk2) * ik;
-            const int jj = nid[j], kk = nid[k];
+            const int jj = tj >> 8, kk = tk >> 8;
             Acc::add(&sF[3 * jj + 0], -gj0);
             Acc::add(&sF[3 * jj + 1], -gj1);
             Acc::add(&sF[3 * jj + 2], -gj2);
@@ -1659,7 +1694,7 @@ static size_t forces_lds(int max_apm, int cap, int S, int nw, bool fixed = false
     const int GL = kNR * S + kBlkPad * S * (S + 1) / 2;
     return ChunkStage<T>::bytes(max_apm, cap) +
            (fixed ? lds_bytes<unsigned long long>(3 * (size_t)max_apm) : lds_bytes<T>(3 * (size_t)max_apm)) +
-           lds_bytes<T>((size_t)nw * cap * kNbStride) + 2 * lds_bytes<int>((size_t)nw * cap) +
+           lds_bytes<T>((size_t)nw * cap * kNbStride) +
            (gd ? 0 : lds_bytes<T>((size_t)nw * GL));
 }
 
