@@ -906,30 +906,6 @@ __device__ inline void load_records(const AevConst<T>& c, const T* __restrict__ 
     }
 }
 
-// 16-byte row pieces: zero four values of an LDS row; store 16 bytes of
-// output elements converted from the featuriser type
-__device__ inline void zero4(float* p) { *(float4*)p = make_float4(0.f, 0.f, 0.f, 0.f); }
-__device__ inline void zero4(double* p) {
-    *(double2*)p = make_double2(0.0, 0.0);
-    *(double2*)(p + 2) = make_double2(0.0, 0.0);
-}
-template <typename TS> __device__ inline void store16(TS* out, const float* v);
-template <> __device__ inline void store16<float>(float* out, const float* v) {
-    *(float4*)out = *(const float4*)v;
-}
-template <> __device__ inline void store16<bf16_t>(bf16_t* out, const float* v) {
-    const float4 a = *(const float4*)v, b = *(const float4*)(v + 4);
-    uint4 q;
-    q.x = pack_bf16x2(a.x, a.y);
-    q.y = pack_bf16x2(a.z, a.w);
-    q.z = pack_bf16x2(b.x, b.y);
-    q.w = pack_bf16x2(b.z, b.w);
-    *(uint4*)out = q;
-}
-template <typename TS> __device__ inline void store16(TS* out, const double* v) {
-    *(double2*)out = *(const double2*)v;
-}
-
 // --------------------------------------------------------------------------
 // Per-atom structure of an element-sorted neighbour list.  The angular run
 // (r < rca) and the radial-only run are each sorted by element, so the
@@ -1047,7 +1023,9 @@ __device__ inline void pair_of(const AtomLists<T>& al, int NB, int S, int p, int
 // blocks meeting a 64-pair batch are dealt to the two halves in turn, and a
 // block's pairs are contiguous).  Pair factors (NA distance
 // terms, NZ angle terms) are computed once per pair, 64 pairs at a time,
-// into LDS.  The row is assembled in LDS and leaves in 16-byte stores.
+// into LDS.  Each slot is stored to the output row by its owner lane as soon
+// as it is complete: no row is assembled in LDS, which keeps the workgroup's
+// LDS small enough for more waves per CU.
 template <typename P, int NZ>
 __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
                                              int chunk, int cap, const int32_t* __restrict__ mol_off,
@@ -1076,7 +1054,6 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
     ChunkStage<T> cs;
     cs.take(lb, max_apm, cap);
     T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
-    T* row = lb.take<T>((size_t)nw * c.Dp) + (size_t)wave * c.Dp;
     T* pf = lb.take<T>((size_t)nw * 64 * PF) + (size_t)wave * 64 * PF;
     AtomLists<T> al;
     {
@@ -1092,11 +1069,17 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
         const int cnt = cs.ccnt[ic];
         const int nang = cnt & 0xffff, nall = cnt >> 16;
         load_records(c, cs.sx, cs.ssp, cs.clst + (size_t)ic * cap, nang, nall, il, nb);
-        // zero the angular blocks and the padding (radial slots are all written)
-        for (int e = RL + 4 * lane; e < c.Dp; e += 256) zero4(row + e);
         wave_sync();
         const int npair = atom_lists(al, [&](int t) { return tag_of(nb + kNbStride * t) & 0xff; }, nang, nall, S);
         wave_sync();
+        // every slot is stored once, straight from the lane that owns it
+        TS* grow = G + (size_t)cs.crow[ic] * c.Dp;
+        T* arow = aev_out ? aev_out + ((size_t)a0 + il) * c.D : nullptr;
+        auto put = [&](int e, T v) {
+            grow[e] = Store<TS>::st(v);
+            if (arow) arow[e] = v;
+        };
+        for (int e = c.D + lane; e < c.Dp; e += 64) grow[e] = Store<TS>::st(T(0));
 
         // ---- radial: lane (group g, shift k) owns slots (s, k), s = g mod 4
         {
@@ -1127,11 +1110,18 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
                         acc0 += m_exp(-c.eta_r * d * d) * nb[kNbStride * t + 4];
                     }
                 }
-                row[kNR * s + k] = c.radial_pref * (acc0 + acc1);
+                put(kNR * s + k, c.radial_pref * (acc0 + acc1));
             }
         }
 
-        // ---- angular, 64 pairs at a time
+        // ---- angular, 64 pairs at a time.  A block's sum is stored when its
+        // last pair is in; a block that runs on into the next batch leaves its
+        // partial sum in the lanes of half 0 (carry), which take that block
+        // first in the next batch.  Blocks without pairs are stored as zeros.
+        const int blo = lane < NB ? al.bst[lane] : 0, bhi = lane < NB ? al.bst[lane + 1] : 0;
+        const unsigned long long filled = __ballot(lane < NB && blo < bhi);
+        T carry = T(0);
+        int carry_blk = -1;
         for (int p0 = 0; p0 < npair; p0 += 64) {
             const int nbat = min(64, npair - p0);
             if (lane < nbat) {
@@ -1161,11 +1151,12 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
             wave_sync();
             // blocks meeting this batch, taken two at a time: the first by
             // lanes 0..31, the second by lanes 32..63, each half summing its
-            // block's pairs in order (four pairs' factors in flight); block
-            // bounds travel lane to lane through readlane
-            const int blo = lane < NB ? al.bst[lane] : 0, bhi = lane < NB ? al.bst[lane + 1] : 0;
-            unsigned long long mset = __ballot(lane < NB && blo < bhi && blo < p0 + nbat && bhi > p0);
-            while (mset) {
+            // block's pairs in order (four pairs' factors in flight)
+            const int pe_ = p0 + nbat;
+            const unsigned long long live = __ballot(lane < NB && blo < bhi && blo < pe_ && bhi > p0);
+            const unsigned long long goes_on = __ballot(lane < NB && blo < bhi && blo < pe_ && bhi > pe_);
+            T next_carry = T(0);
+            for (unsigned long long mset = live; mset;) {
                 const int bA = __builtin_ctzll(mset);
                 mset &= mset - 1;
                 const int bB = mset ? __builtin_ctzll(mset) : bA;
@@ -1175,7 +1166,7 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
                 const int lo = h ? __builtin_amdgcn_readlane(blo, bB) : __builtin_amdgcn_readlane(blo, bA);
                 const int hi = h ? __builtin_amdgcn_readlane(bhi, bB) : __builtin_amdgcn_readlane(bhi, bA);
                 const int s0 = max(lo, p0) - p0;
-                const int e0 = (h && !two) ? s0 : min(hi, p0 + nbat) - p0;
+                const int e0 = (h && !two) ? s0 : min(hi, pe_) - p0;
                 T acc = T(0), acc1 = T(0);
                 int p = s0;
                 for (; p + 4 <= e0; p += 4) {
@@ -1193,30 +1184,43 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
                     const T* f = pf + PF * p;
                     acc += f[qa] * f[NA + qz];
                 }
-                if (s0 < e0) row[RL + kNAZ * bl + q] += acc + acc1;
+                T v = acc + acc1;
+                if (bl == carry_blk) v += carry;
+                if (s0 < e0) {
+                    if (hi > pe_) next_carry = v;
+                    else put(RL + kNAZ * bl + q, v);
+                }
+            }
+            if (goes_on) {
+                // the continuing block is the batch's last; its half is the
+                // parity of its rank among the batch's blocks
+                const int cb = __builtin_ctzll(goes_on);
+                const int half = __popcll(live & ((1ull << cb) - 1)) & 1;
+                const T other = __shfl_xor(next_carry, 32);
+                carry = half ? other : next_carry;
+                carry_blk = cb;
+            } else {
+                carry_blk = -1;
             }
             wave_sync();
         }
-
-        // ---- write the row in 16-byte pieces
-        wave_sync();
-        const size_t grow = (size_t)cs.crow[ic];
-        constexpr int VE = 16 / (int)sizeof(TS);
-        for (int e = VE * lane; e < c.Dp; e += 64 * VE) store16<TS>(G + grow * c.Dp + e, row + e);
-        if (aev_out) {
-            const size_t ai = (size_t)a0 + il;
-            for (int e = lane; e < c.D; e += 64) aev_out[ai * c.D + e] = row[e];
+        for (unsigned long long zset = ~filled & (NB >= 64 ? ~0ull : ((1ull << NB) - 1)); zset;) {
+            const int zA = __builtin_ctzll(zset);
+            zset &= zset - 1;
+            const int zB = zset ? __builtin_ctzll(zset) : -1;
+            zset &= zset - 1;
+            const int zb = h ? zB : zA;
+            if (zb >= 0) put(RL + kNAZ * zb + q, T(0));
         }
-        wave_sync();
     }
 }
 
 template <typename T>
 static size_t aev_lds(int max_apm, int cap, int Dp, int NZ, int nw) {
     const int PF = kNAZ / NZ + NZ;
+    (void)Dp;
     return ChunkStage<T>::bytes(max_apm, cap) + lds_bytes<T>((size_t)nw * cap * kNbStride) +
-           lds_bytes<T>((size_t)nw * Dp) + lds_bytes<T>((size_t)nw * 64 * PF) +
-           (size_t)nw * AtomLists<T>::bytes();
+           lds_bytes<T>((size_t)nw * 64 * PF) + (size_t)nw * AtomLists<T>::bytes();
 }
 
 template <typename P>
