@@ -7,7 +7,8 @@ Bars (FP32): the NNP part |dE| <= 1e-4 kcal/mol per atom and force RMSE
 <= 1e-3 (as in the main parity tests), plus the coupling part's own bars
 (|dE| <= 5e-6 sum |V_ij|, |dF| <= 1e-4 max |F|).  Concurrent and sequential
 runs: energies equal exactly (fixed-order sums), forces to 1e-5 of max |F|
-(atomic adds of per-workgroup partial forces)."""
+with floating-point atomic adds of the per-workgroup partial forces, and
+exactly with the fixed-point force sums (NNP_KNOB_FORCE_SUM = 2)."""
 import numpy as np
 import pytest
 
@@ -76,9 +77,13 @@ def test_step_matches_oracles(orc, hp, prec):
     np.testing.assert_allclose(Fm.double().cpu().numpy(), Fcm, rtol=0, atol=1e-4 * np.abs(Fcm).max())
 
 
-def test_concurrent_equals_sequential(hp):
+@pytest.mark.parametrize("force_sum", [1, 2])
+def test_concurrent_equals_sequential(hp, force_sum):
+    """force_sum 2 (fixed-point force sums): the NNP forces too are bitwise
+    equal between the concurrent and the sequential runs."""
     torch = torch_cuda()
     s, lig, w, t, step, probe, n_probe = _setup(torch, hp)
+    step.model.set_knob("force_sum", force_sum)
     sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
     E = torch.empty(1, dtype=torch.float64, device="cuda")
     Fn = torch.empty_like(t["x_nnp"])
@@ -110,5 +115,8 @@ def test_concurrent_equals_sequential(hp):
         assert float(Ec.cpu()[0]) == float(E.cpu()[0]), it
         assert np.isfinite(float(Ep.cpu()[0])) and float(Epc.cpu()[0]) == float(Ep.cpu()[0]), it
         scale = float(Fn.abs().max())
-        np.testing.assert_allclose(Fc.cpu().numpy(), Fn.cpu().numpy(), rtol=0, atol=1e-5 * scale)
+        if force_sum == 2:
+            np.testing.assert_array_equal(Fc.cpu().numpy(), Fn.cpu().numpy())
+        else:
+            np.testing.assert_allclose(Fc.cpu().numpy(), Fn.cpu().numpy(), rtol=0, atol=1e-5 * scale)
         np.testing.assert_array_equal(Fmc.cpu().numpy(), Fm.cpu().numpy())
