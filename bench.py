@@ -516,8 +516,9 @@ def main():
     # bytes / HBM) / measured time)
     pairs5, triples5 = geometry_counts(b5, hp["rcr"], hp["rca"])
     D = synth.aev_dim(hp)
+    # BF16 handles keep both the AEV rows and the dE/dAEV rows in bf16
     st5 = stage_floors(hp, M, b5.n_atoms, pairs5, triples5, g_bytes=2 * D * b5.n_atoms,
-                       dg_bytes=4 * D * b5.n_atoms)
+                       dg_bytes=2 * D * b5.n_atoms)
     for k, v in per_kernel.items():
         if k in flops:
             v["tflops"] = flops[k] * b5.n_atoms / (v["avg_us"] * 1e-6) / 1e12
@@ -624,7 +625,7 @@ def main():
                 secf, _, Ef, Ff, _ = run_form(torch, hf, b, 20, 3, timing=False, graph=True)
                 p_, t_ = (pairs3, triples3) if name == "ragged_512" else (pairs5, triples5)
                 gb = (2 if prec == "bf16" else 4) * D * b.n_atoms
-                stf = stage_floors(hp, M, b.n_atoms, p_, t_, g_bytes=gb, dg_bytes=4 * D * b.n_atoms,
+                stf = stage_floors(hp, M, b.n_atoms, p_, t_, g_bytes=gb, dg_bytes=gb,
                                    mfma_peak=PEAK["bf16" if prec == "bf16" else "fp32"])
                 fl = sum(v["floor_s"] for v in stf.values())
                 entry.update({"atom_evals_per_s": b.n_atoms / secf, "ms_per_eval": secf * 1e3,

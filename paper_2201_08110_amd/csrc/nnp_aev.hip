@@ -1452,6 +1452,14 @@ __device__ inline void ld4(const double* p, double v[4]) {
     const double2 a = *(const double2*)p, b = *(const double2*)(p + 2);
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
+// four consecutive dE/dAEV values from global memory in their storage type
+__device__ inline void ldg4(const float* p, float v[4]) { ld4(p, v); }
+__device__ inline void ldg4(const double* p, double v[4]) { ld4(p, v); }
+__device__ inline void ldg4(const bf16_t* p, float v[4]) {
+    const uint2 q = *(const uint2*)p;
+    v[0] = __uint_as_float(q.x << 16); v[1] = __uint_as_float(q.x & 0xffff0000u);
+    v[2] = __uint_as_float(q.y << 16); v[3] = __uint_as_float(q.y & 0xffff0000u);
+}
 __device__ inline void st4(float* p, const float v[4]) { *(float4*)p = make_float4(v[0], v[1], v[2], v[3]); }
 __device__ inline void st4(double* p, const double v[4]) {
     *(double2*)p = make_double2(v[0], v[1]);
@@ -1491,11 +1499,12 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_for
                                                 const uint16_t* __restrict__ nbr,
                                                 const int32_t* __restrict__ nbr_cnt,
                                                 const int32_t* __restrict__ row_of_atom,
-                                                const typename P::TA* __restrict__ dG,
+                                                const typename P::TG* __restrict__ dG,
                                                 typename P::T* __restrict__ F,
                                                 unsigned long long* __restrict__ Fq) {
     typedef typename P::T T;
     typedef typename P::TA TA;
+    typedef typename P::TG TG;
     typedef ForceAcc<T, FIXED> Acc;
     typedef typename Acc::V V;
     constexpr int NA = kNAZ / NZ;
@@ -1528,18 +1537,18 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_for
         const int il = i0 + ic;
         const int cnt = cs.ccnt[ic];
         const int nang = cnt & 0xffff, nall = cnt >> 16;
-        const TA* gsrc = dG + (size_t)cs.crow[ic] * c.Dp;
+        const TG* gsrc = dG + (size_t)cs.crow[ic] * c.Dp;
         // the atom's dE/dAEV row: 16 values per lane and load, all in flight
         // before the first use; groups of 16 never straddle a block
         if constexpr (!GD) {
-            const TA* src = dG + (size_t)cs.crow[ic] * c.Dp;
+            const TG* src = dG + (size_t)cs.crow[ic] * c.Dp;
             TA v[2][16];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int e = 16 * (lane + 64 * u);
 #pragma unroll
                 for (int q4 = 0; q4 < 4; ++q4)
-                    if (e < c.D) ld4(src + e + 4 * q4, &v[u][4 * q4]);
+                    if (e < c.D) ldg4(src + e + 4 * q4, &v[u][4 * q4]);
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -1569,7 +1578,7 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_for
                 T gg[4];
                 if constexpr (GD) {
                     TA ga[4];
-                    ld4(gsrc + kNR * st + 4 * q, ga);
+                    ldg4(gsrc + kNR * st + 4 * q, ga);
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) gg[kk] = (T)ga[kk];
                 } else {
@@ -1643,7 +1652,7 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_for
                     T gg[4];
                     if constexpr (GD) {
                         TA ga[4];
-                        ld4(gsrc + pb + NZ * a + z4, ga);
+                        ldg4(gsrc + pb + NZ * a + z4, ga);
 #pragma unroll
                         for (int z = 0; z < 4; ++z) gg[z] = (T)ga[z];
                     } else {

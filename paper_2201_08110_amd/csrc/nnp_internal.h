@@ -68,10 +68,12 @@ template <> struct Store<bf16_t> {
 
 // ---------------------------------------------------------------------------
 // Precision modes: T = featuriser / force arithmetic, TS = GEMM operand
-// storage, TA = GEMM accumulator and epilogue arithmetic.
-struct PrecF64  { typedef double T; typedef double TS; typedef double TA; };
-struct PrecF32  { typedef float  T; typedef float  TS; typedef float  TA; };
-struct PrecBF16 { typedef float  T; typedef bf16_t TS; typedef float  TA; };
+// storage, TA = GEMM accumulator and epilogue arithmetic, TG = storage of the
+// dE/dAEV rows the layer-1 backward hands to the force kernel (BF16 handles
+// keep them in bf16 like every other operand between their kernels).
+struct PrecF64  { typedef double T; typedef double TS; typedef double TA; typedef double TG; };
+struct PrecF32  { typedef float  T; typedef float  TS; typedef float  TA; typedef float  TG; };
+struct PrecBF16 { typedef float  T; typedef bf16_t TS; typedef float  TA; typedef bf16_t TG; };
 
 constexpr int kMaxSpecies = 8;
 constexpr int kNR = 16;          // radial shifts supported by the kernels
@@ -128,7 +130,7 @@ template <typename P> struct Work {
     TS* DZ1;                // [Rcap][M*H1]
     TA* Epart;              // [Rcap][M][epart_nt]  per-row energy partials
     int epart_nt;           // partials per row and model (set by launch_mlp)
-    TA* dG;                 // [Rcap][Dp]
+    typename P::TG* dG;     // [Rcap][Dp]
     unsigned long long* Fq; // [A][3]  fixed-point force sums (2^32 units, two's complement)
     int32_t* moff;          // [max_mols+1]  offsets padded to the launch bound (device counts)
     int32_t* dcnt;          // [2]  the batch's molecule and atom counts (device counts)

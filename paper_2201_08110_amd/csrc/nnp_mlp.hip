@@ -407,7 +407,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs<P> g) {
             }
         }
     } else if (EPI == EPI_ACC) {
-        TA* C = (TA*)g.C + (size_t)z * g.c_z;
+        // dE/dAEV rows, in the precision's dE/dAEV storage type
+        typedef typename P::TG TG;
+        TG* C = (TG*)g.C + (size_t)z * g.c_z;
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
@@ -415,7 +417,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs<P> g) {
                 TA v[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] = (TA)acc[i][j][r];
-                Quad<TA, ST>::st(C + (size_t)(row0 + i * 16) * g.ldc + col0 + j * 16, v);
+                Quad<TG, ST>::st(C + (size_t)(row0 + i * 16) * g.ldc + col0 + j * 16, v);
             }
     } else if (EPI == EPI_DSIG) {
         TS* C = (TS*)g.C + (size_t)z * g.c_z;
@@ -721,17 +723,18 @@ __global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
             }
             st_strip_bf16(Cw + (size_t)i * 16 * g.ldc, pk, lane);
         }
-    } else {   // EPI_ACC
-        TA* C = (TA*)g.C;
+    } else {   // EPI_ACC: dE/dAEV rows in bf16, 64-byte row segments as above
+        TS* Cw = (TS*)g.C + (size_t)row0 * g.ldc + tile_n * BN + wn * WTN + 8 * (lane >> 4);
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+        for (int i = 0; i < FM; ++i) {
+            uint32_t pk[FN][2];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) {
-                TA v[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = acc[i][j][r];
-                Quad<TA, 1>::st(C + (size_t)(row0 + i * 16) * g.ldc + col0 + j * 16, v);
+            for (int j = 0; j < FN; ++j) {
+                pk[j][0] = pack_bf16x2(acc[i][j][0], acc[i][j][1]);
+                pk[j][1] = pack_bf16x2(acc[i][j][2], acc[i][j][3]);
             }
+            st_strip_bf16(Cw + (size_t)i * 16 * g.ldc, pk, lane);
+        }
     }
 }
 

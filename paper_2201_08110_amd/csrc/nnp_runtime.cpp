@@ -349,7 +349,7 @@ template <typename P> nnp_status alloc_work2(nnp_handle* h, const Work<P>& w1, W
     ALLOC(DZ2, sizeof(TS) * R * M * sh.H2);
     ALLOC(DZ1, sizeof(TS) * R * M * sh.H1);
     ALLOC(Epart, sizeof(TA) * R * M * (sh.H3 / 64));
-    ALLOC(dG, sizeof(TA) * R * sh.Dp);
+    ALLOC(dG, sizeof(typename P::TG) * R * sh.Dp);
 #undef ALLOC
     HIP_TRY(hipMemset(w.info, 0, sizeof(BucketInfo)));
     HIP_TRY(hipMemset(w.G, 0, sizeof(TS) * R * sh.Dp));
@@ -386,7 +386,7 @@ template <typename P> nnp_status alloc_work(nnp_handle* h, Work<P>& w) {
     ALLOC(DZ2, sizeof(TS) * R * M * sh.H2);
     ALLOC(DZ1, sizeof(TS) * R * M * sh.H1);
     ALLOC(Epart, sizeof(TA) * R * M * (sh.H3 / 64));
-    ALLOC(dG, sizeof(TA) * R * sh.Dp);
+    ALLOC(dG, sizeof(typename P::TG) * R * sh.Dp);
     ALLOC(Fq, sizeof(unsigned long long) * 3 * A);
     ALLOC(moff, sizeof(int32_t) * ((size_t)h->max_mols + 1));
     ALLOC(dcnt, sizeof(int32_t) * 2);
