@@ -1204,13 +1204,18 @@ __global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, i
             }
             wave_sync();
         }
-        for (unsigned long long zset = ~filled & (NB >= 64 ? ~0ull : ((1ull << NB) - 1)); zset;) {
-            const int zA = __builtin_ctzll(zset);
-            zset &= zset - 1;
-            const int zB = zset ? __builtin_ctzll(zset) : -1;
-            zset &= zset - 1;
-            const int zb = h ? zB : zA;
-            if (zb >= 0) put(RL + kNAZ * zb + q, T(0));
+        // blocks without pairs: zeros in 16-byte pieces, a few lanes per block
+        {
+            constexpr int VP = 16 / (int)sizeof(TS), PPB = kNAZ / VP, BPP = 64 / PPB;
+            const int pc = lane % PPB;
+            for (int b0 = 0; b0 < NB; b0 += BPP) {
+                const int zb = b0 + lane / PPB;
+                if (zb < NB && !((filled >> zb) & 1ull))
+                    *(uint4*)(grow + RL + kNAZ * zb + VP * pc) = make_uint4(0u, 0u, 0u, 0u);
+            }
+            if (arow)
+                for (int e = lane; e < NB * kNAZ; e += 64)
+                    if (!((filled >> (e / kNAZ)) & 1ull)) arow[RL + e] = T(0);
         }
     }
 }
