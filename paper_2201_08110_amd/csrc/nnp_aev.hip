@@ -947,32 +947,39 @@ __device__ inline void block_elements(int L, int S, int& a, int& b) {
 template <typename T, typename SpOf>
 __device__ inline int atom_lists(const AtomLists<T>& al, SpOf sp_of, int nang, int nall, int S) {
     const int lane = lane_id();
-    int ca = 0, cr = 0;   // lane s (< S): neighbours of element s in each run
-    for (int t0 = 0; t0 < nall; t0 += 64) {
-        const int t = t0 + lane;
-        const int sp = t < nall ? sp_of(t) : -1;
-        for (int s = 0; s < S; ++s) {
-            const int na = __popcll(__ballot(sp == s && t < nang));
-            const int nr = __popcll(__ballot(sp == s && t >= nang));
-            if (lane == s) {
-                ca += na;
-                cr += nr;
-            }
+    // Both runs (angular [0, nang), radial-only [nang, nall)) are sorted by
+    // element: the first neighbour of each element in a run marks where that
+    // element starts; an element absent from a run starts where the next
+    // present one does (or at the run's end).
+    if (lane <= S) {
+        al.aoff[lane] = nang;
+        al.roff[lane] = nall;
+    }
+    wave_sync();
+    for (int t = lane; t < nall; t += 64) {
+        const int sp = sp_of(t);
+        if (t == 0 || t == nang || sp_of(t - 1) != sp) {
+            if (t < nang) al.aoff[sp] = t;
+            else al.roff[sp] = t;
         }
     }
-    // exclusive prefix over the elements
-    int pa = ca, pr = cr;
-    for (int o = 1; o < 8; o <<= 1) {
-        const int va = __shfl_up(pa, o), vr = __shfl_up(pr, o);
-        if (lane >= o) {
-            pa += va;
-            pr += vr;
+    wave_sync();
+    int ao = lane <= S ? al.aoff[lane] : nang, ro = lane <= S ? al.roff[lane] : nall;
+    for (int o = 1; o <= 8; o <<= 1) {   // suffix minimum over lanes 0..S
+        const int va = __shfl_down(ao, o), vr = __shfl_down(ro, o);
+        if (lane + o <= S) {
+            ao = min(ao, va);
+            ro = min(ro, vr);
         }
     }
     if (lane <= S) {
-        al.aoff[lane] = lane < S ? pa - ca : nang;
-        al.roff[lane] = lane < S ? nang + pr - cr : nall;
+        al.aoff[lane] = ao;
+        al.roff[lane] = ro;
     }
+    // lane s: angular neighbours of element s (the shuffle runs on every
+    // lane: a lane outside the condition would not supply its value)
+    const int ao_next = __shfl_down(ao, 1);
+    const int ca = lane < S ? ao_next - ao : 0;
     // angular block sizes and their prefix
     const int NB = S * (S + 1) / 2;
     int a = 0, b = 0;
@@ -1027,7 +1034,7 @@ __device__ inline void pair_of(const AtomLists<T>& al, int NB, int S, int p, int
 // as it is complete: no row is assembled in LDS, which keeps the workgroup's
 // LDS small enough for more waves per CU.
 template <typename P, int NZ>
-__global__ __launch_bounds__(256) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
+__global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
                                              int chunk, int cap, const int32_t* __restrict__ mol_off,
                                              const int32_t* __restrict__ species,
                                              const typename P::T* __restrict__ x,
