@@ -1536,6 +1536,7 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_for
     cs.take(lb, max_apm, cap);
     V* sF = lb.take<V>(3 * (size_t)max_apm);
     T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
+    T* pg = lb.take<T>((size_t)nw * 64 * 6) + (size_t)wave * 64 * 6;   // a batch's pair forces
     // the atom's dE/dAEV row: staged in LDS (blocks kBlkPad apart), or read
     // straight from global memory (GD: L1/L2 hits, the LDS left to the
     // force sums)
@@ -1620,9 +1621,16 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_for
                 fi2 += dEdr * u2;
             }
         }
-        // angular: lane per neighbour pair, pairs in rotation order
+        // angular: lane per neighbour pair, pairs in rotation order, 64 at a
+        // time.  A pair's forces on its atoms j and k go to LDS with plain
+        // stores; then lane (t, c) sums component c of neighbour t over the
+        // batch's pairs that hold t and makes one add to the molecule's sums
+        // (LDS atomic adds cost far more than stores and reads on gfx950).
         const int npair = nang * (nang - 1) / 2;
-        for (int p = lane; p < npair; p += 64) {
+        const int full = nang * ((nang - 1) >> 1), D = (nang - 1) >> 1, half = nang >> 1;
+        for (int P0 = 0; P0 < npair; P0 += 64) {
+          const int p = P0 + lane, nbat = min(64, npair - P0);
+          if (p < npair) {
             int j, k;
             decode_pair_rot(p, nang, j, k);
             const T* ej = nb + kNbStride * j;
@@ -1687,16 +1695,40 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_for
             const T gk0 = Drk * uk0 + Dc * (uj0 - cs_ * uk0) * ik;
             const T gk1 = Drk * uk1 + Dc * (uj1 - cs_ * uk1) * ik;
             const T gk2 = Drk * uk2 + Dc * (uj2 - cs_ * uk2) * ik;
-            const int jj = tj >> 8, kk = tk >> 8;
-            Acc::add(&sF[3 * jj + 0], -gj0);
-            Acc::add(&sF[3 * jj + 1], -gj1);
-            Acc::add(&sF[3 * jj + 2], -gj2);
-            Acc::add(&sF[3 * kk + 0], -gk0);
-            Acc::add(&sF[3 * kk + 1], -gk1);
-            Acc::add(&sF[3 * kk + 2], -gk2);
+            T* o = pg + 6 * lane;
+            o[0] = gj0; o[1] = gj1; o[2] = gj2;
+            o[3] = gk0; o[4] = gk1; o[5] = gk2;
             fi0 += gj0 + gk0;
             fi1 += gj1 + gk1;
             fi2 += gj2 + gk2;
+          }
+          wave_sync();
+          // diagonals of this batch: pair q = (d-1) n + a on diagonal d <= D,
+          // q = full + a on the half diagonal d = n/2 of an even n
+          const int d0 = P0 < full ? P0 / nang + 1 : half;
+          const int d1 = P0 + nbat - 1 < full ? (P0 + nbat - 1) / nang + 1 : half;
+          for (int u = lane; u < 3 * nang; u += 64) {
+            const int t = u / 3, cc = u - 3 * t;
+            T sum = T(0);
+            for (int d = d0; d <= d1; ++d) {
+              int qj, qk;   // the pairs (t, t+d) and (t-d, t)
+              if (d <= D) {
+                qj = (d - 1) * nang + t;
+                const int a = t - d;
+                qk = (d - 1) * nang + (a < 0 ? a + nang : a);
+              } else {
+                qj = t < half ? full + t : -1;
+                qk = t >= half ? full + t - half : -1;
+              }
+              qj -= P0;
+              qk -= P0;
+              if (qj >= 0 && qj < nbat) sum += pg[6 * qj + cc];
+              if (qk >= 0 && qk < nbat) sum += pg[6 * qk + 3 + cc];
+            }
+            const int jt = tag_of(nb + kNbStride * t) >> 8;
+            Acc::add(&sF[3 * jt + cc], -sum);
+          }
+          wave_sync();
         }
         for (int off = 32; off > 0; off >>= 1) {
             fi0 += __shfl_xor(fi0, off);
@@ -1719,7 +1751,7 @@ static size_t forces_lds(int max_apm, int cap, int S, int nw, bool fixed = false
     const int GL = kNR * S + kBlkPad * S * (S + 1) / 2;
     return ChunkStage<T>::bytes(max_apm, cap) +
            (fixed ? lds_bytes<unsigned long long>(3 * (size_t)max_apm) : lds_bytes<T>(3 * (size_t)max_apm)) +
-           lds_bytes<T>((size_t)nw * cap * kNbStride) +
+           lds_bytes<T>((size_t)nw * cap * kNbStride) + lds_bytes<T>((size_t)nw * 64 * 6) +
            (gd ? 0 : lds_bytes<T>((size_t)nw * GL));
 }
 
