@@ -1484,6 +1484,35 @@ __device__ inline void st4(double* p, const double v[4]) {
 // (exact for FP32 contributions above 2^-9 in magnitude), and integer
 // addition is associative, so the sums are bitwise the same whatever the
 // order; the energy kernel turns them back into F.
+// Energy of molecule b summed by one wave in a fixed order (atoms strided
+// over the lanes, then a shuffle tree): the per-row partials of every model
+// plus the output bias, the ensemble mean times the energy scale, plus the
+// self-energies.
+template <typename P>
+__device__ inline double molecule_energy(int a0, int a1, int M, int NT, double scale,
+                                         const int32_t* __restrict__ species, int S,
+                                         const int32_t* __restrict__ row_of_atom,
+                                         const typename P::TA* __restrict__ Epart,
+                                         const typename P::TA* __restrict__ b4,
+                                         const double* __restrict__ sae) {
+    const int lane = lane_id();
+    double acc = 0.0;
+    for (int a = a0 + lane; a < a1; a += 64) {
+        int s = species[a];
+        s = (s < 0 || s >= S) ? 0 : s;
+        const size_t row = (size_t)row_of_atom[a];
+        double e = 0.0;
+        for (int m = 0; m < M; ++m) {
+            double em = (double)b4[s * M + m];
+            for (int t = 0; t < NT; ++t) em += (double)Epart[(row * M + m) * NT + t];
+            e += em;
+        }
+        acc += scale * (e / M) + sae[s];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    return (a1 > a0) ? acc : 0.0;
+}
+
 template <typename T, bool FIXED> struct ForceAcc;
 template <typename T> struct ForceAcc<T, false> {
     typedef T V;
@@ -1513,7 +1542,8 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_for
                                                 const int32_t* __restrict__ row_of_atom,
                                                 const typename P::TG* __restrict__ dG,
                                                 typename P::T* __restrict__ F,
-                                                unsigned long long* __restrict__ Fq) {
+                                                unsigned long long* __restrict__ Fq,
+                                                EnergyArgs<P> ea) {
     typedef typename P::T T;
     typedef typename P::TA TA;
     typedef typename P::TG TG;
@@ -1523,6 +1553,14 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_for
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x;
     const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
+    // the molecule's energy (as k_energy computes it), by the first wave of
+    // its first workgroup, ahead of the force work
+    if (ea.E && blockIdx.y == 0 && threadIdx.x < 64 && b < ea.B && !(ea.dcnt && b >= ea.dcnt[0])) {
+        const bool ok = !(a0 < 0 || n < 0 || a0 + n > A);
+        const double v = molecule_energy<P>(ok ? a0 : 0, ok ? a0 + n : 0, ea.M, ea.NT, ea.scale, species,
+                                            c.S, row_of_atom, ea.Epart, ea.b4, ea.sae);
+        if (threadIdx.x == 0) ea.E[b] = ea.accumulate ? ea.E[b] + v : v;
+    }
     if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
     const int i0 = blockIdx.y * chunk;
     if (i0 >= n) return;
@@ -1758,7 +1796,8 @@ static size_t forces_lds(int max_apm, int cap, int S, int nw, bool fixed = false
 template <typename P>
 hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
                          const int32_t* mol_off, const int32_t* species, const typename P::T* x,
-                         Work<P>& w, typename P::T* F, hipStream_t st, const Timer& tm) {
+                         Work<P>& w, typename P::T* F, hipStream_t st, const Timer& tm,
+                         const EnergyArgs<P>& ea) {
     typedef typename P::T T;
     if (c.Dp > 2 * 16 * 64) return hipErrorInvalidValue;
     dim3 grid(sh.B, (sh.max_apm + sh.chunk - 1) / sh.chunk);
@@ -1775,7 +1814,7 @@ hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
     if (e != hipSuccess) return e;
     tm.b("forces", st);
     hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.chunk, sh.cap_nbr,
-                       mol_off, species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.dG, F, w.Fq);
+                       mol_off, species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.dG, F, w.Fq, ea);
     tm.e("forces", st);
     return hipGetLastError();
 }
@@ -2095,24 +2134,24 @@ __global__ __launch_bounds__(256) void k_energy(int A, int B, int M, int NT, dou
             const T f = (T)((double)(long long)Fq[t] * (1.0 / kForceFix));
             F[t] = accumulate ? F[t] + f : f;
         }
-    double acc = 0.0;
-    for (int a = a0 + lane; a < a1; a += 64) {
-        int s = species[a];
-        s = (s < 0 || s >= S) ? 0 : s;
-        const size_t row = (size_t)row_of_atom[a];
-        double e = 0.0;
-        for (int m = 0; m < M; ++m) {
-            double em = (double)b4[s * M + m];
-            for (int t = 0; t < NT; ++t) em += (double)Epart[(row * M + m) * NT + t];
-            e += em;
-        }
-        acc += scale * (e / M) + sae[s];
-    }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) {
-        const double v = (a1 > a0) ? acc : 0.0;
-        E[b] = accumulate ? E[b] + v : v;
-    }
+    const double v = molecule_energy<P>(a0, a1, M, NT, scale, species, S, row_of_atom, Epart, b4, sae);
+    if (lane == 0) E[b] = accumulate ? E[b] + v : v;
+}
+
+template <typename P>
+EnergyArgs<P> energy_args(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, double* E, bool accumulate) {
+    EnergyArgs<P> ea;
+    ea.E = E;
+    ea.Epart = w.Epart;
+    ea.b4 = wt.b4;
+    ea.sae = wt.sae;
+    ea.scale = sh.energy_scale;
+    ea.M = sh.M;
+    ea.NT = w.epart_nt;
+    ea.B = sh.B;
+    ea.accumulate = accumulate ? 1 : 0;
+    ea.dcnt = sh.dev_counts ? w.dcnt : nullptr;
+    return ea;
 }
 
 template <typename P>
@@ -2139,7 +2178,9 @@ hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t
                                       hipStream_t, const Timer&);                              \
     template hipError_t launch_forces<P>(const Shape&, const AevConst<P::T>&, const int32_t*,  \
                                          const int32_t*, const P::T*, Work<P>&, P::T*,         \
-                                         hipStream_t, const Timer&);                           \
+                                         hipStream_t, const Timer&, const EnergyArgs<P>&);     \
+    template EnergyArgs<P> energy_args<P>(const Shape&, const DevWeights<P>&, Work<P>&,        \
+                                          double*, bool);                                      \
     template hipError_t launch_aev_jvp<P>(const Shape&, const AevConst<P::T>&, const int32_t*, \
                                           const int32_t*, const P::T*, const P::T*, Work<P>&,  \
                                           P::TS*, hipStream_t, const Timer&);                  \

@@ -297,10 +297,23 @@ hipError_t launch_aev_jvp(const Shape& sh, const AevConst<typename P::T>& c,
                           const int32_t* mol_off, const int32_t* species,
                           const typename P::T* x, const typename P::T* v, Work<P>& w,
                           typename P::TS* Gd, hipStream_t st, const Timer& tm);
+// Per-molecule energies computed inside the force kernel (E null: none)
+template <typename P> struct EnergyArgs {
+    double* E = nullptr;
+    const typename P::TA* Epart = nullptr;
+    const typename P::TA* b4 = nullptr;
+    const double* sae = nullptr;
+    double scale = 0.0;
+    int M = 0, NT = 0, B = 0, accumulate = 0;
+    const int32_t* dcnt = nullptr;
+};
 template <typename P>
 hipError_t launch_forces(const Shape& sh, const AevConst<typename P::T>& c,
                          const int32_t* mol_off, const int32_t* species, const typename P::T* x,
-                         Work<P>& w, typename P::T* F, hipStream_t st, const Timer& tm);
+                         Work<P>& w, typename P::T* F, hipStream_t st, const Timer& tm,
+                         const EnergyArgs<P>& ea = EnergyArgs<P>());
+template <typename P>
+EnergyArgs<P> energy_args(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, double* E, bool accumulate);
 template <typename P>
 hipError_t launch_train_mlp(const Shape& sh, const DevWeights<P>& wt, Work<P>& w,
                             TrainWork<P>& tw, const int32_t* mol_of_atom, const double* grad_E,

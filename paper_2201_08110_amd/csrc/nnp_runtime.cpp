@@ -535,8 +535,15 @@ nnp_status stage_finish(nnp_handle* h, const Shape& sh, const int32_t* moff, con
                         hipStream_t st, const Timer& tm) {
     const AevConst<typename P::T>& c = const_of<typename P::T>(h);
     const int32_t* sp = w.zlut ? w.sp : species;
-    if (F && sh.A > 0) HIP_TRY(launch_forces<P>(sh, c, moff, sp, x, w, F, st, tm));
-    HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), moff, sp, w, E, sh.A > 0 ? F : nullptr, acc, st, tm));
+    // with floating-point force sums the force kernel also sums the energies
+    // (one launch fewer); fixed-point sums need the energy kernel after every
+    // force workgroup, to convert them
+    const bool fuse_e = F && sh.A > 0 && !sh.force_fixed;
+    if (F && sh.A > 0)
+        HIP_TRY(launch_forces<P>(sh, c, moff, sp, x, w, F, st, tm,
+                                 fuse_e ? energy_args<P>(sh, weights_of<P>(h), w, E, acc) : EnergyArgs<P>()));
+    if (!fuse_e)
+        HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), moff, sp, w, E, sh.A > 0 ? F : nullptr, acc, st, tm));
     return NNP_OK;
 }
 
@@ -630,9 +637,12 @@ nnp_status run_forward(nnp_handle* h, const nnp_batch* b, const typename P::T* x
     }
     if (aev_out) return NNP_OK;
     if (sh.A > 0) HIP_TRY(launch_mlp<P>(sh, weights_of<P>(h), w, st, tm));
+    const bool fuse_e = F && sh.A > 0 && !sh.force_fixed;
     if (F && sh.A > 0)
-        HIP_TRY(launch_forces<P>(sh, c, moff, sp, x, w, F, st, tm));
-    HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), moff, sp, w, E, sh.A > 0 ? F : nullptr, acc, st, tm));
+        HIP_TRY(launch_forces<P>(sh, c, moff, sp, x, w, F, st, tm,
+                                 fuse_e ? energy_args<P>(sh, weights_of<P>(h), w, E, acc) : EnergyArgs<P>()));
+    if (!fuse_e)
+        HIP_TRY(launch_energy<P>(sh, weights_of<P>(h), moff, sp, w, E, sh.A > 0 ? F : nullptr, acc, st, tm));
     return NNP_OK;
 }
 
