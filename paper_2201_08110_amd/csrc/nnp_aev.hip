@@ -103,9 +103,9 @@ __device__ inline void decode_pair_rot(int p, int n, int& j, int& k) {
 }
 
 // ==========================================================================
-// Element bucketing (three kernels): per-block element counts and molecule
-// checks; one small scan of the block counts into padded bucket starts; a
-// stable scatter of every atom to its bucket row.
+// Element bucketing (two kernels): per-block element counts and molecule
+// checks; then, in every workgroup, the prefix of the block counts into
+// padded bucket starts and a stable scatter of its atoms to their bucket rows.
 // Element of atom a: the batch's label itself, or, on handles with a table
 // of atomic numbers (zlut != null), the table's index of that atomic number
 // (-1 when absent), written to sp_out for the later kernels.
@@ -181,102 +181,84 @@ __global__ __launch_bounds__(1024) void k_bucket_count(int A, int B, int S, int 
     }
 }
 
-// Per-element exclusive prefix of the per-block counts (two passes over
-// contiguous block ranges, one range per thread), padded bucket starts, the
-// element of every row tile and the padding rows.
-__global__ __launch_bounds__(256) void k_bucket_scan(int nblk, int S, int row_tile, int Rcap,
-                                                     const int32_t* __restrict__ blk_cnt,
-                                                     int32_t* __restrict__ blk_base,
-                                                     int32_t* __restrict__ atom_of_row,
-                                                     int32_t* __restrict__ tile_species,
-                                                     BucketInfo* __restrict__ info,
-                                                     int32_t* __restrict__ flag) {
-    __shared__ int part[256][kMaxSpecies + 1];
-    __shared__ int tot[kMaxSpecies];
-    __shared__ int base[kMaxSpecies + 1];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int per = (nblk + nt - 1) / nt, k0 = min(tid * per, nblk), k1 = min(k0 + per, nblk);
-    // per-element arrays indexed with compile-time indices only (kept in
-    // registers); elements past S stay zero
-    int sum[kMaxSpecies];
-#pragma unroll
-    for (int q = 0; q < kMaxSpecies; ++q) sum[q] = 0;
-    for (int k = k0; k < k1; ++k)
-#pragma unroll
-        for (int q = 0; q < kMaxSpecies; ++q)
-            if (q < S) sum[q] += blk_cnt[k * kMaxSpecies + q];
-    // exclusive scan over the threads' ranges, per element: in-wave shuffles,
-    // then the totals of the preceding waves
-    __shared__ int wtot[4][kMaxSpecies];
-    const int lane = lane_id(), wave = tid >> 6;
-    int incl[kMaxSpecies];
-#pragma unroll
-    for (int q = 0; q < kMaxSpecies; ++q) incl[q] = sum[q];
-    for (int o = 1; o < 64; o <<= 1)
-#pragma unroll
-        for (int q = 0; q < kMaxSpecies; ++q) {
-            const int v = __shfl_up(incl[q], o);
-            if (lane >= o) incl[q] += v;
-        }
-    if (lane == 63)
-#pragma unroll
-        for (int q = 0; q < kMaxSpecies; ++q) wtot[wave][q] = incl[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kMaxSpecies; ++q) {
-        int off = 0;
-        for (int w = 0; w < wave; ++w) off += wtot[w][q];
-        if (q < S) part[tid][q] = off + incl[q] - sum[q];
-    }
-    if (tid < S) tot[tid] = wtot[0][tid] + wtot[1][tid] + wtot[2][tid] + wtot[3][tid];
-    __syncthreads();
-    if (tid == 0) {
-        base[0] = 0;
-        for (int q = 0; q < S; ++q) {
-            base[q + 1] = base[q] + ((tot[q] + row_tile - 1) / row_tile) * row_tile;
-            info->count[q] = tot[q];
-        }
-        for (int q = 0; q <= S; ++q) info->off[q] = base[q];
-        int rows = base[S];
-        if (rows > Rcap) {
-            atomicOr(flag, FLAG_CAPACITY);
-            rows = 0;
-        }
-        info->rows = rows;
-    }
-    __syncthreads();
-    // absolute bucket start of every block's first atom of each element
-    for (int q = 0; q < S; ++q) {
-        int run = base[q] + part[tid][q];
-        for (int k = k0; k < k1; ++k) {
-            blk_base[k * kMaxSpecies + q] = run;
-            run += blk_cnt[k * kMaxSpecies + q];
-        }
-    }
-    const int rows = base[S] <= Rcap ? base[S] : 0;
-    for (int t = tid; t < Rcap / row_tile; t += nt) {
-        const int r = t * row_tile;
-        int sp = -1;
-        if (r < rows)
-            for (int q = 0; q < S; ++q)
-                if (base[q] <= r && r < base[q + 1]) sp = q;
-        tile_species[t] = sp;
-    }
-    // padding rows of every bucket
-    for (int q = 0; q < S; ++q)
-        for (int r = base[q] + tot[q] + tid; r < base[q + 1] && r < rows; r += nt) atom_of_row[r] = -1;
-}
-
-__global__ __launch_bounds__(1024) void k_bucket_scatter(int A, int B, int S, int sub,
-                                                         const int32_t* __restrict__ dA,
-                                                         const int32_t* __restrict__ mol_off,
-                                                         const int32_t* __restrict__ species,
-                                                         const int32_t* __restrict__ blk_base,
-                                                         const BucketInfo* __restrict__ info,
-                                                         int32_t* __restrict__ row_of_atom,
-                                                         int32_t* __restrict__ atom_of_row) {
-    __shared__ int wcnt[kPrepBlock / 64][kMaxSpecies];
+// Scan and scatter in one launch: every workgroup sums the count kernel's
+// per-block element counts itself (totals and the prefix of the blocks
+// before its own), so the padded bucket starts need no separate kernel;
+// workgroup 0 also writes the bucket info, the element of every row tile and
+// the padding rows.  Then the workgroup's atoms go to their rows, in atom
+// order within each element (stable).
+__global__ __launch_bounds__(1024) void k_bucket_place(int A, int B, int S, int sub, int nblk,
+                                                       int row_tile, int Rcap,
+                                                       const int32_t* __restrict__ dA,
+                                                       const int32_t* __restrict__ mol_off,
+                                                       const int32_t* __restrict__ species,
+                                                       const int32_t* __restrict__ blk_cnt,
+                                                       int32_t* __restrict__ row_of_atom,
+                                                       int32_t* __restrict__ atom_of_row,
+                                                       int32_t* __restrict__ tile_species,
+                                                       BucketInfo* __restrict__ info,
+                                                       int32_t* __restrict__ flag) {
+    constexpr int NWV = kPrepBlock / 64;
+    __shared__ int red[NWV][kMaxSpecies][2];
+    __shared__ int tot_s[kMaxSpecies], pre_s[kMaxSpecies], base_s[kMaxSpecies + 1];
+    __shared__ int wcnt[NWV][kMaxSpecies];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, blk = blockIdx.x;
+    {
+        // thread (chunk kc, element q): count blocks kc, kc + 128, ...
+        const int q = tid & (kMaxSpecies - 1), kc = tid / kMaxSpecies;
+        int tot = 0, pre = 0;
+        if (q < S)
+            for (int k = kc; k < nblk; k += kPrepBlock / kMaxSpecies) {
+                const int v = blk_cnt[k * kMaxSpecies + q];
+                tot += v;
+                pre += k < blk ? v : 0;
+            }
+        for (int o = kMaxSpecies; o < 64; o <<= 1) {   // the lanes of one element in a wave
+            tot += __shfl_xor(tot, o);
+            pre += __shfl_xor(pre, o);
+        }
+        if (lane < kMaxSpecies) {
+            red[wave][lane][0] = tot;
+            red[wave][lane][1] = pre;
+        }
+        __syncthreads();
+        if (tid < S) {
+            int t = 0, p = 0;
+            for (int w = 0; w < NWV; ++w) {
+                t += red[w][tid][0];
+                p += red[w][tid][1];
+            }
+            tot_s[tid] = t;
+            pre_s[tid] = p;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            base_s[0] = 0;
+            for (int q2 = 0; q2 < S; ++q2)
+                base_s[q2 + 1] = base_s[q2] + ((tot_s[q2] + row_tile - 1) / row_tile) * row_tile;
+        }
+        __syncthreads();
+    }
+    const int rows = base_s[S] <= Rcap ? base_s[S] : 0;
+    if (blk == 0) {
+        if (tid == 0) {
+            for (int q = 0; q < S; ++q) info->count[q] = tot_s[q];
+            for (int q = 0; q <= S; ++q) info->off[q] = base_s[q];
+            if (base_s[S] > Rcap) atomicOr(flag, FLAG_CAPACITY);
+            info->rows = rows;
+        }
+        for (int t = tid; t < Rcap / row_tile; t += blockDim.x) {
+            const int r = t * row_tile;
+            int sp = -1;
+            if (r < rows)
+                for (int q = 0; q < S; ++q)
+                    if (base_s[q] <= r && r < base_s[q + 1]) sp = q;
+            tile_species[t] = sp;
+        }
+        for (int q = 0; q < S; ++q)
+            for (int r = base_s[q] + tot_s[q] + tid; r < base_s[q + 1] && r < rows; r += blockDim.x)
+                atom_of_row[r] = -1;
+    }
     int A0, A1;
     atom_range(A, B, dA, mol_off, sub, A0, A1);
     const int a = A0 + blk * kPrepBlock + tid;
@@ -293,10 +275,10 @@ __global__ __launch_bounds__(1024) void k_bucket_scatter(int A, int B, int S, in
         if (s == q) mypre = __popcll(m & lt);
     }
     __syncthreads();
-    if (s >= 0 && info->rows > 0) {
+    if (s >= 0 && rows > 0) {
         int pre = 0;
         for (int w = 0; w < wave; ++w) pre += wcnt[w][s];
-        const int row = blk_base[blk * kMaxSpecies + s] + pre + mypre;
+        const int row = base_s[s] + pre_s[s] + pre + mypre;
         row_of_atom[a] = row;
         atom_of_row[row] = a;
     }
@@ -423,7 +405,6 @@ hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* s
                        Work<P>& w, hipStream_t st, const Timer& tm) {
     const int nblk = std::max((sh.A + kPrepBlock - 1) / kPrepBlock, (sh.B + kPrepBlock - 1) / kPrepBlock);
     int32_t* blk_cnt = w.blk;
-    int32_t* blk_base = w.blk + (size_t)nblk * kMaxSpecies;
     const int32_t* dA = sh.dev_counts ? w.dcnt + 1 : nullptr;
     tm.b("prep", st);
     if (nblk <= 1) {
@@ -435,14 +416,12 @@ hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* s
     }
     hipLaunchKernelGGL(k_bucket_count, dim3(nblk), dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S,
                        sh.max_apm, sh.sub, dA, mol_off, species, w.zlut, w.sp, w.mol_of_atom, blk_cnt, w.flag);
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(256), 0, st, nblk, sh.S, sh.row_tile, sh.Rcap,
-                       blk_cnt, blk_base, w.atom_of_row, w.tile_species, w.info, w.flag);
     // on handles with atomic numbers the count kernel has written the
     // element indices to w.sp
-    if (sh.A > 0)
-        hipLaunchKernelGGL(k_bucket_scatter, dim3((sh.A + kPrepBlock - 1) / kPrepBlock),
-                           dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S, sh.sub, dA, mol_off,
-                           w.zlut ? w.sp : species, blk_base, w.info, w.row_of_atom, w.atom_of_row);
+    hipLaunchKernelGGL(k_bucket_place, dim3(std::max(1, (sh.A + kPrepBlock - 1) / kPrepBlock)),
+                       dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S, sh.sub, nblk, sh.row_tile, sh.Rcap, dA,
+                       mol_off, w.zlut ? w.sp : species, blk_cnt, w.row_of_atom, w.atom_of_row,
+                       w.tile_species, w.info, w.flag);
     tm.e("prep", st);
     return hipGetLastError();
 }

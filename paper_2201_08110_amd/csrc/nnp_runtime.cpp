@@ -341,7 +341,7 @@ template <typename P> nnp_status alloc_work2(nnp_handle* h, const Work<P>& w1, W
     ALLOC(tile_species, sizeof(int32_t) * (R / sh.row_tile));
     ALLOC(info, sizeof(BucketInfo));
     const size_t nblk = (std::max(A, (size_t)h->max_mols) + kPrepBlock - 1) / kPrepBlock + 1;
-    ALLOC(blk, sizeof(int32_t) * 2 * kMaxSpecies * nblk);
+    ALLOC(blk, sizeof(int32_t) * kMaxSpecies * nblk);
     ALLOC(G, sizeof(TS) * R * sh.Dp);
     ALLOC(H1, sizeof(TS) * R * M * sh.H1);
     ALLOC(H2, sizeof(TS) * R * M * sh.H2);
@@ -376,7 +376,7 @@ template <typename P> nnp_status alloc_work(nnp_handle* h, Work<P>& w) {
     ALLOC(tile_species, sizeof(int32_t) * (R / sh.row_tile));
     ALLOC(info, sizeof(BucketInfo));
     const size_t nblk = (std::max(A, (size_t)h->max_mols) + kPrepBlock - 1) / kPrepBlock + 1;
-    ALLOC(blk, sizeof(int32_t) * 2 * kMaxSpecies * nblk);
+    ALLOC(blk, sizeof(int32_t) * kMaxSpecies * nblk);
     ALLOC(nbr, sizeof(uint16_t) * A * sh.cap_nbr);
     ALLOC(nbr_cnt, sizeof(int32_t) * A);
     ALLOC(G, sizeof(TS) * R * sh.Dp);
