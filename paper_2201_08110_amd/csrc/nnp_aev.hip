@@ -634,6 +634,71 @@ __global__ __launch_bounds__(64) void k_neighbours(int A, int S, int max_apm, in
 // its hits are appended in order through a ballot, angular ones (r < rca) in
 // a first sweep and the rest (r < rcr) in a second.  The lists equal those of
 // the scanning kernel entry for entry; no lane walks the molecule serially.
+// One wave: the molecule's atoms staged in stable element order (sx4: x y z
+// and a spare word per atom, sid: input index of each staged atom).
+template <typename T>
+__device__ inline void stage_element_order(const T* tx, const int* tsp, int n, int S, T* sx4, int* sid) {
+    const int lane = lane_id();
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int base = 0;
+    for (int q = 0; q < S; ++q)
+        for (int j0 = 0; j0 < n; j0 += 64) {
+            const int j = j0 + lane;
+            const int s = j < n ? tsp[j] : -1;
+            const unsigned long long m = __ballot(s == q);
+            if (s == q) {
+                const int pos = base + __popcll(m & lt);
+                sid[pos] = j;
+                sx4[4 * pos + 0] = tx[3 * j + 0];
+                sx4[4 * pos + 1] = tx[3 * j + 1];
+                sx4[4 * pos + 2] = tx[3 * j + 2];
+            }
+            base += __popcll(m);
+        }
+}
+
+// One wave: the neighbours of atom il within Rcr, those within Rca first,
+// each run in the staged (element) order, one lane per candidate and hits
+// appended through ballots; written to out and, if given, out2.  Returns
+// the packed counts nang | nall << 16, clamped to cap (an overflow raises the
+// capacity flag; writes stay within cap).
+template <typename T>
+__device__ inline int atom_neighbours(const T* sx4, const int* sid, int n, int il, T xi0, T xi1, T xi2,
+                                      T rca2, T rcr2, int cap, uint16_t* out, uint16_t* out2,
+                                      int32_t* __restrict__ flag) {
+    const int lane = lane_id();
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int cnt = 0, nang = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int k0 = 0; k0 < n; k0 += 64) {
+            const int k = k0 + lane;
+            bool hit = false;
+            int j = 0;
+            if (k < n) {
+                j = sid[k];
+                const T d0 = sx4[4 * k] - xi0, d1 = sx4[4 * k + 1] - xi1, d2 = sx4[4 * k + 2] - xi2;
+                const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                hit = j != il && (pass == 0 ? (r2 < rca2) : (r2 >= rca2 && r2 < rcr2));
+            }
+            const unsigned long long m = __ballot(hit);
+            const int pos = cnt + __popcll(m & lt);
+            if (hit && pos < cap) {
+                out[pos] = (uint16_t)j;
+                if (out2) out2[pos] = (uint16_t)j;
+            }
+            cnt += __popcll(m);
+        }
+        if (pass == 0) nang = cnt;
+    }
+    int nall = cnt;
+    if (nall > cap) {
+        if (lane == 0) atomicOr(flag, FLAG_CAPACITY);
+        nall = cap;
+        nang = nang > cap ? cap : nang;
+    }
+    return nang | (nall << 16);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_nbr_pairs(int A, int S, int max_apm, int cell_min, int chunk,
                                                    int cap, T rca2, T rcr2,
@@ -662,60 +727,16 @@ __global__ __launch_bounds__(256) void k_nbr_pairs(int A, int S, int max_apm, in
         tsp[j] = (s < 0 || s >= S) ? 0 : s;
     }
     __syncthreads();
-    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (wave == 0) {   // stable counting order by element
-        int base = 0;
-        for (int q = 0; q < S; ++q)
-            for (int j0 = 0; j0 < n; j0 += 64) {
-                const int j = j0 + lane;
-                const int s = j < n ? tsp[j] : -1;
-                const unsigned long long m = __ballot(s == q);
-                if (s == q) {
-                    const int pos = base + __popcll(m & lt);
-                    sid[pos] = j;
-                    sx[4 * pos + 0] = tx[3 * j + 0];
-                    sx[4 * pos + 1] = tx[3 * j + 1];
-                    sx[4 * pos + 2] = tx[3 * j + 2];
-                }
-                base += __popcll(m);
-            }
-    }
+    if (wave == 0) stage_element_order(tx, tsp, n, S, sx, sid);
     __syncthreads();
     const int nc = min(chunk, n - i0);
     for (int ic = wave; ic < nc; ic += nw) {
         const int il = i0 + ic;
-        const T xi0 = tx[3 * il], xi1 = tx[3 * il + 1], xi2 = tx[3 * il + 2];
         if (F && lane < 3) F[3 * ((size_t)a0 + il) + lane] = T(0);
         if (Fq && lane < 3) Fq[3 * ((size_t)a0 + il) + lane] = 0ull;
-        uint16_t* out = nbr + ((size_t)a0 + il) * cap;
-        int cnt = 0, nang = 0;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int k0 = 0; k0 < n; k0 += 64) {
-                const int k = k0 + lane;
-                bool hit = false;
-                int j = 0;
-                if (k < n) {
-                    j = sid[k];
-                    const T d0 = sx[4 * k] - xi0, d1 = sx[4 * k + 1] - xi1, d2 = sx[4 * k + 2] - xi2;
-                    const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                    hit = j != il && (pass == 0 ? (r2 < rca2) : (r2 >= rca2 && r2 < rcr2));
-                }
-                const unsigned long long m = __ballot(hit);
-                const int pos = cnt + __popcll(m & lt);
-                if (hit && pos < cap) out[pos] = (uint16_t)j;
-                cnt += __popcll(m);
-            }
-            if (pass == 0) nang = cnt;
-        }
-        if (lane == 0) {
-            int nall = cnt;
-            if (nall > cap) {
-                atomicOr(flag, FLAG_CAPACITY);
-                nall = cap;
-                nang = nang > cap ? cap : nang;
-            }
-            nbr_cnt[(size_t)a0 + il] = nang | (nall << 16);
-        }
+        const int cnt = atom_neighbours(sx, sid, n, il, tx[3 * il], tx[3 * il + 1], tx[3 * il + 2], rca2, rcr2,
+                                        cap, nbr + ((size_t)a0 + il) * cap, (uint16_t*)nullptr, flag);
+        if (lane == 0) nbr_cnt[(size_t)a0 + il] = cnt;
     }
 }
 
@@ -787,16 +808,18 @@ template <typename T> struct ChunkStage {
     int* ccnt;        // [kChunk]      packed neighbour counts
     int* crow;        // [kChunk]      bucket rows
     uint16_t* clst;   // [kChunk*cap]  neighbour lists
-    __device__ void take(LdsBump& lb, int max_apm, int cap) {
+    // lists = false: the workgroup finds its atoms' neighbours itself, so
+    // neither the lists nor their counts are staged
+    __device__ void take(LdsBump& lb, int max_apm, int cap, bool lists = true) {
         sx = lb.take<T>(3 * (size_t)max_apm);
         ssp = lb.take<int>(max_apm);
-        ccnt = lb.take<int>(kChunk);
+        ccnt = lists ? lb.take<int>(kChunk) : nullptr;
         crow = lb.take<int>(kChunk);
-        clst = lb.take<uint16_t>((size_t)kChunk * cap);
+        clst = lists ? lb.take<uint16_t>((size_t)kChunk * cap) : nullptr;
     }
-    static size_t bytes(int max_apm, int cap) {
+    static size_t bytes(int max_apm, int cap, bool lists = true) {
         return lds_bytes<T>(3 * (size_t)max_apm) + lds_bytes<int>(max_apm) +
-               2 * lds_bytes<int>(kChunk) + lds_bytes<uint16_t>((size_t)kChunk * cap);
+               (lists ? 2 : 1) * lds_bytes<int>(kChunk) + (lists ? lds_bytes<uint16_t>((size_t)kChunk * cap) : 0);
     }
     __device__ void load(const T* __restrict__ x, const int32_t* __restrict__ species, int S,
                          int a0, int n, int i0, int nc, int cap,
@@ -809,11 +832,13 @@ template <typename T> struct ChunkStage {
             ssp[t] = (s < 0 || s >= S) ? 0 : s;
         }
         for (int t = tid; t < nc; t += blockDim.x) {
-            ccnt[t] = nbr_cnt[(size_t)a0 + i0 + t];
+            if (ccnt) ccnt[t] = nbr_cnt[(size_t)a0 + i0 + t];
             crow[t] = row_of_atom[(size_t)a0 + i0 + t];
         }
-        const uint16_t* src = nbr + ((size_t)a0 + i0) * cap;
-        for (int e = tid; e < nc * cap; e += blockDim.x) clst[e] = src[e];
+        if (clst) {
+            const uint16_t* src = nbr + ((size_t)a0 + i0) * cap;
+            for (int e = tid; e < nc * cap; e += blockDim.x) clst[e] = src[e];
+        }
     }
 };
 
@@ -1021,7 +1046,8 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev
                                              const int32_t* __restrict__ nbr_cnt,
                                              const int32_t* __restrict__ row_of_atom,
                                              typename P::TS* __restrict__ G,
-                                             typename P::T* __restrict__ aev_out) {
+                                             typename P::T* __restrict__ aev_out,
+                                             NbrFuse<typename P::T> nf) {
     typedef typename P::T T;
     typedef typename P::TS TS;
     constexpr int NA = kNAZ / NZ;
@@ -1036,11 +1062,17 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
     const int S = c.S, RL = kNR * S, NB = S * (S + 1) / 2;
 
+    // fused: the workgroup finds its atoms' neighbour lists itself (and
+    // writes them out for the force kernel) instead of reading them
+    const bool fuse = nf.nbr != nullptr;
     LdsBump lb(smem);
     ChunkStage<T> cs;
-    cs.take(lb, max_apm, cap);
+    cs.take(lb, max_apm, cap, !fuse);
     T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
     T* pf = lb.take<T>((size_t)nw * 64 * PF) + (size_t)wave * 64 * PF;
+    T* sx4 = fuse ? lb.take<T>(4 * (size_t)max_apm) : nullptr;
+    int* sid = fuse ? lb.take<int>(max_apm) : nullptr;
+    uint16_t* wl = fuse ? lb.take<uint16_t>((size_t)nw * cap) + (size_t)wave * cap : nullptr;
     AtomLists<T> al;
     {
         LdsBump lw(lb.p + (size_t)wave * AtomLists<T>::bytes());
@@ -1048,13 +1080,32 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev
     }
     cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, row_of_atom);
     __syncthreads();
+    if (fuse) {
+        if (wave == 0) stage_element_order(cs.sx, cs.ssp, n, S, sx4, sid);
+        __syncthreads();
+    }
 
     const int h = lane >> 5, q = lane & 31, qa = q / NZ, qz = q % NZ;
     for (int ic = wave; ic < nc; ic += nw) {
         const int il = i0 + ic;
-        const int cnt = cs.ccnt[ic];
+        int cnt;
+        const uint16_t* lst;
+        if (fuse) {
+            // this evaluation's force accumulators, cleared as the neighbour
+            // kernel clears them
+            if (nf.F && lane < 3) nf.F[3 * ((size_t)a0 + il) + lane] = T(0);
+            if (nf.Fq && lane < 3) nf.Fq[3 * ((size_t)a0 + il) + lane] = 0ull;
+            cnt = atom_neighbours(sx4, sid, n, il, cs.sx[3 * il], cs.sx[3 * il + 1], cs.sx[3 * il + 2], nf.rca2,
+                                  nf.rcr2, cap, wl, nf.nbr + ((size_t)a0 + il) * cap, nf.flag);
+            if (lane == 0) nf.cnt[(size_t)a0 + il] = cnt;
+            wave_sync();
+            lst = wl;
+        } else {
+            cnt = cs.ccnt[ic];
+            lst = cs.clst + (size_t)ic * cap;
+        }
         const int nang = cnt & 0xffff, nall = cnt >> 16;
-        load_records(c, cs.sx, cs.ssp, cs.clst + (size_t)ic * cap, nang, nall, il, nb);
+        load_records(c, cs.sx, cs.ssp, lst, nang, nall, il, nb);
         wave_sync();
         const int npair = atom_lists(al, [&](int t) { return tag_of(nb + kNbStride * t) & 0xff; }, nang, nall, S);
         wave_sync();
@@ -1207,31 +1258,65 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev
 }
 
 template <typename T>
-static size_t aev_lds(int max_apm, int cap, int Dp, int NZ, int nw) {
+static size_t aev_lds(int max_apm, int cap, int Dp, int NZ, int nw, bool fuse = false) {
     const int PF = kNAZ / NZ + NZ;
     (void)Dp;
-    return ChunkStage<T>::bytes(max_apm, cap) + lds_bytes<T>((size_t)nw * cap * kNbStride) +
-           lds_bytes<T>((size_t)nw * 64 * PF) + (size_t)nw * AtomLists<T>::bytes();
+    return ChunkStage<T>::bytes(max_apm, cap, !fuse) + lds_bytes<T>((size_t)nw * cap * kNbStride) +
+           lds_bytes<T>((size_t)nw * 64 * PF) +
+           (fuse ? lds_bytes<T>(4 * (size_t)max_apm) + lds_bytes<int>(max_apm) +
+                       lds_bytes<uint16_t>((size_t)nw * cap)
+                 : 0) +
+           (size_t)nw * AtomLists<T>::bytes();
 }
 
 template <typename P>
 hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
                       const int32_t* species, const typename P::T* x, Work<P>& w,
-                      typename P::T* aev_out, hipStream_t st, const Timer& tm) {
+                      typename P::T* aev_out, hipStream_t st, const Timer& tm,
+                      const NbrFuse<typename P::T>& nf) {
     typedef typename P::T T;
     dim3 grid(sh.B, (sh.max_apm + sh.chunk - 1) / sh.chunk);
     int nw = kWaves;
-    size_t lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw);
-    while (lds > kMaxLds && nw > 1) lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw /= 2);
+    const bool fuse = nf.nbr != nullptr;
+    size_t lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw, fuse);
+    while (lds > kMaxLds && nw > 1) lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw /= 2, fuse);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = c.nZ == 4 ? k_aev<P, 4> : k_aev<P, 8>;
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("aev", st);
     hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, st, c, sh.A, sh.max_apm, sh.chunk, sh.cap_nbr,
-                       mol_off, species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.G, aev_out);
+                       mol_off, species, x, w.nbr, w.nbr_cnt, w.row_of_atom, w.G, aev_out, nf);
     tm.e("aev", st);
     return hipGetLastError();
+}
+
+// Neighbour lists and AEV rows.  Small batches (up to kFuseAtoms atoms, all
+// molecules within the all-pairs neighbour search) take one fused launch:
+// there the launch and the list round trip are a visible part of the
+// latency.  Large batches measured no faster fused (the search is the same
+// work inside the featuriser's waves), so they keep the neighbour kernels.
+// The force accumulators are cleared as launch_neighbours clears them.
+constexpr int kFuseAtoms = 4096;
+template <typename P>
+hipError_t launch_features(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
+                           const int32_t* species, const typename P::T* x, typename P::T* F,
+                           bool accumulate, Work<P>& w, typename P::T* aev_out, hipStream_t st,
+                           const Timer& tm) {
+    if (sh.max_apm > sh.cell_min || sh.A > kFuseAtoms) {
+        hipError_t e = launch_neighbours<P>(sh, c, mol_off, species, x, F, accumulate, w, st, tm);
+        if (e != hipSuccess) return e;
+        return launch_aev<P>(sh, c, mol_off, species, x, w, aev_out, st, tm, NbrFuse<typename P::T>());
+    }
+    NbrFuse<typename P::T> nf;
+    nf.rca2 = c.rca2;
+    nf.rcr2 = c.rcr2;
+    nf.F = (F && !sh.force_fixed && !accumulate) ? F : nullptr;
+    nf.Fq = (F && sh.force_fixed) ? w.Fq : nullptr;
+    nf.nbr = w.nbr;
+    nf.cnt = w.nbr_cnt;
+    nf.flag = w.flag;
+    return launch_aev<P>(sh, c, mol_off, species, x, w, aev_out, st, tm, nf);
 }
 
 // --------------------------------------------------------------------------
@@ -2154,7 +2239,10 @@ hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t
                                              P::T*, bool, Work<P>&, hipStream_t, const Timer&); \
     template hipError_t launch_aev<P>(const Shape&, const AevConst<P::T>&, const int32_t*,     \
                                       const int32_t*, const P::T*, Work<P>&, P::T*,            \
-                                      hipStream_t, const Timer&);                              \
+                                      hipStream_t, const Timer&, const NbrFuse<P::T>&);        \
+    template hipError_t launch_features<P>(const Shape&, const AevConst<P::T>&,                \
+                                           const int32_t*, const int32_t*, const P::T*, P::T*, \
+                                           bool, Work<P>&, P::T*, hipStream_t, const Timer&);  \
     template hipError_t launch_forces<P>(const Shape&, const AevConst<P::T>&, const int32_t*,  \
                                          const int32_t*, const P::T*, Work<P>&, P::T*,         \
                                          hipStream_t, const Timer&, const EnergyArgs<P>&);     \

@@ -282,10 +282,26 @@ hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
                              const int32_t* mol_off, const int32_t* species,
                              const typename P::T* x, typename P::T* F, bool accumulate, Work<P>& w,
                              hipStream_t st, const Timer& tm);
+// The featuriser finding its own neighbour lists (nbr null: it reads them):
+// cutoffs, the force accumulators it clears, and where the lists go
+template <typename T> struct NbrFuse {
+    T rca2 = 0, rcr2 = 0;
+    T* F = nullptr;
+    unsigned long long* Fq = nullptr;
+    uint16_t* nbr = nullptr;
+    int32_t* cnt = nullptr;
+    int32_t* flag = nullptr;
+};
 template <typename P>
 hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
                       const int32_t* species, const typename P::T* x, Work<P>& w,
-                      typename P::T* aev_out, hipStream_t st, const Timer& tm);
+                      typename P::T* aev_out, hipStream_t st, const Timer& tm,
+                      const NbrFuse<typename P::T>& nf = NbrFuse<typename P::T>());
+template <typename P>
+hipError_t launch_features(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
+                           const int32_t* species, const typename P::T* x, typename P::T* F,
+                           bool accumulate, Work<P>& w, typename P::T* aev_out, hipStream_t st,
+                           const Timer& tm);
 // hidden widths (padded) the fused layers 2-3 kernel is compiled for
 bool mlp_fused_supported(int H1, int H2, int H3);
 

@@ -523,10 +523,7 @@ nnp_status stage_features(nnp_handle* h, const Shape& sh, const int32_t* moff, c
     const AevConst<typename P::T>& c = const_of<typename P::T>(h);
     HIP_TRY(launch_prep<P>(sh, moff, species, w, st, tm));
     const int32_t* sp = w.zlut ? w.sp : species;
-    if (sh.A > 0) {
-        HIP_TRY(launch_neighbours<P>(sh, c, moff, sp, x, F, acc, w, st, tm));
-        HIP_TRY(launch_aev<P>(sh, c, moff, sp, x, w, nullptr, st, tm));
-    }
+    if (sh.A > 0) HIP_TRY(launch_features<P>(sh, c, moff, sp, x, F, acc, w, nullptr, st, tm));
     return NNP_OK;
 }
 template <typename P>
@@ -631,10 +628,7 @@ nnp_status run_forward(nnp_handle* h, const nnp_batch* b, const typename P::T* x
     }
     HIP_TRY(launch_prep<P>(sh, moff, b->species, w, st, tm));
     const int32_t* sp = elements_of(w, b);
-    if (sh.A > 0) {
-        HIP_TRY(launch_neighbours<P>(sh, c, moff, sp, x, F, acc, w, st, tm));
-        HIP_TRY(launch_aev<P>(sh, c, moff, sp, x, w, aev_out, st, tm));
-    }
+    if (sh.A > 0) HIP_TRY(launch_features<P>(sh, c, moff, sp, x, F, acc, w, aev_out, st, tm));
     if (aev_out) return NNP_OK;
     if (sh.A > 0) HIP_TRY(launch_mlp<P>(sh, weights_of<P>(h), w, st, tm));
     const bool fuse_e = F && sh.A > 0 && !sh.force_fixed;
