@@ -659,6 +659,17 @@ __global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
         }
     };
 
+    // CELU epilogue: the accumulators start at the bias of their columns,
+    // requested ahead of the first loads (the oldest loads in flight, so the
+    // fixed wait counts below cover them)
+    TA bb[FN][4];
+    if constexpr (EPI == EPI_CELU) {
+        const TA* bias = g.bias + (size_t)s * g.bias_s + tile_n * BN + wn * WTN + mf::col0(lane);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bb[j][r] = bias[j * 16 + r];
+    }
     const int nk = g.K / BK, last = 2 * nk - 1;
 #pragma unroll
     for (int p = 0; p < S - 1; ++p) issue_rows(min(p, nk - 1), p);
@@ -668,6 +679,14 @@ __global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
     issue_rows(min(S - 1, nk - 1), S - 1);
     __builtin_amdgcn_s_waitcnt(0xc07f);                  // lgkmcnt(0): kernel arguments
     read_rows(fa[0], stage(0), 0);
+    if constexpr (EPI == EPI_CELU) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[i][j][r] = bb[j][r];
+    }
     for (int kt = 0; kt < nk - 1; ++kt) {
         // k-step 2 kt
         load_frags(fb[1], 2 * kt + 1);
@@ -698,17 +717,10 @@ __global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
 
     // ---- epilogue: acc[i][j][r] of lane l is C[row i*16 + l%16][col j*16 + 4 (l/16) + r]
     const int row0 = tile_m * BM + (lane & 15);
-    const int col0 = tile_n * BN + wn * WTN + mf::col0(lane);
     if (EPI == EPI_CELU) {
         // lane q of a row holds 4-column pieces at 16 j + 4 q; st_strip_bf16
         // regroups them into 64-byte row segments
         TS* C = (TS*)g.C;
-        const TA* bias = g.bias + (size_t)s * g.bias_s;
-        TA bb[FN][4];
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) bb[j][r] = bias[col0 + j * 16 + r];
         TS* Cw = C + (size_t)row0 * g.ldc + tile_n * BN + wn * WTN + 8 * (lane >> 4);
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
@@ -717,7 +729,7 @@ __global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
             for (int j = 0; j < FN; ++j) {
                 TA v[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = celu(acc[i][j][r] + bb[j][r], g.alpha, g.inv_alpha);
+                for (int r = 0; r < 4; ++r) v[r] = celu(acc[i][j][r], g.alpha, g.inv_alpha);
                 pk[j][0] = pack_bf16x2(v[0], v[1]);
                 pk[j][1] = pack_bf16x2(v[2], v[3]);
             }
