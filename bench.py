@@ -528,6 +528,16 @@ def main():
             v["bound"] = max(("trans", fl["trans_s"]), ("valu", fl["valu_s"]), ("hbm", fl["hbm_s"]),
                              key=lambda t: t[1])[0]
             v["floor_us"] = fl["floor_s"] * 1e6
+        elif k == "neighbours":
+            # per atom: coordinates and element in (16 B), its list out (2 B per
+            # neighbour within Rcr) with its count (4 B), its force row cleared
+            # (12 B); the candidate tests (pairs of a molecule, ~8 FLOP each,
+            # both orders) are far below the VALU peak
+            nbytes = b5.n_atoms * (16 + 4 + 12) + 2 * 2 * pairs5
+            v["bound"], v["floor_us"] = "hbm", nbytes / HBM_BW * 1e6
+        elif k == "prep":
+            # per atom: element in, molecule, row and the row's atom out (16 B)
+            v["bound"], v["floor_us"] = "hbm", b5.n_atoms * 16 / HBM_BW * 1e6
         else:
             continue
         v["frac"] = v["floor_us"] / v["avg_us"]
