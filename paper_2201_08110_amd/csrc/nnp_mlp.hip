@@ -84,6 +84,26 @@ template <typename TS> struct Slice {
     __device__ static int at(int r, int k) { return r * BK + ((((k / VE) ^ r) & 7) * VE) + (k % VE); }
 };
 
+// Fragments of G consecutive k-steps read as one 16-byte vector per lane
+// (element j feeds step j): four FP32 or two FP64 k-steps; a BF16 fragment
+// already fills 16 bytes.
+template <typename TS> struct FragGroup {
+    static constexpr int G = 1;
+    typedef typename MF<TS>::Frag V;
+    __device__ static typename MF<TS>::Frag at(const V& v, int) { return v; }
+};
+template <> struct FragGroup<float> {
+    static constexpr int G = 4;
+    typedef f32x4 V;
+    __device__ static float at(const V& v, int j) { return v[j]; }
+};
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <> struct FragGroup<double> {
+    static constexpr int G = 2;
+    typedef f64x2 V;
+    __device__ static double at(const V& v, int j) { return v[j]; }
+};
+
 enum { EPI_CELU = 0, EPI_L3F = 1, EPI_DSIG = 2, EPI_ACC = 3, EPI_RAW = 4, EPI_REV = 5 };
 
 // CELU and its derivative, branch-free (the exponential is taken of min(z, 0)
@@ -325,24 +345,34 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs<P> g) {
     // and the loop body has no branches (a join would make the compiler wait
     // for every LDS read).  Scheduling barriers keep the compiler from
     // moving the MFMAs of a step above the reads issued for the next one.
-    typedef typename mf::Frag Frag;
-    constexpr int NSTEP = BK / mf::KM;
-    static_assert(NSTEP % 2 == 0, "k-steps per slice");
+    // FP32 / FP64 fragments hold one element per lane and k-step, so a
+    // plain read would fetch 4 or 8 bytes per lane.  Those are read FG
+    // k-steps at a time instead, one 16-byte chunk per lane: within a group,
+    // lane group g holds k = kk + g FG + j for step j, which still covers
+    // kk .. kk + 4 FG - 1 once each, identically for A and B (only the order
+    // of the K sum changes).
+    typedef typename FragGroup<TS>::V FragG;
+    constexpr int FG = FragGroup<TS>::G, KG = mf::KM * FG;   // k-steps, K per group
+    constexpr int NSTEP = BK / KG;
+    static_assert(NSTEP % 2 == 0, "k-step groups per slice");
     auto stage = [&](int kt) { return stage0 + (size_t)(kt % S) * (BM + BN) * BK; };
-    Frag af[2][FM], bq[2][FN];
-    auto read_frags = [&](Frag(&fa)[FM], Frag(&fb)[FN], const TS* As, int kk) {
+    FragG af[2][FM], bq[2][FN];
+    auto read_frags = [&](FragG(&fa)[FM], FragG(&fb)[FN], const TS* As, int kk) {
         const TS* Bs = As + BM * BK;
-        const int kf = kk + (lane >> 4) * mf::KL;
+        const int kf = kk + (lane >> 4) * mf::KL * FG;
 #pragma unroll
-        for (int i = 0; i < FM; ++i) fa[i] = *(const Frag*)(&As[L::at(wm * WTM + i * 16 + (lane & 15), kf)]);
+        for (int i = 0; i < FM; ++i) fa[i] = *(const FragG*)(&As[L::at(wm * WTM + i * 16 + (lane & 15), kf)]);
 #pragma unroll
-        for (int j = 0; j < FN; ++j) fb[j] = *(const Frag*)(&Bs[L::at(wn * WTN + j * 16 + (lane & 15), kf)]);
+        for (int j = 0; j < FN; ++j) fb[j] = *(const FragG*)(&Bs[L::at(wn * WTN + j * 16 + (lane & 15), kf)]);
     };
-    auto mma_step = [&](const Frag(&fa)[FM], const Frag(&fb)[FN]) {
+    auto mma_step = [&](const FragG(&fa)[FM], const FragG(&fb)[FN]) {
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+        for (int u = 0; u < FG; ++u)
 #pragma unroll
-            for (int i = 0; i < FM; ++i) acc[i][j] = mf::mma(fb[j], fa[i], acc[i][j]);
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    acc[i][j] = mf::mma(FragGroup<TS>::at(fb[j], u), FragGroup<TS>::at(fa[i], u), acc[i][j]);
     };
 
     const int nk = g.K / BK;
@@ -360,7 +390,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs<P> g) {
 #pragma unroll
         for (int t = 0; t < NSTEP; ++t) {
             if (t + 1 < NSTEP) {
-                read_frags(af[(t + 1) & 1], bq[(t + 1) & 1], As, (t + 1) * mf::KM);
+                read_frags(af[(t + 1) & 1], bq[(t + 1) & 1], As, (t + 1) * KG);
             } else {
                 vm_wait_barrier<QMIN * (S - 2)>();          // slice kt+1 landed
                 issue(min(kt + S, nk - 1), kt % S);          // stage of slice kt is free
@@ -375,7 +405,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs<P> g) {
         const TS* As = stage(nk - 1);
 #pragma unroll
         for (int t = 0; t < NSTEP; ++t) {
-            if (t + 1 < NSTEP) read_frags(af[(t + 1) & 1], bq[(t + 1) & 1], As, (t + 1) * mf::KM);
+            if (t + 1 < NSTEP) read_frags(af[(t + 1) & 1], bq[(t + 1) & 1], As, (t + 1) * KG);
             __builtin_amdgcn_sched_barrier(0);
             mma_step(af[t & 1], bq[t & 1]);
             __builtin_amdgcn_sched_barrier(0);
