@@ -156,10 +156,14 @@ struct NetLayout {
     long offW1, offb1, offW2, offb2, offW3, offb3, offw4, offb4, net;
 };
 
-// MFMA operand fragment of the network kernels: KM = K extent of one MFMA,
-// KL = consecutive K elements one lane holds (bf16 16x16x32: 32, 8; f32 and
-// f64 16x16x4: 4, 1).  Lane l holds row l % 16, K elements (l / 16) KL ...
-template <typename TS> struct FragK { static constexpr int KM = 4, KL = 1; };
+// Stored MFMA operand fragment of the network kernels: KM = K extent of one
+// fragment, KL = consecutive K elements one lane holds, 16 bytes in every
+// precision.  Lane l holds row l % 16, K elements (l / 16) KL ... + KL - 1.
+// A bf16 fragment (32, 8) feeds one 16x16x32 MFMA; an f32 (16, 4) or f64
+// (8, 2) fragment feeds four or two 16x16x4 MFMAs, step j taking element j
+// of every lane (so step j reduces over k = j, KL + j, 2 KL + j, 3 KL + j).
+template <typename TS> struct FragK { static constexpr int KM = 16, KL = 4; };
+template <> struct FragK<double> { static constexpr int KM = 8, KL = 2; };
 template <> struct FragK<bf16_t> { static constexpr int KM = 32, KL = 8; };
 
 // A [N][K] row-major matrix in fragment order: fragment (n-tile t, k-step q)

@@ -40,7 +40,7 @@ typedef short bf16x8 __attribute__((ext_vector_type(8)));
 
 template <typename TS> struct MF;
 template <> struct MF<float> {
-    static constexpr int KM = FragK<float>::KM, KL = FragK<float>::KL;
+    static constexpr int KM = 4, KL = 1;   // K of one MFMA, K elements per lane
     typedef float Frag;
     typedef f32x4 Acc;
     __device__ static Acc mma(Frag a, Frag b, Acc c) {
@@ -52,7 +52,7 @@ template <> struct MF<float> {
     __device__ static int col0(int l) { return 4 * (l >> 4); }
 };
 template <> struct MF<double> {
-    static constexpr int KM = FragK<double>::KM, KL = FragK<double>::KL;
+    static constexpr int KM = 4, KL = 1;
     typedef double Frag;
     typedef f64x4 Acc;
     __device__ static Acc mma(Frag a, Frag b, Acc c) {
@@ -64,7 +64,7 @@ template <> struct MF<double> {
     __device__ static int col0(int l) { return l >> 4; }
 };
 template <> struct MF<bf16_t> {
-    static constexpr int KM = FragK<bf16_t>::KM, KL = FragK<bf16_t>::KL;
+    static constexpr int KM = 32, KL = 8;
     typedef bf16x8 Frag;
     typedef f32x4 Acc;
     __device__ static Acc mma(Frag a, Frag b, Acc c) {
@@ -841,12 +841,14 @@ template <typename TS> using AccE = typename std::conditional<std::is_same<TS, d
 
 // acc = A rows m0 + [0, 16 FM) (LDS, sliced, BM rows, K columns) x B^T, B
 // n-tiles nt0 + [0, FN) of a matrix in fragment order (one contiguous 64-lane
-// load per fragment).  The B fragments of k-step t+PD are requested before the
-// MFMAs of step t; the empty asm with a memory clobber keeps the compiler from
-// sinking those loads next to their use, so PD k-steps of MFMAs (and the
-// other waves) cover the L2 latency.
+// load per fragment).  A stored fragment spans FragK<TS>::KM of K (one bf16
+// MFMA, four FP32 or two FP64 ones); the A operand is read from LDS in the
+// same grouping, one 16-byte vector per lane.  The B fragments of step t+PD
+// are requested before the MFMAs of step t; the empty asm with a memory
+// clobber keeps the compiler from sinking those loads next to their use, so
+// PD steps of MFMAs (and the other waves) cover the L2 latency.
 // K: the reduction length used; KS: the K the fragment-ordered matrix is
-// stored with (its k-steps per n-tile); bias, if given, points at the bias of
+// stored with (its steps per n-tile); bias, if given, points at the bias of
 // this lane's first column and starts the accumulators there.
 template <typename TS, int BM, int FM, int FN, int K, int KS = K>
 __device__ inline void tail_product(typename MF<TS>::Acc (&acc)[FM][FN], const TS* As, int m0,
@@ -854,11 +856,14 @@ __device__ inline void tail_product(typename MF<TS>::Acc (&acc)[FM][FN], const T
                                     const AccE<TS>* bias = nullptr) {
     typedef MF<TS> mf;
     typedef Sliced<TS> L;
-    typedef typename mf::Frag Frag;
-    // prefetch distance in k-steps: a bf16 fragment covers 32 of K, an
-    // FP32 / FP64 one only 4, so those look 8 steps ahead
-    constexpr int NS = K / mf::KM, NSS = KS / mf::KM, PD = mf::KM == 4 ? 8 : 2;
-    static_assert(K % mf::KM == 0 && K <= KS, "reduction length");
+    typedef FragGroup<TS> FGp;
+    typedef typename FGp::V FragG;
+    constexpr int G = FGp::G, KMS = FragK<TS>::KM, KLS = FragK<TS>::KL;
+    static_assert(KMS == mf::KM * G && KLS == mf::KL * G, "stored fragment = G MFMA steps");
+    // prefetch distance in stored fragments: 8 MFMA steps ahead for FP32
+    // (2 x 4) and FP64 (4 x 2), 2 for bf16
+    constexpr int NS = K / KMS, NSS = KS / KMS, PD = G == 2 ? 4 : 2;
+    static_assert(K % KMS == 0 && K <= KS, "reduction length");
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
@@ -867,28 +872,31 @@ __device__ inline void tail_product(typename MF<TS>::Acc (&acc)[FM][FN], const T
 #pragma unroll
             for (int i = 0; i < FM; ++i) acc[i][j][r] = b0;
         }
-    const TS* Bl = Bf + (size_t)nt0 * NSS * 64 * mf::KL + lane * mf::KL;
-    Frag bq[PD + 1][FN];
+    const TS* Bl = Bf + (size_t)nt0 * NSS * 64 * KLS + lane * KLS;
+    FragG bq[PD + 1][FN];
 #pragma unroll
     for (int t = 0; t < PD && t < NS; ++t)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) bq[t][j] = *(const Frag*)(Bl + ((size_t)j * NSS + t) * 64 * mf::KL);
+        for (int j = 0; j < FN; ++j) bq[t][j] = *(const FragG*)(Bl + ((size_t)j * NSS + t) * 64 * KLS);
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
         if (t + PD < NS) {
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-                bq[(t + PD) % (PD + 1)][j] = *(const Frag*)(Bl + ((size_t)j * NSS + t + PD) * 64 * mf::KL);
+                bq[(t + PD) % (PD + 1)][j] = *(const FragG*)(Bl + ((size_t)j * NSS + t + PD) * 64 * KLS);
         }
         asm volatile("" ::: "memory");
-        const int kf = t * mf::KM + (lane >> 4) * mf::KL;
-        Frag af[FM];
+        const int kf = t * KMS + (lane >> 4) * KLS;
+        FragG af[FM];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) af[i] = *(const Frag*)(&As[L::at(BM, m0 + i * 16 + (lane & 15), kf)]);
+        for (int i = 0; i < FM; ++i) af[i] = *(const FragG*)(&As[L::at(BM, m0 + i * 16 + (lane & 15), kf)]);
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+        for (int u = 0; u < G; ++u)
 #pragma unroll
-            for (int i = 0; i < FM; ++i) acc[i][j] = mf::mma(bq[t % (PD + 1)][j], af[i], acc[i][j]);
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    acc[i][j] = mf::mma(FGp::at(bq[t % (PD + 1)][j], u), FGp::at(af[i], u), acc[i][j]);
     }
 }
 
