@@ -286,6 +286,7 @@ __global__ __launch_bounds__(1024) void k_bucket_place(int A, int B, int S, int 
 
 // The three steps in one workgroup, for batches of at most kPrepBlock atoms
 // and molecules (one launch instead of three on small batches); same results.
+// The workgroup has one wave per 64 atoms (or molecules) of the bounds.
 __global__ __launch_bounds__(1024) void k_bucket_one(int A, int B, int S, int max_apm, int row_tile,
                                                      int Rcap, int sub, const int32_t* __restrict__ dA,
                                                      const int32_t* __restrict__ mol_off,
@@ -332,22 +333,36 @@ __global__ __launch_bounds__(1024) void k_bucket_one(int A, int B, int S, int ma
         if (s == q) mypre = __popcll(m & lt);
     }
     __syncthreads();
-    if (tid == 0) {
-        base[0] = 0;
-        for (int q = 0; q < S; ++q) {
-            int c = 0;
-            for (int w = 0; w < kPrepBlock / 64; ++w) c += wcnt[w][q];
-            tot[q] = c;
-            base[q + 1] = base[q] + ((c + row_tile - 1) / row_tile) * row_tile;
-            info->count[q] = c;
+    // per element (lane q of wave 0): the count over the block's waves, its
+    // rows padded to whole row tiles, and the offsets as a prefix scan over
+    // the lanes (lane S ends with the total)
+    if (wave == 0) {
+        const int nwv = blockDim.x >> 6;
+        int c = 0;
+        if (lane < S)
+            for (int w = 0; w < nwv; ++w) c += wcnt[w][lane];
+        const int pc = ((c + row_tile - 1) / row_tile) * row_tile;
+        int incl = pc;
+        for (int d = 1; d < 2 * kMaxSpecies; d <<= 1) {
+            const int v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
         }
-        for (int q = 0; q <= S; ++q) info->off[q] = base[q];
-        int rows = base[S];
-        if (rows > Rcap) {
-            atomicOr(flag, FLAG_CAPACITY);
-            rows = 0;
+        if (lane < S) {
+            tot[lane] = c;
+            info->count[lane] = c;
         }
-        info->rows = rows;
+        if (lane <= S) {
+            base[lane] = incl - pc;
+            info->off[lane] = incl - pc;
+        }
+        if (lane == S) {
+            int rows = incl;
+            if (rows > Rcap) {
+                atomicOr(flag, FLAG_CAPACITY);
+                rows = 0;
+            }
+            info->rows = rows;
+        }
     }
     __syncthreads();
     const int rows = base[S] <= Rcap ? base[S] : 0;
@@ -408,7 +423,9 @@ hipError_t launch_prep(const Shape& sh, const int32_t* mol_off, const int32_t* s
     const int32_t* dA = sh.dev_counts ? w.dcnt + 1 : nullptr;
     tm.b("prep", st);
     if (nblk <= 1) {
-        hipLaunchKernelGGL(k_bucket_one, dim3(1), dim3(kPrepBlock), 0, st, sh.A, sh.B, sh.S, sh.max_apm,
+        // one wave per 64 atoms (or molecules) of the bounds
+        const int nt = std::min(kPrepBlock, std::max(64, (std::max(sh.A, sh.B) + 63) / 64 * 64));
+        hipLaunchKernelGGL(k_bucket_one, dim3(1), dim3(nt), 0, st, sh.A, sh.B, sh.S, sh.max_apm,
                            sh.row_tile, sh.Rcap, sh.sub, dA, mol_off, species, w.zlut, w.sp, w.mol_of_atom,
                            w.row_of_atom, w.atom_of_row, w.tile_species, w.info, w.flag);
         tm.e("prep", st);
@@ -821,19 +838,21 @@ template <typename T> struct ChunkStage {
         return lds_bytes<T>(3 * (size_t)max_apm) + lds_bytes<int>(max_apm) +
                (lists ? 2 : 1) * lds_bytes<int>(kChunk) + (lists ? lds_bytes<uint16_t>((size_t)kChunk * cap) : 0);
     }
+    // (zlut: species are atomic numbers; row_of_atom null: crow already set)
     __device__ void load(const T* __restrict__ x, const int32_t* __restrict__ species, int S,
                          int a0, int n, int i0, int nc, int cap,
                          const uint16_t* __restrict__ nbr, const int32_t* __restrict__ nbr_cnt,
-                         const int32_t* __restrict__ row_of_atom) {
+                         const int32_t* __restrict__ row_of_atom, const int8_t* __restrict__ zlut = nullptr) {
         const int tid = threadIdx.x;
         for (int t = tid; t < 3 * n; t += blockDim.x) sx[t] = x[3 * (size_t)a0 + t];
         for (int t = tid; t < n; t += blockDim.x) {
             int s = species[a0 + t];
+            if (zlut) s = (s >= 0 && s < kZLut) ? (int)zlut[s] : -1;
             ssp[t] = (s < 0 || s >= S) ? 0 : s;
         }
         for (int t = tid; t < nc; t += blockDim.x) {
             if (ccnt) ccnt[t] = nbr_cnt[(size_t)a0 + i0 + t];
-            crow[t] = row_of_atom[(size_t)a0 + i0 + t];
+            if (row_of_atom) crow[t] = row_of_atom[(size_t)a0 + i0 + t];
         }
         if (clst) {
             const uint16_t* src = nbr + ((size_t)a0 + i0) * cap;
@@ -1037,7 +1056,118 @@ __device__ inline void pair_of(const AtomLists<T>& al, int NB, int S, int p, int
 // into LDS.  Each slot is stored to the output row by its owner lane as soon
 // as it is complete: no row is assembled in LDS, which keeps the workgroup's
 // LDS small enough for more waves per CU.
-template <typename P, int NZ>
+// Bucketing inside the featuriser, for batches of at most kPrepBlock atoms and
+// molecules: the steps and results of k_bucket_one without its launch.  Every
+// workgroup counts the elements of the batch's atoms per 64-atom segment
+// (ballots) and forms the padded bucket offsets (prefix over the lanes of
+// wave 0); it then places its own central atoms [c0, c0 + nc) (row = bucket
+// start + atoms of the element in earlier segments + rank in its segment),
+// keeps their rows in crow and writes their per-atom outputs.  The lead
+// workgroup also writes the bucket table, the row tiles' elements, the
+// padding rows and the capacity flags.  Returns false when the rows exceed
+// the capacity (the rows are then not written, as the kernel leaves them).
+constexpr int kBucketScratch = (kPrepBlock / 64) * kMaxSpecies + 2 * kMaxSpecies + 1 + 2 * kChunk;
+__device__ inline bool bucket_in_features(const BucketFuse& bk, int S, int A, int max_apm,
+                                          const int32_t* __restrict__ mol_off,
+                                          const int32_t* __restrict__ species, int b, int c0, int nc,
+                                          bool mine, bool lead, int* scr, int* crow,
+                                          int32_t* __restrict__ flag) {
+    int* segcnt = scr;                                   // [segment][element]
+    int* base = segcnt + (kPrepBlock / 64) * kMaxSpecies;   // [S + 1] padded starts
+    int* tot = base + kMaxSpecies + 1;                   // [S] atoms per element
+    int* crank = tot + kMaxSpecies;                      // [nc] rank in its segment
+    int* csp = crank + kChunk;                           // [nc] element (| 0x100: invalid)
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
+    int A0, A1;
+    const bool rng = atom_range(A, bk.B, bk.dA, mol_off, bk.sub, A0, A1);
+    if (lead) {
+        if (!rng && tid == 0) atomicOr(flag, FLAG_CAPACITY);
+        for (int m = tid; m < bk.B; m += blockDim.x) {
+            const int m0 = mol_off[m], m1 = mol_off[m + 1];
+            if (m0 < A0 || m1 < m0 || m1 > A1 || m1 - m0 > max_apm) atomicOr(flag, FLAG_CAPACITY);
+        }
+    }
+    // central atoms outside the call's range have no row (the lead has flagged them)
+    mine = mine && c0 >= A0 && c0 + nc <= A1;
+    const int nseg = (A1 - A0 + 63) >> 6;
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int g = wave; g < nseg; g += nw) {
+        const int a = A0 + 64 * g + lane;
+        int sv = -1;
+        if (a < A1) {
+            sv = species[a];
+            if (bk.zlut) sv = (sv >= 0 && sv < kZLut) ? (int)bk.zlut[sv] : -1;
+            if (sv >= S) sv = -1;
+        }
+        const int s = sv < 0 ? 0 : sv;   // as the bucketing kernel counts them
+        for (int q = 0; q < S; ++q) {
+            const unsigned long long m = __ballot(a < A1 && s == q);
+            if (lane == 0) segcnt[g * kMaxSpecies + q] = __popcll(m);
+            if (a < A1 && s == q && a >= c0 && a < c0 + nc) {
+                crank[a - c0] = __popcll(m & lt);
+                csp[a - c0] = q | (sv < 0 ? 0x100 : 0);
+            }
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        int c = 0;
+        if (lane < S)
+            for (int g = 0; g < nseg; ++g) c += segcnt[g * kMaxSpecies + lane];
+        const int pc = ((c + bk.row_tile - 1) / bk.row_tile) * bk.row_tile;
+        int incl = pc;
+        for (int d = 1; d < 2 * kMaxSpecies; d <<= 1) {
+            const int v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        if (lane < S) tot[lane] = c;
+        if (lane <= S) base[lane] = incl - pc;
+        if (lead) {
+            if (lane < S) bk.info->count[lane] = c;
+            if (lane <= S) bk.info->off[lane] = incl - pc;
+            if (lane == S) {
+                int rows = incl;
+                if (rows > bk.Rcap) {
+                    atomicOr(flag, FLAG_CAPACITY);
+                    rows = 0;
+                }
+                bk.info->rows = rows;
+            }
+        }
+    }
+    __syncthreads();
+    const bool fits = base[S] <= bk.Rcap;
+    const int rows = fits ? base[S] : 0;
+    if (lead) {
+        for (int t = tid; t < bk.Rcap / bk.row_tile; t += blockDim.x) {
+            const int r = t * bk.row_tile;
+            int sp = -1;
+            if (r < rows)
+                for (int q = 0; q < S; ++q)
+                    if (base[q] <= r && r < base[q + 1]) sp = q;
+            bk.tile_species[t] = sp;
+        }
+        for (int q = 0; q < S; ++q)
+            for (int r = base[q] + tot[q] + tid; r < base[q + 1] && r < rows; r += blockDim.x)
+                bk.atom_of_row[r] = -1;
+    }
+    if (!fits || !mine) return false;
+    for (int ic = tid; ic < nc; ic += blockDim.x) {
+        const int a = c0 + ic, s = csp[ic] & 0xff, g = (a - A0) >> 6;
+        int row = base[s] + crank[ic];
+        for (int g2 = 0; g2 < g; ++g2) row += segcnt[g2 * kMaxSpecies + s];
+        crow[ic] = row;
+        bk.row_of_atom[a] = row;
+        bk.atom_of_row[row] = a;
+        bk.mol_of_atom[a] = b;
+        if (bk.zlut) bk.sp_out[a] = s;
+        if (csp[ic] & 0x100) atomicOr(flag, FLAG_SPECIES);
+    }
+    __syncthreads();
+    return true;
+}
+
+template <typename P, int NZ, bool BUCKET = false>
 __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
                                              int chunk, int cap, const int32_t* __restrict__ mol_off,
                                              const int32_t* __restrict__ species,
@@ -1055,10 +1185,20 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x;
     const int a0 = mol_off[b], n = mol_off[b + 1] - a0;
-    if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
     const int i0 = blockIdx.y * chunk;
-    if (i0 >= n) return;
-    const int nc = min(chunk, n - i0);
+    // with the bucketing fused in, workgroup (0, 0) also writes the batch's
+    // bucket table, whether or not it has central atoms
+    constexpr bool bucket = BUCKET;
+    bool mine = true, lead = false;
+    if constexpr (bucket) {
+        mine = !(n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) && i0 < n;
+        lead = b == 0 && blockIdx.y == 0;
+        if (!mine && !lead) return;
+    } else {
+        if (n <= 0 || n > max_apm || a0 < 0 || a0 + n > A) return;
+        if (i0 >= n) return;
+    }
+    const int nc = mine ? min(chunk, n - i0) : 0;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
     const int S = c.S, RL = kNR * S, NB = S * (S + 1) / 2;
 
@@ -1068,6 +1208,12 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev
     LdsBump lb(smem);
     ChunkStage<T> cs;
     cs.take(lb, max_apm, cap, !fuse);
+    if constexpr (bucket) {
+        int* scr = lb.take<int>(kBucketScratch);
+        if (!bucket_in_features(nf.bk, S, A, max_apm, mol_off, species, b, a0 + i0, nc, mine, lead, scr,
+                                cs.crow, nf.flag))
+            return;
+    }
     T* nb = lb.take<T>((size_t)nw * cap * kNbStride) + (size_t)wave * cap * kNbStride;
     T* pf = lb.take<T>((size_t)nw * 64 * PF) + (size_t)wave * 64 * PF;
     T* sx4 = fuse ? lb.take<T>(4 * (size_t)max_apm) : nullptr;
@@ -1078,7 +1224,8 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev
         LdsBump lw(lb.p + (size_t)wave * AtomLists<T>::bytes());
         al.take(lw);
     }
-    cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, row_of_atom);
+    if constexpr (bucket) cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, nullptr, nf.bk.zlut);
+    else cs.load(x, species, S, a0, n, i0, nc, cap, nbr, nbr_cnt, row_of_atom);
     __syncthreads();
     if (fuse) {
         if (wave == 0) stage_element_order(cs.sx, cs.ssp, n, S, sx4, sid);
@@ -1258,10 +1405,11 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev
 }
 
 template <typename T>
-static size_t aev_lds(int max_apm, int cap, int Dp, int NZ, int nw, bool fuse = false) {
+static size_t aev_lds(int max_apm, int cap, int Dp, int NZ, int nw, bool fuse = false, bool bucket = false) {
     const int PF = kNAZ / NZ + NZ;
     (void)Dp;
-    return ChunkStage<T>::bytes(max_apm, cap, !fuse) + lds_bytes<T>((size_t)nw * cap * kNbStride) +
+    return ChunkStage<T>::bytes(max_apm, cap, !fuse) + (bucket ? lds_bytes<int>(kBucketScratch) : 0) +
+           lds_bytes<T>((size_t)nw * cap * kNbStride) +
            lds_bytes<T>((size_t)nw * 64 * PF) +
            (fuse ? lds_bytes<T>(4 * (size_t)max_apm) + lds_bytes<int>(max_apm) +
                        lds_bytes<uint16_t>((size_t)nw * cap)
@@ -1277,11 +1425,12 @@ hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const i
     typedef typename P::T T;
     dim3 grid(sh.B, (sh.max_apm + sh.chunk - 1) / sh.chunk);
     int nw = kWaves;
-    const bool fuse = nf.nbr != nullptr;
-    size_t lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw, fuse);
-    while (lds > kMaxLds && nw > 1) lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw /= 2, fuse);
+    const bool fuse = nf.nbr != nullptr, bucket = nf.bk.info != nullptr;
+    size_t lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw, fuse, bucket);
+    while (lds > kMaxLds && nw > 1) lds = aev_lds<T>(sh.max_apm, sh.cap_nbr, c.Dp, c.nZ, nw /= 2, fuse, bucket);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    auto kern = c.nZ == 4 ? k_aev<P, 4> : k_aev<P, 8>;
+    auto kern = bucket ? (c.nZ == 4 ? k_aev<P, 4, true> : k_aev<P, 8, true>)
+                       : (c.nZ == 4 ? k_aev<P, 4> : k_aev<P, 8>);
     hipError_t e = ensure_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     tm.b("aev", st);
@@ -1316,6 +1465,48 @@ hipError_t launch_features(const Shape& sh, const AevConst<typename P::T>& c, co
     nf.nbr = w.nbr;
     nf.cnt = w.nbr_cnt;
     nf.flag = w.flag;
+    return launch_aev<P>(sh, c, mol_off, species, x, w, aev_out, st, tm, nf);
+}
+
+// Bucketing and featurisation.  A batch that fits one bucketing workgroup and
+// takes the fused neighbour search is bucketed inside the featuriser (one
+// launch for all three steps: on a single small molecule each dependent
+// launch is a visible part of the latency); otherwise the bucketing kernels
+// run first.
+template <typename P>
+hipError_t launch_prep_features(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
+                                const int32_t* species, const typename P::T* x, typename P::T* F,
+                                bool accumulate, Work<P>& w, typename P::T* aev_out, hipStream_t st,
+                                const Timer& tm) {
+    const bool small = sh.A > 0 && std::max(sh.A, sh.B) <= kPrepBlock && sh.max_apm <= sh.cell_min &&
+                       sh.A <= kFuseAtoms;
+    if (!small) {
+        hipError_t e = launch_prep<P>(sh, mol_off, species, w, st, tm);
+        if (e != hipSuccess) return e;
+        if (sh.A == 0) return hipSuccess;
+        return launch_features<P>(sh, c, mol_off, w.zlut ? w.sp : species, x, F, accumulate, w, aev_out, st, tm);
+    }
+    NbrFuse<typename P::T> nf;
+    nf.rca2 = c.rca2;
+    nf.rcr2 = c.rcr2;
+    nf.F = (F && !sh.force_fixed && !accumulate) ? F : nullptr;
+    nf.Fq = (F && sh.force_fixed) ? w.Fq : nullptr;
+    nf.nbr = w.nbr;
+    nf.cnt = w.nbr_cnt;
+    nf.flag = w.flag;
+    BucketFuse& bk = nf.bk;
+    bk.zlut = w.zlut;
+    bk.sp_out = w.sp;
+    bk.mol_of_atom = w.mol_of_atom;
+    bk.row_of_atom = w.row_of_atom;
+    bk.atom_of_row = w.atom_of_row;
+    bk.tile_species = w.tile_species;
+    bk.info = w.info;
+    bk.dA = sh.dev_counts ? w.dcnt + 1 : nullptr;
+    bk.B = sh.B;
+    bk.row_tile = sh.row_tile;
+    bk.Rcap = sh.Rcap;
+    bk.sub = sh.sub;
     return launch_aev<P>(sh, c, mol_off, species, x, w, aev_out, st, tm, nf);
 }
 
@@ -2240,6 +2431,10 @@ hipError_t launch_energy(const Shape& sh, const DevWeights<P>& wt, const int32_t
     template hipError_t launch_aev<P>(const Shape&, const AevConst<P::T>&, const int32_t*,     \
                                       const int32_t*, const P::T*, Work<P>&, P::T*,            \
                                       hipStream_t, const Timer&, const NbrFuse<P::T>&);        \
+    template hipError_t launch_prep_features<P>(const Shape&, const AevConst<P::T>&,           \
+                                                const int32_t*, const int32_t*, const P::T*,     \
+                                                P::T*, bool, Work<P>&, P::T*, hipStream_t,       \
+                                                const Timer&);                                   \
     template hipError_t launch_features<P>(const Shape&, const AevConst<P::T>&,                \
                                            const int32_t*, const int32_t*, const P::T*, P::T*, \
                                            bool, Work<P>&, P::T*, hipStream_t, const Timer&);  \

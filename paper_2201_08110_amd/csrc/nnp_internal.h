@@ -288,6 +288,20 @@ hipError_t launch_neighbours(const Shape& sh, const AevConst<typename P::T>& c,
                              hipStream_t st, const Timer& tm);
 // The featuriser finding its own neighbour lists (nbr null: it reads them):
 // cutoffs, the force accumulators it clears, and where the lists go
+// (bucketing, for batches of at most kPrepBlock atoms and molecules: the
+// bucketing kernel's outputs, written by the featuriser instead; info null:
+// the bucketing kernel has run)
+struct BucketFuse {
+    const int8_t* zlut = nullptr;      // atomic number -> element, or null
+    int32_t* sp_out = nullptr;         // element indices (zlut != null)
+    int32_t* mol_of_atom = nullptr;
+    int32_t* row_of_atom = nullptr;
+    int32_t* atom_of_row = nullptr;
+    int32_t* tile_species = nullptr;
+    BucketInfo* info = nullptr;
+    const int32_t* dA = nullptr;       // device atom count, or null
+    int B = 0, row_tile = 16, Rcap = 0, sub = 0;
+};
 template <typename T> struct NbrFuse {
     T rca2 = 0, rcr2 = 0;
     T* F = nullptr;
@@ -295,12 +309,20 @@ template <typename T> struct NbrFuse {
     uint16_t* nbr = nullptr;
     int32_t* cnt = nullptr;
     int32_t* flag = nullptr;
+    BucketFuse bk;
 };
 template <typename P>
 hipError_t launch_aev(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
                       const int32_t* species, const typename P::T* x, Work<P>& w,
                       typename P::T* aev_out, hipStream_t st, const Timer& tm,
                       const NbrFuse<typename P::T>& nf = NbrFuse<typename P::T>());
+// bucketing, neighbour lists and AEV rows of an evaluation (species as the
+// batch gives them: atomic numbers on handles with an element table)
+template <typename P>
+hipError_t launch_prep_features(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
+                                const int32_t* species, const typename P::T* x, typename P::T* F,
+                                bool accumulate, Work<P>& w, typename P::T* aev_out, hipStream_t st,
+                                const Timer& tm);
 template <typename P>
 hipError_t launch_features(const Shape& sh, const AevConst<typename P::T>& c, const int32_t* mol_off,
                            const int32_t* species, const typename P::T* x, typename P::T* F,

@@ -521,9 +521,7 @@ nnp_status stage_features(nnp_handle* h, const Shape& sh, const int32_t* moff, c
                           const typename P::T* x, typename P::T* F, bool acc, Work<P>& w, hipStream_t st,
                           const Timer& tm) {
     const AevConst<typename P::T>& c = const_of<typename P::T>(h);
-    HIP_TRY(launch_prep<P>(sh, moff, species, w, st, tm));
-    const int32_t* sp = w.zlut ? w.sp : species;
-    if (sh.A > 0) HIP_TRY(launch_features<P>(sh, c, moff, sp, x, F, acc, w, nullptr, st, tm));
+    HIP_TRY(launch_prep_features<P>(sh, c, moff, species, x, F, acc, w, nullptr, st, tm));
     return NNP_OK;
 }
 template <typename P>
@@ -626,9 +624,8 @@ nnp_status run_forward(nnp_handle* h, const nnp_batch* b, const typename P::T* x
         tm.e("prep", st);
         moff = w.moff;
     }
-    HIP_TRY(launch_prep<P>(sh, moff, b->species, w, st, tm));
+    HIP_TRY(launch_prep_features<P>(sh, c, moff, b->species, x, F, acc, w, aev_out, st, tm));
     const int32_t* sp = elements_of(w, b);
-    if (sh.A > 0) HIP_TRY(launch_features<P>(sh, c, moff, sp, x, F, acc, w, aev_out, st, tm));
     if (aev_out) return NNP_OK;
     if (sh.A > 0) HIP_TRY(launch_mlp<P>(sh, weights_of<P>(h), w, st, tm));
     const bool fuse_e = F && sh.A > 0 && !sh.force_fixed;
