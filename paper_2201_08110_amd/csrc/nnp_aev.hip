@@ -1168,7 +1168,7 @@ __device__ inline bool bucket_in_features(const BucketFuse& bk, int S, int A, in
 }
 
 template <typename P, int NZ, bool BUCKET = false>
-__global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 7) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
+__global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
                                              int chunk, int cap, const int32_t* __restrict__ mol_off,
                                              const int32_t* __restrict__ species,
                                              const typename P::T* __restrict__ x,

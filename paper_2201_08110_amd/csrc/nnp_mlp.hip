@@ -1206,8 +1206,12 @@ static hipError_t run_l1(GemmArgs<P> a, const Shape& sh, int N, hipStream_t st, 
                                        : run_gemm<P, BM, C::BNW, 2, 4, 3, EPI>(a, R, N, 1, st, tm, name);
     }
     // 16-row tiles (small batches) stream the weights through a deeper pipeline:
-    // few workgroups, so each keeps more loads in flight
-    if constexpr (BM == 16) return run_gemm<P, BM, C::BNW, C::WM, C::WN, 6, EPI>(a, R, N, 1, st, tm, name);
+    // few workgroups, so each keeps more loads in flight (BF16 6 stages; FP32
+    // and FP64, whose slices hold half or a quarter of the K, measured best at 4)
+    if constexpr (BM == 16) {
+        constexpr int S16 = sizeof(typename P::TS) == 2 ? 6 : 4;
+        return run_gemm<P, BM, C::BNW, C::WM, C::WN, S16, EPI>(a, R, N, 1, st, tm, name);
+    }
     return sh.gemm_stages == 2 ? run_gemm<P, BM, C::BNW, C::WM, C::WN, 2, EPI>(a, R, N, 1, st, tm, name)
                                : run_gemm<P, BM, C::BNW, C::WM, C::WN, 3, EPI>(a, R, N, 1, st, tm, name);
 }
