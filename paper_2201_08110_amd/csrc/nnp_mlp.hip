@@ -648,7 +648,11 @@ __global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
     // the loop and waits for every load in flight before the first k-step of
     // each slice.  Each use below is preceded by an explicit vm_wait that
     // leaves exactly the loads issued after it in flight, and a scheduling
-    // barrier keeps the MFMAs behind that wait.
+    // barrier keeps the MFMAs behind that wait.  The compiler takes an inline
+    // load's registers as written at issue, so nothing may read or reuse them
+    // before that wait: the compiled kernels are checked for this.  (Plain
+    // loads measured no faster, and the compiler then reorders them against
+    // the direct row loads, which breaks the fixed wait counts.)
     Frag fb[2][FN];
     auto load_frags = [&](Frag(&b)[FN], int step) {
 #pragma unroll
