@@ -941,13 +941,21 @@ template <typename P> struct TailArgs {
     int nm;                                   // row tiles
 };
 
+// LDS of the fused tail: H2 / DZ2 [BM][H2] at 0, DZ3 [BM][H3] after it, then
+// the energy partials and the layer parameters.  The H1 tile of the first
+// product spans the first two regions (it is dead once that product is
+// done); for the last epilogue the H1 column quarters of waves 0-2 go to the
+// DZ3 region and the fourth to the start of the DZ2 region once every wave
+// is past the last product.  So the tile never needs a region of its own
+// (ANI-2x widths, BF16: 51 KB, three workgroups per CU).
 template <typename P, int BM, int H1, int H2, int H3>
 struct TailShape {
     typedef typename P::TS TS;
     static constexpr size_t hs = (size_t)BM * H2 * sizeof(TS);
     static constexpr size_t u1 = (size_t)BM * H1 * sizeof(TS), u2 = (size_t)BM * H3 * sizeof(TS);
+    static_assert(u1 <= hs + u2 && 3 * (u1 / 4) <= u2 && u1 / 4 <= hs, "H1 tile placement");
     static constexpr size_t par = sizeof(typename P::TA) * (H2 + 2 * H3);   // b2, b3, w4
-    static constexpr size_t lds_bytes() { return hs + (u1 > u2 ? u1 : u2) + sizeof(typename P::TA) * BM * 4 + par; }
+    static constexpr size_t lds_bytes() { return hs + u2 + sizeof(typename P::TA) * BM * 4 + par; }
 };
 
 // H3 is the stored (padded) width of layer 3, H3L <= H3 the width the
@@ -964,9 +972,10 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
     static_assert(H1 % 64 == 0 && H2 % 64 == 0 && H3 % 64 == 0 && BM % 16 == 0, "widths");
     typedef TailShape<P, BM, H1, H2, H3> Sh;
     extern __shared__ __align__(16) char smem_raw[];
+    TS* H1t = (TS*)smem_raw;                             // H1 tile (first product only)
     TS* Hs = (TS*)smem_raw;                              // H2, later DZ2   [BM][H2]
-    TS* Us = (TS*)(smem_raw + Sh::hs);                   // H1 tile, later DZ3
-    TA* red = (TA*)(smem_raw + Sh::hs + (Sh::u1 > Sh::u2 ? Sh::u1 : Sh::u2));   // [BM][4]
+    TS* Us = (TS*)(smem_raw + Sh::hs);                   // DZ3, later H1 quarters 0-2
+    TA* red = (TA*)(smem_raw + Sh::hs + Sh::u2);         // [BM][4]
     TA* sb2 = red + BM * 4;            // b2 [H2], b3 [H3], w4 [H3] of this element and model
     TA* sb3 = sb2 + H2;
     TA* sw4 = sb3 + H3;
@@ -987,25 +996,24 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
     const int wn = wave & 3, m0 = (wave >> 2) * (BM / TW);   // column quarter, first row
     const size_t sz = (size_t)s * g.M + z;
 
-    // H1 tile -> LDS (sliced), direct loads: per K slice BM/8 loads of 8 rows.
-    // Loaded again into the same region for the last phase's CELU'(H1).
-    auto load_h1_tile = [&]() {
-        const TS* src0 = g.H1 + (size_t)row0 * g.ldh + (size_t)z * H1;
+    // H1 columns [c0, c0 + NC) (whole K slices) of rows [r0, r0 + NR) -> a
+    // sliced LDS tile of BM rows at dst (its slice 0 = column c0), by direct
+    // loads of 8 rows x one slice, dealt to waves w, w + nw, ...
+    auto load_h1 = [&](TS* dst, int c0, auto nc_c, int r0, auto nr_c, int w, int nw) {
+        constexpr int NC = decltype(nc_c)::value, NR = decltype(nr_c)::value;
+        constexpr int NG = NR / 8, NQ = (NC / L::BK) * NG;
+        static_assert(NC % L::BK == 0 && NR % 8 == 0, "whole slices and row groups");
+        const TS* src0 = g.H1 + (size_t)row0 * g.ldh + (size_t)z * H1 + c0;
         const int lr = lane >> 3, lc = (lane & 7) ^ (lane >> 3);
-        constexpr int NQ = (H1 / L::BK) * (BM / 8);
-        constexpr int NW = 4 * TW;
-#pragma unroll
-        for (int u = 0; u < (NQ + NW - 1) / NW; ++u) {
-            const int q = wave + NW * u;
-            if (NQ % NW == 0 || q < NQ) {
-                const int t = q / (BM / 8), rq = q % (BM / 8);
-                const TS* src = src0 + (size_t)(rq * 8 + lr) * g.ldh + t * L::BK + lc * L::VE;
-                __builtin_amdgcn_global_load_lds(NNP_GPTR(src), NNP_LPTR(Us + (t * BM + rq * 8) * L::BK), 16, 0, 0);
-            }
+        for (int q = w; q < NQ; q += nw) {
+            const int t = q / NG, rq = r0 / 8 + q % NG;
+            const TS* src = src0 + (size_t)(rq * 8 + lr) * g.ldh + t * L::BK + lc * L::VE;
+            __builtin_amdgcn_global_load_lds(NNP_GPTR(src), NNP_LPTR(dst + (t * BM + rq * 8) * L::BK), 16, 0, 0);
         }
     };
+    constexpr int NWV = 4 * TW, HQ = H1 / 4;   // waves; H1 columns per column quarter
     {
-        load_h1_tile();
+        load_h1(H1t, 0, std::integral_constant<int, H1>{}, 0, std::integral_constant<int, BM>{}, wave, NWV);
         // the layer parameters the epilogues read, staged beside the tile
         for (int t = tid; t < H2 + 2 * H3; t += NT) {
             const TA v = t < H2 ? g.b2[sz * H2 + t]
@@ -1022,7 +1030,8 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
         constexpr int FN = H2 / 64;
         Acc acc[FM][FN];
         const int n0 = wn * (H2 / 4);
-        tail_product<TS, BM, FM, FN, H1>(acc, Us, m0, g.W2f + sz * H2 * H1, n0 / 16, lane, sb2 + n0 + cl);
+        tail_product<TS, BM, FM, FN, H1>(acc, H1t, m0, g.W2f + sz * H2 * H1, n0 / 16, lane, sb2 + n0 + cl);
+        __syncthreads();   // every wave is done with the H1 tile, which H2 overwrites
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int c = n0 + j * 16 + cl;
@@ -1035,7 +1044,7 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
             }
         }
     }
-    __syncthreads();   // H2 complete; the H1 tile is dead from here on
+    __syncthreads();   // H2 complete
     // ---- layer 3 forward, output layer, dE/dz3: the H3L / 16 column tiles
     // dealt to the four waves as evenly as they go (160: 2, 3, 2, 3), each
     // wave running a product with its own static tile count
@@ -1116,17 +1125,24 @@ __global__ __launch_bounds__(256 * TW, 2 * TW) void k_tail(TailArgs<P> g) {
         Acc acc[FM][FN];
         const int n0 = wn * (H1 / 4);
         TS* Out = g.DZ1 + (size_t)row0 * g.ldh + (size_t)z * H1;
-        // CELU'(H1) operands of the epilogue: the H1 tile again, into the
-        // region DZ3 held (every wave is past its last read of DZ3), in
-        // flight during the product; whole 128-byte rows per load
-        load_h1_tile();
+        // CELU'(H1) operands of the epilogue: the H1 column quarters of waves
+        // 0-2 into the region DZ3 held (every wave is past its last read of
+        // DZ3), in flight during the product; whole 128-byte rows per load
+        load_h1(Us, 0, std::integral_constant<int, 3 * HQ>{}, 0, std::integral_constant<int, BM>{}, wave, NWV);
         tail_product<TS, BM, FM, FN, H2>(acc, Hs, m0, g.W2Tf + sz * H1 * H2, n0 / 16, lane);
-        vm_wait_barrier<0>();   // H1 tile landed (all waves' parts)
+        vm_wait_barrier<0>();   // quarters 0-2 landed; every wave is done reading DZ2
+        // the fourth quarter over the start of DZ2, loaded by the waves that
+        // read it (each its own rows)
+        if (wn == 3) {
+            load_h1(Hs, 3 * HQ, std::integral_constant<int, HQ>{}, m0, std::integral_constant<int, BM / TW>{}, 0, 1);
+            vm_wait<0>();
+        }
+        const TS* Hq = wn < 3 ? Us + (size_t)wn * BM * HQ : Hs;   // this wave's quarter (sliced, BM rows)
         TA hh[FM][FN][4];
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int i = 0; i < FM; ++i) LdsQuad<TS, ST>::ld(Us, BM, m0 + i * 16 + rl, n0 + j * 16 + cl, hh[i][j]);
+            for (int i = 0; i < FM; ++i) LdsQuad<TS, ST>::ld(Hq, BM, m0 + i * 16 + rl, j * 16 + cl, hh[i][j]);
         if constexpr (std::is_same<TS, bf16_t>::value && FN == 4) {
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
