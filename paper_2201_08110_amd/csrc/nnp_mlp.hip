@@ -594,6 +594,7 @@ static hipError_t run_gemm(GemmArgs<P> a, int Rcap, int N, int nz, hipStream_t s
 // The LDS fragment reads of the next k-step are interleaved with the MFMAs
 // of the current one.
 constexpr int kRbBM = 128, kRbBN = 256, kRbWN = 4;
+constexpr int kRbRows = 128;   // bucket row tile the register-weight path runs on
 
 template <int S, int EPI>
 __global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
@@ -606,7 +607,7 @@ __global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
     constexpr int BM = kRbBM, BN = kRbBN, BK = L::BK;   // BK = 64 (two 32-deep k-steps)
     constexpr int WTN = BN / kRbWN, FM = BM / 16, FN = WTN / 16;
     constexpr int NQ = BM / 8 / kRbWN;                   // direct row loads per wave per slice
-    static_assert(BK == 2 * mf::KM && NQ == 4 && FN == 4, "tile");
+    static_assert(BK == 2 * mf::KM && NQ >= 1 && FN == 4, "tile");
     static_assert(S == 2 || S == 3, "stages");
     extern __shared__ __align__(16) char smem_raw[];
     TS* const stage0 = (TS*)smem_raw;                    // S stages of BM rows
@@ -709,7 +710,7 @@ __global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
     for (int p = 0; p < S - 1; ++p) issue_rows(min(p, nk - 1), p);
     load_frags(fb[0], 0);
     if (S == 3) issue_rows(min(1, nk - 1), 1);          // count padding (same rows again)
-    vm_wait_barrier<S == 2 ? 4 : 12>();                  // rows of slice 0 landed
+    vm_wait_barrier<S == 2 ? FN : 2 * NQ + FN>();        // rows of slice 0 landed
     issue_rows(min(S - 1, nk - 1), S - 1);
     __builtin_amdgcn_s_waitcnt(0xc07f);                  // lgkmcnt(0): kernel arguments
     read_rows(fa[0], stage(0), 0);
@@ -724,22 +725,22 @@ __global__ __launch_bounds__(256, 2) void k_l1rb(GemmArgs<PrecBF16> g) {
     for (int kt = 0; kt < nk - 1; ++kt) {
         // k-step 2 kt
         load_frags(fb[1], 2 * kt + 1);
-        vm_wait<8>();                                    // fragments of this step
+        vm_wait<NQ + FN>();                              // fragments of this step
         __builtin_amdgcn_sched_barrier(0);
         mma_reads(fa[0], fb[0], fa[1], stage(kt), mf::KM);
         __builtin_amdgcn_sched_barrier(0);
         // k-step 2 kt + 1
         load_frags(fb[0], min(2 * kt + 2, last));
-        vm_wait_barrier<12 * (S - 2) + 8>();             // rows of slice kt+1 landed, stage of kt free
+        vm_wait_barrier<(NQ + 2 * FN) * (S - 2) + 2 * FN>();   // rows of slice kt+1 landed, stage of kt free
         issue_rows(min(kt + S, nk - 1), S == 2 ? kt & 1 : kt % S);
-        vm_wait<8>();
+        vm_wait<NQ + FN>();
         __builtin_amdgcn_sched_barrier(0);
         mma_reads(fa[1], fb[1], fa[0], stage(kt + 1), 0);
         __builtin_amdgcn_sched_barrier(0);
     }
     {
         load_frags(fb[1], last);
-        vm_wait<8>();
+        vm_wait<NQ + FN>();
         __builtin_amdgcn_sched_barrier(0);
         mma_reads(fa[0], fb[0], fa[1], stage(nk - 1), mf::KM);
         __builtin_amdgcn_sched_barrier(0);
@@ -1247,7 +1248,7 @@ static hipError_t mlp_l1_bwd(const Shape& sh, const DevWeights<P>& wt, Work<P>& 
     a.B = wt.W1T; a.ldb = M * H1; a.b_s = (long)Dp * M * H1; a.b_z = 0;
     a.C = w.dG; a.ldc = Dp; a.c_z = 0;
     a.K = M * H1;
-    if constexpr (std::is_same<P, PrecBF16>::value && BM == kRbBM) {
+    if constexpr (std::is_same<P, PrecBF16>::value && BM == kRbRows) {
         if (sh.l1_path == 2) {
             a.B = wt.W1Tf;
             return run_l1rb<EPI_ACC>(a, R, Dp, sh.gemm_stages, st, tm, "mlp_l1_bwd");
@@ -1283,7 +1284,7 @@ static hipError_t mlp_all(const Shape& sh, const DevWeights<P>& wt, Work<P>& w, 
     a.C = w.H1; a.ldc = M * H1; a.c_z = 0;
     a.K = Dp;
     bool l1_done = false;
-    if constexpr (std::is_same<P, PrecBF16>::value && BM == kRbBM) {
+    if constexpr (std::is_same<P, PrecBF16>::value && BM == kRbRows) {
         if (sh.l1_path == 2) {
             a.B = wt.W1f;
             e = run_l1rb<EPI_CELU>(a, R, M * H1, sh.gemm_stages, st, tm, "mlp_l1_fwd");
