@@ -1044,18 +1044,6 @@ __device__ inline void pair_of(const AtomLists<T>& al, int NB, int S, int p, int
     }
 }
 
-// --------------------------------------------------------------------------
-// AEV forward.  One wave per central atom; the output row of atom a goes to
-// G[row_of_atom[a]] in the GEMM operand type, optionally also to aev_out[a]
-// (atom order, unpadded).  Every AEV slot is owned by one lane: radial slot
-// (s, k) by lane (group s % 4, shift k) summing over the neighbours of
-// element s; angular slot q of a block by lane q of one half-wave (the
-// blocks meeting a 64-pair batch are dealt to the two halves in turn, and a
-// block's pairs are contiguous).  Pair factors (NA distance
-// terms, NZ angle terms) are computed once per pair, 64 pairs at a time,
-// into LDS.  Each slot is stored to the output row by its owner lane as soon
-// as it is complete: no row is assembled in LDS, which keeps the workgroup's
-// LDS small enough for more waves per CU.
 // Bucketing inside the featuriser, for batches of at most kPrepBlock atoms and
 // molecules: the steps and results of k_bucket_one without its launch.  Every
 // workgroup counts the elements of the batch's atoms per 64-atom segment
@@ -1167,6 +1155,18 @@ __device__ inline bool bucket_in_features(const BucketFuse& bk, int S, int A, in
     return true;
 }
 
+// --------------------------------------------------------------------------
+// AEV forward.  One wave per central atom; the output row of atom a goes to
+// G[row_of_atom[a]] in the GEMM operand type, optionally also to aev_out[a]
+// (atom order, unpadded).  Every AEV slot is owned by one lane: radial slot
+// (s, k) by lane (group s % 4, shift k) summing over the neighbours of
+// element s; angular slot q of a block by lane q of one half-wave (the
+// blocks meeting a 64-pair batch are dealt to the two halves in turn, and a
+// block's pairs are contiguous).  Pair factors (NA distance
+// terms, NZ angle terms) are computed once per pair, 64 pairs at a time,
+// into LDS.  Each slot is stored to the output row by its owner lane as soon
+// as it is complete: no row is assembled in LDS, which keeps the workgroup's
+// LDS small enough for more waves per CU.
 template <typename P, int NZ, bool BUCKET = false>
 __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_aev(AevConst<typename P::T> c, int A, int max_apm,
                                              int chunk, int cap, const int32_t* __restrict__ mol_off,
