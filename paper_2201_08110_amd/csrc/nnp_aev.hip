@@ -1232,7 +1232,10 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_aev
         __syncthreads();
     }
 
-    const int h = lane >> 5, q = lane & 31, qa = q / NZ, qz = q % NZ;
+    // angular block sums by quarter-waves: lane (r = lane / 16, l = lane % 16)
+    // owns slots l and l + 16 of the block dealt to quarter r
+    const int qr = lane >> 4, ql = lane & 15;
+    const int qa1 = ql / NZ, qa2 = (ql + 16) / NZ, qzl = ql % NZ;
     for (int ic = wave; ic < nc; ic += nw) {
         const int il = i0 + ic;
         int cnt;
@@ -1300,11 +1303,11 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_aev
 
         // ---- angular, 64 pairs at a time.  A block's sum is stored when its
         // last pair is in; a block that runs on into the next batch leaves its
-        // partial sum in the lanes of half 0 (carry), which take that block
+        // partial sums in the lanes of quarter 0 (carry), which take that block
         // first in the next batch.  Blocks without pairs are stored as zeros.
         const int blo = lane < NB ? al.bst[lane] : 0, bhi = lane < NB ? al.bst[lane + 1] : 0;
         const unsigned long long filled = __ballot(lane < NB && blo < bhi);
-        T carry = T(0);
+        T carry1 = T(0), carry2 = T(0);
         int carry_blk = -1;
         for (int p0 = 0; p0 < npair; p0 += 64) {
             const int nbat = min(64, npair - p0);
@@ -1333,55 +1336,67 @@ __global__ __launch_bounds__(256, sizeof(typename P::T) == 8 ? 1 : 6) void k_aev
                 }
             }
             wave_sync();
-            // blocks meeting this batch, taken two at a time: the first by
-            // lanes 0..31, the second by lanes 32..63, each half summing its
-            // block's pairs in order (four pairs' factors in flight)
+            // blocks meeting this batch, taken four at a time, one per
+            // quarter-wave, each quarter summing its block's pairs in order
+            // (two pairs' factors in flight)
             const int pe_ = p0 + nbat;
             const unsigned long long live = __ballot(lane < NB && blo < bhi && blo < pe_ && bhi > p0);
             const unsigned long long goes_on = __ballot(lane < NB && blo < bhi && blo < pe_ && bhi > pe_);
-            T next_carry = T(0);
+            T nc1 = T(0), nc2 = T(0);
             for (unsigned long long mset = live; mset;) {
-                const int bA = __builtin_ctzll(mset);
-                mset &= mset - 1;
-                const int bB = mset ? __builtin_ctzll(mset) : bA;
-                const bool two = mset != 0;
-                mset &= mset - 1;
-                const int bl = h ? bB : bA;
-                const int lo = h ? __builtin_amdgcn_readlane(blo, bB) : __builtin_amdgcn_readlane(blo, bA);
-                const int hi = h ? __builtin_amdgcn_readlane(bhi, bB) : __builtin_amdgcn_readlane(bhi, bA);
-                const int s0 = max(lo, p0) - p0;
-                const int e0 = (h && !two) ? s0 : min(hi, pe_) - p0;
-                T acc = T(0), acc1 = T(0);
-                int p = s0;
-                for (; p + 4 <= e0; p += 4) {
-                    T fa[4], fz[4];
+                int bq[4], lq[4], hq[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const T* f = pf + PF * (p + u);
-                        fa[u] = f[qa];
-                        fz[u] = f[NA + qz];
-                    }
-                    acc += fa[0] * fz[0] + fa[2] * fz[2];
-                    acc1 += fa[1] * fz[1] + fa[3] * fz[3];
+                for (int r = 0; r < 4; ++r) {
+                    bq[r] = mset ? __builtin_ctzll(mset) : -1;
+                    lq[r] = bq[r] >= 0 ? __builtin_amdgcn_readlane(blo, bq[r]) : 0;
+                    hq[r] = bq[r] >= 0 ? __builtin_amdgcn_readlane(bhi, bq[r]) : 0;
+                    mset &= mset - 1;
                 }
-                for (; p < e0; ++p) {
-                    const T* f = pf + PF * p;
-                    acc += f[qa] * f[NA + qz];
+                const int bl = qr == 0 ? bq[0] : (qr == 1 ? bq[1] : (qr == 2 ? bq[2] : bq[3]));
+                const int lo = qr == 0 ? lq[0] : (qr == 1 ? lq[1] : (qr == 2 ? lq[2] : lq[3]));
+                const int hi = qr == 0 ? hq[0] : (qr == 1 ? hq[1] : (qr == 2 ? hq[2] : hq[3]));
+                const int s0 = bl < 0 ? 0 : max(lo, p0) - p0;
+                const int e0 = bl < 0 ? 0 : min(hi, pe_) - p0;
+                T a1 = T(0), a2 = T(0), b1 = T(0), b2 = T(0);
+                int p = s0;
+                for (; p + 2 <= e0; p += 2) {
+                    const T* f0 = pf + PF * p;
+                    const T* f1 = f0 + PF;
+                    const T z0 = f0[NA + qzl], z1 = f1[NA + qzl];
+                    const T x1 = f0[qa1], x2 = f0[qa2], y1 = f1[qa1], y2 = f1[qa2];
+                    a1 += x1 * z0;
+                    a2 += x2 * z0;
+                    b1 += y1 * z1;
+                    b2 += y2 * z1;
                 }
-                T v = acc + acc1;
-                if (bl == carry_blk) v += carry;
+                if (p < e0) {
+                    const T* f0 = pf + PF * p;
+                    const T z0 = f0[NA + qzl];
+                    a1 += f0[qa1] * z0;
+                    a2 += f0[qa2] * z0;
+                }
+                T v1 = a1 + b1, v2 = a2 + b2;
+                if (bl == carry_blk) {
+                    v1 += carry1;
+                    v2 += carry2;
+                }
                 if (s0 < e0) {
-                    if (hi > pe_) next_carry = v;
-                    else put(RL + kNAZ * bl + q, v);
+                    if (hi > pe_) {
+                        nc1 = v1;
+                        nc2 = v2;
+                    } else {
+                        put(RL + kNAZ * bl + ql, v1);
+                        put(RL + kNAZ * bl + ql + 16, v2);
+                    }
                 }
             }
             if (goes_on) {
-                // the continuing block is the batch's last; its half is the
-                // parity of its rank among the batch's blocks
+                // the continuing block is the batch's last; its quarter is its
+                // rank among the batch's blocks, mod 4
                 const int cb = __builtin_ctzll(goes_on);
-                const int half = __popcll(live & ((1ull << cb) - 1)) & 1;
-                const T other = __shfl_xor(next_carry, 32);
-                carry = half ? other : next_carry;
+                const int qc = __popcll(live & ((1ull << cb) - 1)) & 3;
+                carry1 = __shfl(nc1, ql + 16 * qc);
+                carry2 = __shfl(nc2, ql + 16 * qc);
                 carry_blk = cb;
             } else {
                 carry_blk = -1;
