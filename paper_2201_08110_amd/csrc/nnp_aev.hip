@@ -1160,9 +1160,9 @@ __device__ inline bool bucket_in_features(const BucketFuse& bk, int S, int A, in
 // G[row_of_atom[a]] in the GEMM operand type, optionally also to aev_out[a]
 // (atom order, unpadded).  Every AEV slot is owned by one lane: radial slot
 // (s, k) by lane (group s % 4, shift k) summing over the neighbours of
-// element s; angular slot q of a block by lane q of one half-wave (the
-// blocks meeting a 64-pair batch are dealt to the two halves in turn, and a
-// block's pairs are contiguous).  Pair factors (NA distance
+// element s; angular slots l and l + 16 of a block by lane l of one
+// quarter-wave (the blocks meeting a 64-pair batch are dealt to the four
+// quarters in turn, and a block's pairs are contiguous).  Pair factors (NA distance
 // terms, NZ angle terms) are computed once per pair, 64 pairs at a time,
 // into LDS.  Each slot is stored to the output row by its owner lane as soon
 // as it is complete: no row is assembled in LDS, which keeps the workgroup's
