@@ -447,8 +447,8 @@ def main():
                          "reference dispatch for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(molecules shard across GPUs with no exchange; see the design notes)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(molecules shard across GPUs with no exchange between them)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -51,7 +51,7 @@ typedef int32_t nnp_status;
 #define NNP_E_CAPACITY      3   /* batch exceeds the capacity given at creation               */
 #define NNP_E_NOMEM         4   /* device allocation failed                                   */
 #define NNP_E_DEVICE        5   /* a HIP runtime call failed                                  */
-#define NNP_E_UNSUPPORTED   6   /* valid request this build does not implement                */
+#define NNP_E_UNSUPPORTED   6   /* valid request the library does not implement               */
 
 /* Arithmetic of the path. */
 #define NNP_PREC_FP64       0   /* everything in FP64 (checking mode)                         */

@@ -969,7 +969,7 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
     if (!p->shf_r || !p->shf_a || !p->shf_z || !p->weights || (!p->widths && !p->species_widths))
         return fail(NNP_E_INVALID, "null shift, width or weight array");
     if (p->n_shf_r != kNR || p->n_shf_a * p->n_shf_z != kNAZ || (p->n_shf_z != 4 && p->n_shf_z != 8))
-        return fail(NNP_E_UNSUPPORTED, "this build supports 16 radial shifts and 8x4 or 4x8 angular shifts");
+        return fail(NNP_E_UNSUPPORTED, "the library supports 16 radial shifts and 8x4 or 4x8 angular shifts");
     if (!(p->rcr > 0) || !(p->rca > 0) || p->rca > p->rcr)
         return fail(NNP_E_INVALID, "cutoffs must satisfy 0 < rca <= rcr");
     if (!(p->angle_scale > 0 && p->angle_scale < 1))
@@ -978,7 +978,7 @@ nnp_status nnp_create(const nnp_model_params* p, nnp_handle** out) {
         return fail(NNP_E_INVALID, "need zeta >= 1, eta_r >= 0, eta_a >= 0");
     if (!(p->celu_alpha > 0)) return fail(NNP_E_INVALID, "celu_alpha must be > 0");
     if (p->n_models < 1 || p->n_models > 64) return fail(NNP_E_INVALID, "n_models must be in 1..64");
-    if (p->n_layers != 4) return fail(NNP_E_UNSUPPORTED, "this build supports 4 affine layers");
+    if (p->n_layers != 4) return fail(NNP_E_UNSUPPORTED, "the library supports 4 affine layers");
     const int S = p->n_species;
     const int D = S * p->n_shf_r + (S * (S + 1) / 2) * p->n_shf_a * p->n_shf_z;
     // element network widths sw[s][l]; the uniform layout wi[l] every element

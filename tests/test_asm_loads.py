@@ -3,7 +3,7 @@ assembly, each followed later by an explicit wait, so that its LDS pipeline's
 fixed wait counts stay exact.  The compiler treats an inline load's
 destination registers as written as soon as the instruction issues, so two
 properties of the compiled device code have to hold, and are checked here on
-the assembly of this build:
+the compiled assembly:
 
   (a) no instruction reads or overwrites a fragment load's destination
       registers before the MFMA that consumes it (a copy would read the
